@@ -1,0 +1,208 @@
+/* pksell.h -- PackSELL sparse matrix-vector products on AMD MI355X (gfx950).
+ *
+ * PackSELL (Suzuki & Iwashita, "PackSELL: A Sparse Matrix Format for
+ * Precision-Agnostic High-Performance SpMV") is sliced ELLPACK in which every
+ * stored element is one 32-bit word holding a column delta and a quantised
+ * value.  Word layout (sec. 4.2.1, W = V + D + 1 = 32): bit 0 is a flag;
+ * flag = 1 puts the value in the upper V bits and a delta < 2^D in bits
+ * 1..D; flag = 0 puts a delta up to 2^31 - 1 in bits 1..31 and no value (a
+ * "dummy", inserted before an element whose delta does not fit, sec. 4.3).
+ * The all-zero word is padding.  Column indices are rebuilt as running sums
+ * of deltas from a left offset that is uniform within each sigma-block of
+ * rows (eq. 4).  Rows are grouped in slices of C rows stored column-major,
+ * after a descending sort by stored-word count inside windows of sigma rows
+ * (SELL-C-sigma, sec. 3).
+ *
+ * Conventions for every call:
+ *  - Pointers named in a call are DEVICE pointers unless said otherwise; the
+ *    caller allocates and owns all of them.  The library allocates no device
+ *    memory; scratch space is passed in as a workspace (``ws``).
+ *  - ``stream`` is a hipStream_t (NULL = the default stream).  All device
+ *    work is enqueued on it asynchronously unless a call says it
+ *    synchronises.
+ *  - Every call returns a status code (PKSELL_OK = 0, negative on error);
+ *    pksell_status_string() names it, and pksell_last_error() gives detail
+ *    for the calling thread.  Inputs are never modified.
+ *  - Sizes: n, m < 2^30 (so byte offsets into x fit 32 bits), columns < m.
+ */
+#ifndef PKSELL_H
+#define PKSELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PKSELL_OK 0
+#define PKSELL_EINVAL (-1)      /* bad argument, shape or CSR structure */
+#define PKSELL_ERANGE (-2)      /* a size exceeds what the format or kernels address */
+#define PKSELL_EWORKSPACE (-3)  /* workspace missing or too small */
+#define PKSELL_EHIP (-4)        /* a HIP runtime call failed */
+#define PKSELL_ENOTCONV (-5)    /* solver hit its iteration limit */
+#define PKSELL_EBREAKDOWN (-6)  /* solver breakdown (p^T A p <= 0 or NaN) */
+
+/* ---- value formats (sec. 4.2.2) ---------------------------------------- */
+#define PKSELL_FP16 0 /* IEEE binary16 in the upper 16 bits; D must be 15 */
+#define PKSELL_E8MY 1 /* FP32-compatible float, Y = 22 - D mantissa bits; 1 <= D <= 22 */
+#define PKSELL_FIX 2  /* (31-D)-bit two's-complement integer times a per-row
+                         power of two; 1 <= D <= 29 */
+
+/* ---- row permutation modes (sec. 3) ------------------------------------ */
+#define PKSELL_EXPLICIT 0 /* results are produced in stored (sorted) row order */
+#define PKSELL_IMPLICIT 1 /* results are produced in the original row order via perm */
+
+/* ---- value input types ------------------------------------------------- */
+#define PKSELL_F32 4
+#define PKSELL_F64 8
+
+/* A PackSELL matrix.  pksell_encode_query() fills the shape and parameter
+ * fields; the analyse phase of pksell_encode() fills n_words, n_dummies and
+ * k_left; the caller allocates the device arrays.
+ *
+ *   pack     uint32[n_words]     slice k occupies [offset[k], offset[k+1]),
+ *                                word j of lane l at offset[k] + j*C + l
+ *   offset   int64[n_slices + 1] slice starts in words (sec. 3)
+ *   perm     uint8 (sigma <= 256) or uint16 [n]  original row minus its
+ *                                window start, per stored row (implicit mode
+ *                                only; may be NULL in explicit mode)
+ *   row_exp  int16[n]            FIX only: row scale exponent e, stored order
+ *                                (decoded value = q * 2^e)
+ */
+typedef struct pksell_matrix {
+  int64_t n, m, nnz;
+  int32_t C, sigma, D, fmt, perm_mode, perm_bytes;
+  int64_t n_slices;
+  int64_t n_words, n_dummies, k_left;
+  uint32_t *pack;
+  int64_t *offset;
+  void *perm;
+  int16_t *row_exp;
+} pksell_matrix;
+
+/* Plain SELL-C-sigma (sec. 3) with float32 or float64 values and int32
+ * columns -- the same-GPU comparator and the float64 operator of the outer
+ * solver.  Padding slots hold value 0 and the row's last column.
+ *   val  float or double [n_slots], col int32[n_slots], offset int64[n_slices+1]
+ */
+typedef struct pksell_sell {
+  int64_t n, m, nnz;
+  int32_t C, sigma, perm_mode, perm_bytes, dtype; /* dtype PKSELL_F32/PKSELL_F64 */
+  int32_t reserved;
+  int64_t n_slices, n_slots;
+  int64_t *offset;
+  void *perm;
+  int32_t *col;
+  void *val;
+} pksell_sell;
+
+/* Result of pksell_pcg (host struct). */
+typedef struct pksell_pcg_info {
+  int32_t outer_iterations; /* outer (FCG) iterations, or CG iterations */
+  int32_t inner_iterations; /* total inner iterations */
+  double rel_residual;      /* final true ||b - A x||_2 / ||b||_2 */
+  double seconds;           /* wall time of the solve on the host clock */
+} pksell_pcg_info;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int pksell_version(void);
+
+/* Static name of a status code. */
+const char *pksell_status_string(int status);
+
+/* Detail of the last failing call on the calling host thread (static buffer). */
+const char *pksell_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Encoding CSR -> PackSELL (sec. 4.1 delta encoding with eq. 4 left offsets,
+ * sec. 4.2 packing, sec. 4.3 dummies, padding and the sigma-window sort).
+ * ---------------------------------------------------------------------- */
+
+/* Validates (n, m, nnz, C, sigma, D, fmt, perm_mode), fills A's shape and
+ * parameter fields (n_slices = ceil(n/C), perm_bytes), sets its array
+ * pointers to NULL, and writes the workspace size pksell_encode needs to
+ * *ws_bytes (host pointers).  C is a power of two in [1, 64]; sigma in
+ * [1, 65536].  Returns PKSELL_EINVAL on bad parameters, PKSELL_ERANGE when n
+ * or m reaches 2^30.  No device work. */
+int pksell_encode_query(int64_t n, int64_t m, int64_t nnz, int32_t C,
+                        int32_t sigma, int32_t D, int32_t fmt,
+                        int32_t perm_mode, pksell_matrix *A, size_t *ws_bytes);
+
+/* Encodes a device CSR matrix (rowptr int64[n+1], col int32[nnz] strictly
+ * increasing within each row, val float32 or float64 [nnz] per val_dtype;
+ * float64 values are rounded to float32 first, as sec. 4.2.2 converts from
+ * float).  Two phases, chosen by A->pack:
+ *
+ *  - A->pack == NULL (analyse): needs A->offset (and A->perm in implicit
+ *    mode).  Validates the CSR on the device, computes the lower bandwidth
+ *    k_left, the per-row word counts (nonzeros + dummies), the sigma-window
+ *    sort and the slice offsets; then SYNCHRONISES the stream and fills
+ *    A->n_words, A->n_dummies, A->k_left.  The caller then allocates
+ *    A->pack (n_words) and, for FIX, A->row_exp (n).
+ *  - A->pack != NULL (fill): writes every word of A->pack (padding included)
+ *    and A->row_exp; asynchronous.  ``ws`` must still hold what the analyse
+ *    phase left in it.
+ *
+ * Errors: PKSELL_EINVAL for a malformed CSR (unsorted or duplicate columns,
+ * column >= m, bad rowptr) or non-finite values in FIX; PKSELL_EWORKSPACE
+ * when ws_bytes is below pksell_encode_query's size. */
+int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val,
+                  int32_t val_dtype, pksell_matrix *A, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Products (sec. 4.4 PackSELL SpMV).  k right-hand sides are row-major
+ * blocks: x is m x k, y is n x k (element (r, c) at r*k + c).
+ * ---------------------------------------------------------------------- */
+
+/* y = A_q x with float32 accumulation; y is overwritten (no beta term).  In
+ * implicit mode y is in the original row order, in explicit mode in stored
+ * order.  1 <= k <= 64. */
+int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k,
+                void *stream);
+
+/* y = A_q^T g (the adjoint: grad_x of <g, A x>).  g is n x k in the row
+ * order pksell_spmv produces; y (m x k) is zeroed on the stream and then
+ * accumulated with float32 atomics, so the summation order is not fixed. */
+int pksell_spmv_t(const pksell_matrix *A, const float *g, float *y,
+                  int64_t k, void *stream);
+
+/* grad[e] = g_i * x_j for every stored nonzero e = (i, j) of the CSR matrix
+ * the words were encoded from, in that CSR's order (rowptr int64[n+1] of the
+ * ORIGINAL matrix).  g (n) in pksell_spmv's row order, x (m).  k = 1. */
+int pksell_grad_values(const pksell_matrix *A, const int64_t *rowptr,
+                       const float *g, const float *x, float *grad,
+                       void *stream);
+
+/* Decodes every word position: cols[p] = column reconstructed at word p
+ * (running sum of deltas from the left offset), vals[p] = decoded value
+ * (0 for flag-0 words; FIX: q * 2^e).  Positions of phantom rows past n are
+ * left untouched.  For checking encoders against a reference. */
+int pksell_decode(const pksell_matrix *A, int32_t *cols, float *vals,
+                  void *stream);
+
+/* ------------------------------------------------------------------------
+ * Plain SELL-C-sigma (sec. 3), the comparator and the float64 operator.
+ * ---------------------------------------------------------------------- */
+
+/* As pksell_encode_query for SELL; dtype is PKSELL_F32 or PKSELL_F64. */
+int pksell_sell_query(int64_t n, int64_t m, int64_t nnz, int32_t C,
+                      int32_t sigma, int32_t dtype, int32_t perm_mode,
+                      pksell_sell *S, size_t *ws_bytes);
+
+/* As pksell_encode: analyse when S->val == NULL (needs S->offset, S->perm;
+ * synchronises; fills S->n_slots), fill otherwise (needs S->col, S->val). */
+int pksell_sell_encode(const int64_t *rowptr, const int32_t *col,
+                       const void *val, int32_t val_dtype, pksell_sell *S,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* y = S x in S->dtype (x: m, y: n, of S->dtype), accumulated in S->dtype. */
+int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y,
+                     void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PKSELL_H */

@@ -1,0 +1,342 @@
+"""Thin Python binding of ``libpksell.so`` (the C ABI in include/pksell.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the computation runs in the library's
+kernels.  There is no fallback: if the library is missing, loading it
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpksell.so")
+
+OK, EINVAL, ERANGE, EWORKSPACE, EHIP, ENOTCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
+FP16, E8MY, FIX = 0, 1, 2
+EXPLICIT, IMPLICIT = 0, 1
+F32, F64 = 4, 8
+FMT_BY_NAME = {"fp16": FP16, "e8my": E8MY, "fix": FIX}
+
+i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+
+
+class PackSELLError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"pksell error {status}: {detail}")
+        self.status = status
+
+
+class CMatrix(ctypes.Structure):
+    _fields_ = [("n", i64), ("m", i64), ("nnz", i64),
+                ("C", i32), ("sigma", i32), ("D", i32), ("fmt", i32),
+                ("perm_mode", i32), ("perm_bytes", i32),
+                ("n_slices", i64), ("n_words", i64), ("n_dummies", i64), ("k_left", i64),
+                ("pack", vp), ("offset", vp), ("perm", vp), ("row_exp", vp)]
+
+
+class CSell(ctypes.Structure):
+    _fields_ = [("n", i64), ("m", i64), ("nnz", i64),
+                ("C", i32), ("sigma", i32), ("perm_mode", i32), ("perm_bytes", i32),
+                ("dtype", i32), ("reserved", i32),
+                ("n_slices", i64), ("n_slots", i64),
+                ("offset", vp), ("perm", vp), ("col", vp), ("val", vp)]
+
+
+class CPcgInfo(ctypes.Structure):
+    _fields_ = [("outer_iterations", i32), ("inner_iterations", i32),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+_PROTOS = {
+    "pksell_version": ([], ctypes.c_int),
+    "pksell_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "pksell_last_error": ([], ctypes.c_char_p),
+    "pksell_encode_query": ([i64, i64, i64, i32, i32, i32, i32, i32,
+                             ctypes.POINTER(CMatrix), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pksell_encode": ([vp, vp, vp, i32, ctypes.POINTER(CMatrix), vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "pksell_spmv": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
+    "pksell_spmv_t": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
+    "pksell_grad_values": ([ctypes.POINTER(CMatrix), vp, vp, vp, vp, vp], ctypes.c_int),
+    "pksell_decode": ([ctypes.POINTER(CMatrix), vp, vp, vp], ctypes.c_int),
+    "pksell_sell_query": ([i64, i64, i64, i32, i32, i32, i32,
+                           ctypes.POINTER(CSell), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pksell_sell_encode": ([vp, vp, vp, i32, ctypes.POINTER(CSell), vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "pksell_sell_spmv": ([ctypes.POINTER(CSell), vp, vp, vp], ctypes.c_int),
+}
+
+OPTIONAL = {
+    "pksell_pcg": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CSell), vp, vp, ctypes.c_double,
+                    i32, i32, ctypes.POINTER(CPcgInfo), vp, ctypes.c_size_t, vp], ctypes.c_int),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in {**_PROTOS, **OPTIONAL}.items():
+            if hasattr(L, name):
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(set(_PROTOS) | set(OPTIONAL))
+
+
+def _check(status: int):
+    if status != OK:
+        raise PackSELLError(status, lib().pksell_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(t, dtype, device):
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+class PackSELLMatrix:
+    """A PackSELL matrix on the GPU (device arrays held as torch tensors)."""
+
+    def __init__(self, desc: CMatrix, tensors: dict, device):
+        self.desc = desc
+        self.t = tensors
+        self.device = device
+
+    # shape / statistics
+    n = property(lambda s: s.desc.n)
+    m = property(lambda s: s.desc.m)
+    nnz = property(lambda s: s.desc.nnz)
+    n_words = property(lambda s: s.desc.n_words)
+    n_dummies = property(lambda s: s.desc.n_dummies)
+    k_left = property(lambda s: s.desc.k_left)
+    fmt = property(lambda s: s.desc.fmt)
+    D = property(lambda s: s.desc.D)
+    C = property(lambda s: s.desc.C)
+    sigma = property(lambda s: s.desc.sigma)
+    perm_mode = property(lambda s: s.desc.perm_mode)
+
+    @property
+    def pack(self):
+        return self.t["pack"]
+
+    @property
+    def offset(self):
+        return self.t["offset"]
+
+    @property
+    def perm(self):
+        p = self.t.get("perm")
+        if p is None:
+            return None
+        return p.view(torch.uint8) if self.desc.perm_bytes == 1 else p.view(torch.int16)
+
+    @property
+    def row_exp(self):
+        return self.t.get("row_exp")
+
+    def bytes_per_spmv(self, k: int = 1) -> int:
+        """Algorithmic bytes of one product: every stored word (padding and
+        dummies included), the offsets, perm (implicit), row exponents
+        (FIX), x once and y once."""
+        d = self.desc
+        b = 4 * d.n_words + 8 * (d.n_slices + 1) + 4 * d.m * k + 4 * d.n * k
+        if d.perm_mode == IMPLICIT:
+            b += d.perm_bytes * d.n
+        if d.fmt == FIX:
+            b += 2 * d.n
+        return int(b)
+
+    def replicate(self):
+        """A copy with its own word/offset/perm arrays (same descriptor)."""
+        t = {k: v.clone() for k, v in self.t.items()}
+        desc = CMatrix.from_buffer_copy(self.desc)
+        m = PackSELLMatrix(desc, t, self.device)
+        m._bind()
+        return m
+
+    def _bind(self):
+        d = self.desc
+        d.pack = self.t["pack"].data_ptr() if self.t.get("pack") is not None else None
+        d.offset = self.t["offset"].data_ptr()
+        d.perm = self.t["perm"].data_ptr() if self.t.get("perm") is not None else None
+        d.row_exp = self.t["row_exp"].data_ptr() if self.t.get("row_exp") is not None else None
+
+
+def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 64,
+           sigma: int = 256, perm_mode: int = IMPLICIT, device="cuda",
+           keep_perm: bool = True) -> PackSELLMatrix:
+    """CSR (numpy or torch; values float32 or float64) -> PackSELL on the GPU."""
+    if isinstance(fmt, str):
+        fmt = FMT_BY_NAME[fmt]
+    device = torch.device(device)
+    rp = _dev(rowptr, torch.int64, device)
+    cl = _dev(col, torch.int32, device)
+    if isinstance(val, np.ndarray):
+        vdt = torch.float64 if val.dtype == np.float64 else torch.float32
+    else:
+        vdt = torch.float64 if val.dtype == torch.float64 else torch.float32
+    vl = _dev(val, vdt, device)
+    nnz = int(cl.numel())
+    desc = CMatrix()
+    ws_bytes = ctypes.c_size_t()
+    L = lib()
+    _check(L.pksell_encode_query(n, m, nnz, C, sigma, D, fmt, perm_mode,
+                                 ctypes.byref(desc), ctypes.byref(ws_bytes)))
+    t = {"offset": torch.empty(desc.n_slices + 1, dtype=torch.int64, device=device)}
+    if perm_mode == IMPLICIT or keep_perm:
+        t["perm"] = torch.empty(max(1, n * desc.perm_bytes), dtype=torch.uint8, device=device)
+    ws = torch.empty(max(1, ws_bytes.value), dtype=torch.uint8, device=device)
+    A = PackSELLMatrix(desc, t, device)
+    A._bind()
+    st = _stream(device)
+    vcode = F64 if vdt == torch.float64 else F32
+    _check(L.pksell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
+                           _ptr(ws), ws_bytes.value, st))
+    t["pack"] = torch.empty(max(1, desc.n_words), dtype=torch.int32, device=device)
+    if fmt == FIX:
+        t["row_exp"] = torch.empty(max(1, n), dtype=torch.int16, device=device)
+    A._bind()
+    _check(L.pksell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
+                           _ptr(ws), ws_bytes.value, st))
+    return A
+
+
+def spmv(A: PackSELLMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    """y = A_q x (x: m or m x k float32 on the device)."""
+    k = 1 if x.dim() == 1 else x.shape[1]
+    if y is None:
+        y = torch.empty((A.n,) if x.dim() == 1 else (A.n, k), dtype=torch.float32, device=x.device)
+    assert x.dtype == torch.float32 and x.is_contiguous() and x.shape[0] == A.m
+    assert y.dtype == torch.float32 and y.is_contiguous() and y.shape[0] == A.n
+    _check(lib().pksell_spmv(ctypes.byref(A.desc), _ptr(x), _ptr(y), k, _stream(x.device)))
+    return y
+
+
+def spmv_t(A: PackSELLMatrix, g: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    """y = A_q^T g (g: n or n x k float32)."""
+    k = 1 if g.dim() == 1 else g.shape[1]
+    if y is None:
+        y = torch.empty((A.m,) if g.dim() == 1 else (A.m, k), dtype=torch.float32, device=g.device)
+    assert g.dtype == torch.float32 and g.is_contiguous() and g.shape[0] == A.n
+    _check(lib().pksell_spmv_t(ctypes.byref(A.desc), _ptr(g), _ptr(y), k, _stream(g.device)))
+    return y
+
+
+def grad_values(A: PackSELLMatrix, rowptr: torch.Tensor, g: torch.Tensor,
+                x: torch.Tensor) -> torch.Tensor:
+    """g_i * x_j at every stored nonzero, in the CSR order of ``rowptr``."""
+    out = torch.empty(max(1, A.nnz), dtype=torch.float32, device=g.device)
+    rp = _dev(rowptr, torch.int64, g.device)
+    _check(lib().pksell_grad_values(ctypes.byref(A.desc), _ptr(rp), _ptr(g), _ptr(x),
+                                    _ptr(out), _stream(g.device)))
+    return out[:A.nnz]
+
+
+def decode(A: PackSELLMatrix):
+    """(column, value) at every word position (phantom rows left at 0)."""
+    cols = torch.zeros(max(1, A.n_words), dtype=torch.int32, device=A.device)
+    vals = torch.zeros(max(1, A.n_words), dtype=torch.float32, device=A.device)
+    _check(lib().pksell_decode(ctypes.byref(A.desc), _ptr(cols), _ptr(vals), _stream(A.device)))
+    return cols[:A.n_words], vals[:A.n_words]
+
+
+class SellMatrix:
+    """Plain SELL-C-sigma with float32 or float64 values (the comparator)."""
+
+    def __init__(self, desc: CSell, tensors: dict, device):
+        self.desc = desc
+        self.t = tensors
+        self.device = device
+
+    n = property(lambda s: s.desc.n)
+    m = property(lambda s: s.desc.m)
+    n_slots = property(lambda s: s.desc.n_slots)
+
+    @property
+    def dtype(self):
+        return torch.float64 if self.desc.dtype == F64 else torch.float32
+
+    def bytes_per_spmv(self) -> int:
+        d = self.desc
+        vb = 8 if d.dtype == F64 else 4
+        b = (vb + 4) * d.n_slots + 8 * (d.n_slices + 1) + vb * (d.m + d.n)
+        if d.perm_mode == IMPLICIT:
+            b += d.perm_bytes * d.n
+        return int(b)
+
+    def replicate(self):
+        t = {k: v.clone() for k, v in self.t.items()}
+        desc = CSell.from_buffer_copy(self.desc)
+        s = SellMatrix(desc, t, self.device)
+        s._bind()
+        return s
+
+    def _bind(self):
+        d = self.desc
+        d.offset = self.t["offset"].data_ptr()
+        d.perm = self.t["perm"].data_ptr() if self.t.get("perm") is not None else None
+        d.col = self.t["col"].data_ptr() if self.t.get("col") is not None else None
+        d.val = self.t["val"].data_ptr() if self.t.get("val") is not None else None
+
+
+def sell_encode(rowptr, col, val, n: int, m: int, dtype=torch.float32, C: int = 64,
+                sigma: int = 256, perm_mode: int = IMPLICIT, device="cuda") -> SellMatrix:
+    device = torch.device(device)
+    rp = _dev(rowptr, torch.int64, device)
+    cl = _dev(col, torch.int32, device)
+    vdt = torch.float64 if (isinstance(val, np.ndarray) and val.dtype == np.float64) or \
+        (isinstance(val, torch.Tensor) and val.dtype == torch.float64) else torch.float32
+    vl = _dev(val, vdt, device)
+    code = F64 if dtype == torch.float64 else F32
+    desc = CSell()
+    ws_bytes = ctypes.c_size_t()
+    L = lib()
+    _check(L.pksell_sell_query(n, m, int(cl.numel()), C, sigma, code, perm_mode,
+                               ctypes.byref(desc), ctypes.byref(ws_bytes)))
+    t = {"offset": torch.empty(desc.n_slices + 1, dtype=torch.int64, device=device)}
+    if perm_mode == IMPLICIT:
+        t["perm"] = torch.empty(max(1, n * desc.perm_bytes), dtype=torch.uint8, device=device)
+    ws = torch.empty(max(1, ws_bytes.value), dtype=torch.uint8, device=device)
+    S = SellMatrix(desc, t, device)
+    S._bind()
+    st = _stream(device)
+    vcode = F64 if vdt == torch.float64 else F32
+    _check(L.pksell_sell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
+                                _ptr(ws), ws_bytes.value, st))
+    t["col"] = torch.empty(max(1, desc.n_slots), dtype=torch.int32, device=device)
+    t["val"] = torch.empty(max(1, desc.n_slots), dtype=dtype, device=device)
+    S._bind()
+    _check(L.pksell_sell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
+                                _ptr(ws), ws_bytes.value, st))
+    return S
+
+
+def sell_spmv(S: SellMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    if y is None:
+        y = torch.empty(S.n, dtype=S.dtype, device=x.device)
+    assert x.dtype == S.dtype and y.dtype == S.dtype and x.numel() == S.m
+    _check(lib().pksell_sell_spmv(ctypes.byref(S.desc), _ptr(x), _ptr(y), _stream(x.device)))
+    return y

@@ -1,0 +1,348 @@
+// PackSELL SpMV y = A_q x (sec. 4.4) and the plain SELL-C-sigma SpMV
+// (sec. 3) on gfx950.
+//
+// One lane per stored row: thread t of the grid owns stored row t, i.e.
+// slice t / C, lane t mod C, so a wave64 reads 64 consecutive words of the
+// column-major slice per step (fully coalesced; with C = 64 the wave is one
+// slice and its loop bounds are scalar).  Each word is unpacked in
+// registers, the column is the running sum of deltas from the eq. 4 offset,
+// and x is gathered through a buffer resource whose range check returns 0
+// past the end (padding of empty rows can point past m).  Accumulation is
+// float32, in word order.  Workgroups are remapped so each XCD walks one
+// contiguous range of slices and its L2 serves the x window they share.
+#include "codec.hpp"
+
+namespace pksell {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kUnroll = 8;
+
+struct SpmvArgs {
+  const uint32_t *pack;
+  const int64_t *offset;
+  const void *perm;
+  const int16_t *row_exp;
+  const float *x;
+  float *y;
+  uint32_t n, m, n_slices;
+  int32_t C, perm_bytes, k, r0;
+  RowGeo geo;
+  Codec cd;
+};
+
+__device__ inline uint32_t out_row(const void *perm, int32_t perm_bytes, uint32_t t,
+                                   const RowGeo &g) {
+  if (perm == nullptr) return t;
+  return block_start(t, g) + (perm_bytes == 1 ? (uint32_t) static_cast<const uint8_t *>(perm)[t]
+                                              : (uint32_t) static_cast<const uint16_t *>(perm)[t]);
+}
+
+// Slice coordinates of the calling lane: stored row t, slice k = t / C,
+// lane l, slice start s (words) and width w.  With C = 64 a wave is exactly
+// one slice, so k, s and w are made wave-uniform (scalar loads, scalar loop).
+struct Lane {
+  uint32_t k, l, t, w;
+  int64_t s;
+};
+
+template <bool CWAVE>
+__device__ inline bool lane_slice(const int64_t *offset, uint32_t n_slices, const RowGeo &g,
+                                  Lane &ln) {
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  if constexpr (CWAVE) {
+    ln.k = __builtin_amdgcn_readfirstlane(b * (kBlock / kWave) + (threadIdx.x / kWave));
+    ln.l = threadIdx.x & (kWave - 1);
+    ln.t = ln.k * kWave + ln.l;
+  } else {
+    ln.t = b * kBlock + threadIdx.x;
+    ln.k = ln.t >> g.c_log2;
+    ln.l = ln.t - (ln.k << g.c_log2);
+  }
+  if (ln.k >= n_slices) return false;
+  ln.s = offset[ln.k];
+  ln.w = (uint32_t)((offset[ln.k + 1] - ln.s) >> g.c_log2);
+  return true;
+}
+
+// KB right-hand sides (columns r0 .. r0+KB-1 of the row-major x / y blocks;
+// K1: k == 1, so the x offset is a shift).  Words are processed in groups
+// of kUnroll: all loads of a group are issued together, the columns are
+// the running sums of the deltas, then all gathers are issued together and
+// the products are accumulated in word order.  The last partial group
+// re-reads the slice's last word (clamped, in bounds) and turns the extra
+// words into padding (delta 0, value 0).
+template <int FMT, bool CWAVE, int KB, bool K1>
+__global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
+  Lane ln;
+  if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
+  const uint32_t t = ln.t, w = ln.w;
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, (uint32_t)a.m * (uint32_t)a.k * 4u);
+  const uint32_t kx = (uint32_t)a.k * 4u, x0 = (uint32_t)a.r0 * 4u;
+  uint32_t c = left_offset32(t, a.geo);
+  float acc[KB];
+#pragma unroll
+  for (int r = 0; r < KB; ++r) acc[r] = 0.0f;
+  const uint32_t *P = a.pack + ln.s + ln.l;
+  const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)a.C;
+  auto group = [&](uint32_t j, bool full) {
+    uint32_t p[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const uint32_t jj = full ? j + q : min(j + q, w - 1);
+      p[q] = __builtin_nontemporal_load(P + jj * stride);
+      if (!full && j + q >= w) p[q] = 0u;
+    }
+    uint32_t xo[kUnroll];
+    float v[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const Unpacked u = unpack(p[q], a.cd);
+      c += u.delta;
+      xo[q] = K1 ? (c << 2) : (c * kx + x0);
+      v[q] = decode_value<FMT>(u.vbits);
+    }
+#pragma unroll
+    for (int r = 0; r < KB; ++r) {
+      float xv[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) xv[q] = buffer_load_f32(rx, xo[q] + 4u * r);
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) acc[r] = fmaf(v[q], xv[q], acc[r]);
+    }
+  };
+  uint32_t j = 0;
+  for (; j + kUnroll <= w; j += kUnroll) group(j, true);
+  if (j < w) group(j, false);
+  if (t >= a.n) return;
+  if constexpr (FMT == PKSELL_FIX) {
+    const int sh = (int)a.row_exp[t] - (a.cd.D + 1);
+#pragma unroll
+    for (int r = 0; r < KB; ++r) acc[r] = ldexpf(acc[r], sh);
+  }
+  const int64_t o = (int64_t)out_row(a.perm, a.perm_bytes, t, a.geo) * a.k + a.r0;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) a.y[o + r] = acc[r];
+}
+
+// Word-by-word decode: the column reached at each word position and the
+// decoded value (0 for flag-0 words, FIX times the row scale).
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_decode(SpmvArgs a, int32_t *cols, float *vals) {
+  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= a.n) return;
+  const uint32_t k = t >> a.geo.c_log2, l = t - (k << a.geo.c_log2);
+  const int64_t s = a.offset[k];
+  const int64_t w = (a.offset[k + 1] - s) >> a.geo.c_log2;
+  uint32_t c = left_offset32(t, a.geo);
+  for (int64_t j = 0; j < w; ++j) {
+    const int64_t p = s + j * a.C + l;
+    Unpacked u = unpack(a.pack[p], a.cd);
+    c += u.delta;
+    cols[p] = (int32_t)c;
+    float v = decode_value<FMT>(u.vbits);
+    if constexpr (FMT == PKSELL_FIX) v = ldexpf(v, (int)a.row_exp[t] - (a.cd.D + 1));
+    vals[p] = v;
+  }
+}
+
+__global__ void k_fill_zero_f32(float *p, int64_t len) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = 0.0f;
+}
+
+template <typename T>
+__global__ void k_fill_zero(T *p, int64_t len) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = T(0);
+}
+
+// Plain SELL-C-sigma SpMV (sec. 3): the float32 / float64 comparator, with
+// the same lane mapping and batched loads as the PackSELL kernel.
+template <typename T, bool CWAVE>
+__global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict__ offset,
+                                                      const int32_t *__restrict__ scol,
+                                                      const T *__restrict__ sval, const void *perm,
+                                                      int32_t perm_bytes, const T *__restrict__ x,
+                                                      T *__restrict__ y, uint32_t n,
+                                                      uint32_t n_slices, int32_t C, RowGeo g) {
+  Lane ln;
+  if (!lane_slice<CWAVE>(offset, n_slices, g, ln)) return;
+  const uint32_t t = ln.t, w = ln.w;
+  const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)C;
+  T acc = 0;
+  const int32_t *pc = scol + ln.s + ln.l;
+  const T *pv = sval + ln.s + ln.l;
+  for (uint32_t j = 0; j < w; j += kUnroll) {
+    int32_t cc[kUnroll];
+    T vv[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const bool in = j + q < w;
+      cc[q] = in ? __builtin_nontemporal_load(pc + (j + q) * stride) : 0;
+      vv[q] = in ? __builtin_nontemporal_load(pv + (j + q) * stride) : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q)
+      if (j + q < w) acc += vv[q] * x[cc[q]];
+  }
+  if (t >= n) return;
+  y[out_row(perm, perm_bytes, t, g)] = acc;
+}
+
+SpmvArgs make_args(const pksell_matrix *A, const float *x, float *y, int64_t k) {
+  SpmvArgs a;
+  a.pack = A->pack;
+  a.offset = A->offset;
+  a.perm = A->perm_mode == PKSELL_IMPLICIT ? A->perm : nullptr;
+  a.row_exp = A->row_exp;
+  a.x = x;
+  a.y = y;
+  a.n = (uint32_t)A->n;
+  a.m = (uint32_t)A->m;
+  a.n_slices = (uint32_t)A->n_slices;
+  a.C = A->C;
+  a.geo = make_geo(A->sigma, A->k_left, A->C);
+  a.perm_bytes = A->perm_bytes;
+  a.k = (int32_t)k;
+  a.r0 = 0;
+  a.cd = make_codec(A->D);
+  return a;
+}
+
+int check_matrix(const pksell_matrix *A) {
+  PKS_CHECK(A, PKSELL_EINVAL, "null matrix");
+  PKS_CHECK(A->n == 0 || (A->offset && (A->n_words == 0 || A->pack)), PKSELL_EINVAL,
+            "matrix arrays not set");
+  PKS_CHECK(A->perm_mode != PKSELL_IMPLICIT || A->n == 0 || A->perm, PKSELL_EINVAL,
+            "implicit mode needs perm");
+  PKS_CHECK(A->fmt != PKSELL_FIX || A->n == 0 || A->row_exp, PKSELL_EINVAL, "FIX needs row_exp");
+  PKS_CHECK(A->fmt >= PKSELL_FP16 && A->fmt <= PKSELL_FIX, PKSELL_EINVAL, "bad fmt");
+  return PKSELL_OK;
+}
+
+template <int FMT, bool CW>
+int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, hipStream_t st) {
+  if (k == 1) {
+    k_spmv<FMT, CW, 1, true><<<grid, kBlock, 0, st>>>(base);
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
+  int64_t r0 = 0;
+  while (r0 < k) {
+    SpmvArgs a = base;
+    a.r0 = (int32_t)r0;
+    int64_t left = k - r0;
+    if (left >= 8) {
+      k_spmv<FMT, CW, 8, false><<<grid, kBlock, 0, st>>>(a);
+      r0 += 8;
+    } else if (left >= 4) {
+      k_spmv<FMT, CW, 4, false><<<grid, kBlock, 0, st>>>(a);
+      r0 += 4;
+    } else if (left >= 2) {
+      k_spmv<FMT, CW, 2, false><<<grid, kBlock, 0, st>>>(a);
+      r0 += 2;
+    } else {
+      k_spmv<FMT, CW, 1, false><<<grid, kBlock, 0, st>>>(a);
+      r0 += 1;
+    }
+    PKS_LAUNCHED();
+  }
+  return PKSELL_OK;
+}
+
+template <int FMT>
+int launch_fmt(const SpmvArgs &a, int64_t grid, int64_t k, int32_t C, hipStream_t st) {
+  return C == kWave ? launch_fmt_cw<FMT, true>(a, grid, k, st)
+                    : launch_fmt_cw<FMT, false>(a, grid, k, st);
+}
+
+}  // namespace
+
+// Zero-fills float32 device memory with a kernel (safe inside captured graphs).
+int zero_f32(float *p, int64_t len, hipStream_t st) {
+  if (len <= 0) return PKSELL_OK;
+  k_fill_zero_f32<<<cdiv(len, kBlock), kBlock, 0, st>>>(p, len);
+  PKS_LAUNCHED();
+  return PKSELL_OK;
+}
+
+int check_matrix_public(const pksell_matrix *A) { return check_matrix(A); }
+
+}  // namespace pksell
+
+using namespace pksell;
+
+extern "C" {
+
+int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, void *stream) {
+  int rc = check_matrix(A);
+  if (rc) return rc;
+  PKS_CHECK(k >= 1 && k <= 64, PKSELL_EINVAL, "k must be in [1, 64]");
+  PKS_CHECK(A->m * k * 4 < (int64_t(1) << 32), PKSELL_ERANGE, "m * k * 4 must be below 2^32");
+  PKS_CHECK(A->n == 0 || y, PKSELL_EINVAL, "null y");
+  hipStream_t st = as_stream(stream);
+  if (A->n == 0) return PKSELL_OK;
+  if (A->m == 0) return zero_f32(y, A->n * k, st);
+  PKS_CHECK(x, PKSELL_EINVAL, "null x");
+  SpmvArgs a = make_args(A, x, y, k);
+  const int64_t grid = cdiv(A->n_slices * A->C, kBlock);
+  switch (A->fmt) {
+    case PKSELL_FP16: return launch_fmt<PKSELL_FP16>(a, grid, k, A->C, st);
+    case PKSELL_E8MY: return launch_fmt<PKSELL_E8MY>(a, grid, k, A->C, st);
+    default: return launch_fmt<PKSELL_FIX>(a, grid, k, A->C, st);
+  }
+}
+
+int pksell_decode(const pksell_matrix *A, int32_t *cols, float *vals, void *stream) {
+  int rc = check_matrix(A);
+  if (rc) return rc;
+  PKS_CHECK(A->n_words == 0 || (cols && vals), PKSELL_EINVAL, "null output");
+  hipStream_t st = as_stream(stream);
+  if (A->n == 0) return PKSELL_OK;
+  SpmvArgs a = make_args(A, nullptr, nullptr, 1);
+  const int64_t grid = cdiv(A->n, kBlock);
+  switch (A->fmt) {
+    case PKSELL_FP16: k_decode<PKSELL_FP16><<<grid, kBlock, 0, st>>>(a, cols, vals); break;
+    case PKSELL_E8MY: k_decode<PKSELL_E8MY><<<grid, kBlock, 0, st>>>(a, cols, vals); break;
+    default: k_decode<PKSELL_FIX><<<grid, kBlock, 0, st>>>(a, cols, vals); break;
+  }
+  PKS_LAUNCHED();
+  return PKSELL_OK;
+}
+
+int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream) {
+  PKS_CHECK(S, PKSELL_EINVAL, "null matrix");
+  PKS_CHECK(S->n == 0 || (S->offset && y), PKSELL_EINVAL, "arrays not set");
+  PKS_CHECK(S->n_slots == 0 || (S->col && S->val), PKSELL_EINVAL, "arrays not set");
+  PKS_CHECK(S->perm_mode != PKSELL_IMPLICIT || S->n == 0 || S->perm, PKSELL_EINVAL,
+            "implicit mode needs perm");
+  hipStream_t st = as_stream(stream);
+  if (S->n == 0) return PKSELL_OK;
+  const void *perm = S->perm_mode == PKSELL_IMPLICIT ? S->perm : nullptr;
+  if (S->m == 0) {
+    if (S->dtype == PKSELL_F32) return zero_f32(static_cast<float *>(y), S->n, st);
+    k_fill_zero<double><<<cdiv(S->n, kBlock), kBlock, 0, st>>>(static_cast<double *>(y), S->n);
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
+  PKS_CHECK(x, PKSELL_EINVAL, "null x");
+  const int64_t grid = cdiv(S->n_slices * S->C, kBlock);
+#define PKS_SELL(T, CW)                                                                       \
+  k_sell_spmv<T, CW><<<grid, kBlock, 0, st>>>(S->offset, S->col, static_cast<const T *>(S->val), \
+                                             perm, S->perm_bytes, static_cast<const T *>(x),     \
+                                             static_cast<T *>(y), (uint32_t)S->n,                \
+                                             (uint32_t)S->n_slices, S->C,                        \
+                                             make_geo(S->sigma, 0, S->C))
+  if (S->dtype == PKSELL_F32) {
+    if (S->C == kWave) PKS_SELL(float, true); else PKS_SELL(float, false);
+  } else {
+    if (S->C == kWave) PKS_SELL(double, true); else PKS_SELL(double, false);
+  }
+#undef PKS_SELL
+  PKS_LAUNCHED();
+  return PKSELL_OK;
+}
+
+}  // extern "C"

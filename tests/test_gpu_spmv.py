@@ -1,0 +1,228 @@
+"""GPU parity: encoder words, decoded columns and SpMV against the oracle.
+
+Encoded words, offsets, perm and decoded columns must match the oracle bit
+for bit; products must agree with the oracle's float64 product on the same
+quantised values within 1e-6, normalised by ||A_q||_inf ||x||_inf.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import FMTS, SPMV_TOL, normalised_error, oracle_product, random_csr
+from oracle import formats as F
+from oracle import linalg as L
+from oracle import packsell as P
+from paper_2604_13433_amd import binding as B
+from paper_2604_13433_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def words(A):
+    return A.pack.cpu().numpy().view(np.uint32)[:A.n_words]
+
+
+def both(a, fmt, D, C, sigma, mode=B.IMPLICIT):
+    A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, C, sigma, mode, DEV)
+    E = P.encode(a.rowptr, a.col, a.val, a.n, a.m, FMTS[fmt], D, C, sigma, mode)
+    return A, E
+
+
+def assert_same_encoding(A, E):
+    assert A.k_left == E.k_left
+    assert A.n_dummies == E.n_dummies
+    assert A.n_words == E.n_words
+    assert np.array_equal(A.offset.cpu().numpy(), E.offset)
+    assert np.array_equal(words(A), E.pack)
+    if A.perm is not None and A.n:
+        assert np.array_equal(A.perm.cpu().numpy()[:A.n].astype(np.int64),
+                              E.perm.astype(np.int64))
+    if E.row_exp is not None and A.n:
+        assert np.array_equal(A.row_exp.cpu().numpy()[:A.n].astype(np.int64), E.row_exp)
+
+
+def check_spmv(A, a, fmt, D, x, mode, E):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    y = B.spmv(A, xt).cpu().numpy()
+    ref, q = oracle_product(a, FMTS[fmt], D, x)
+    if mode == B.EXPLICIT:
+        ref = ref[E.stored_rows]
+    err = normalised_error(y, ref, a, q, x)
+    assert err <= SPMV_TOL, err
+    return err
+
+
+def test_fixture_4x8():
+    with open(os.path.join(GOLD, "fixture_4x8_e8m20.json")) as f:
+        fx = json.load(f)
+    r, c, v = [], [], []
+    for i, row in enumerate(fx["rows"]):
+        for j, val in row:
+            r.append(i), c.append(j), v.append(val)
+    a = W.csr_from_triplets(fx["n"], fx["m"], r, c, v)
+    A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e8my", 2, 2, 2, B.IMPLICIT, DEV)
+    assert A.k_left == fx["k_left"] and A.n_dummies == fx["n_dummies"]
+    assert list(A.offset.cpu().numpy()) == fx["offset"]
+    assert [int(w) for w in words(A)] == [int(h, 16) for h in fx["pack"]]
+    assert list(A.perm.cpu().numpy()[:4]) == fx["perm"]
+    cols, _ = B.decode(A)
+    assert list(cols.cpu().numpy()) == fx["decoded_columns"]
+    y = B.spmv(A, torch.tensor(fx["x"], dtype=torch.float32, device=DEV)).cpu().numpy()
+    assert list(y) == fx["y"]
+    yt = B.spmv_t(A, torch.ones(4, dtype=torch.float32, device=DEV)).cpu().numpy()
+    assert list(yt) == fx["At_ones"]
+
+
+CASES = [("fp16", 15), ("e8my", 1), ("e8my", 2), ("e8my", 9), ("e8my", 12), ("e8my", 22),
+         ("fix", 15), ("fix", 4)]
+SHAPES = [(1, 1, 1.0), (37, 53, 0.2), (300, 280, 0.05), (1000, 777, None), (2500, 4000, None)]
+
+
+@pytest.mark.parametrize("fmt,D", CASES)
+@pytest.mark.parametrize("C,sigma", [(64, 256), (32, 256), (2, 2), (64, 1), (16, 4096), (8, 3)])
+def test_random_parity(fmt, D, C, sigma):
+    for si, (n, m, dens) in enumerate(SHAPES):
+        a = random_csr(1000 * D + 7 * C + si, n, m, density=dens, per_row=None if dens else 9)
+        x = W.uniform_vector(m, si + 1)
+        for mode in (B.IMPLICIT, B.EXPLICIT):
+            A, E = both(a, fmt, D, C, sigma, mode)
+            assert_same_encoding(A, E)
+            check_spmv(A, a, fmt, D, x, mode, E)
+        # decoded columns and values, word by word (positions of real rows)
+        _, tr_cols, tr_vals = P.spmv_algorithm(E, x, return_trace=True)
+        cols, vals = B.decode(A)
+        word_row = np.full(E.n_words, -1)
+        for t in range(a.n):
+            k, l = divmod(t, C)
+            word_row[E.offset[k] + l:E.offset[k + 1]:C] = t
+        live = word_row >= 0
+        assert np.array_equal(cols.cpu().numpy()[live], tr_cols[live])
+        dv = vals.cpu().numpy().astype(np.float64)[live]
+        ref_v = tr_vals[live]
+        if FMTS[fmt] == F.FMT_FIX:
+            # the oracle trace holds the integer q; the decoder applies 2^e
+            ref_v = np.ldexp(ref_v, E.row_exp[word_row[live]])
+        assert np.array_equal(dv, ref_v)
+
+
+@pytest.mark.parametrize("k", [2, 3, 8, 13])
+def test_multiple_rhs(k):
+    a = random_csr(5, 700, 650, density=0.02)
+    X = W.uniform_vector(a.m, 9, k=k)
+    for fmt, D in [("fp16", 15), ("e8my", 9), ("fix", 15)]:
+        A, E = both(a, fmt, D, 64, 256)
+        Y = B.spmv(A, torch.from_numpy(X).to(DEV)).cpu().numpy()
+        ref, q = oracle_product(a, FMTS[fmt], D, X)
+        assert normalised_error(Y, ref, a, q, X) <= SPMV_TOL
+
+
+def test_m1_poisson_fp16():
+    a = W.m1_poisson2d()
+    x = W.uniform_vector(a.m, 1)
+    for C in (64, 32):
+        A, E = both(a, "fp16", 15, C, 256)
+        assert_same_encoding(A, E)
+        assert A.n_dummies == 0 and A.k_left == 64
+        check_spmv(A, a, "fp16", 15, x, B.IMPLICIT, E)
+
+
+@pytest.mark.parametrize("fmt,D", [("fp16", 15), ("e8my", 9)])
+def test_m2_laplace3d_full_size(fmt, D):
+    """3D 7-point 128^3 (n = 2,097,152; nnz = 14,581,760) at the launch
+    configuration the benchmark times (C = 64, sigma = 256, implicit)."""
+    a = W.m2_laplace3d()
+    x = W.uniform_vector(a.m, 3)
+    A, E = both(a, fmt, D, 64, 256)
+    assert_same_encoding(A, E)
+    check_spmv(A, a, fmt, D, x, B.IMPLICIT, E)
+
+
+def test_sell_fp32_fp64():
+    a = random_csr(3, 3000, 2500, per_row=12)
+    x = W.uniform_vector(a.m, 4)
+    for dt in (torch.float32, torch.float64):
+        for mode in (B.IMPLICIT, B.EXPLICIT):
+            S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, dt, 64, 256, mode, DEV)
+            y = B.sell_spmv(S, torch.from_numpy(x.astype(np.float64)).to(DEV, dt)).cpu().numpy()
+            vals = a.val.astype(np.float32).astype(np.float64) if dt == torch.float32 else a.val
+            ref = L.spmv(a.rowptr, a.col, vals, x)
+            if mode == B.EXPLICIT:
+                # SELL sorts rows by nonzero count; PackSELL with deltas that
+                # never overflow (D = 22 > log2 m) has the same counts
+                E = P.encode(a.rowptr, a.col, a.val, a.n, a.m, F.FMT_E8MY, 22, 64, 256, mode)
+                assert E.n_dummies == 0
+                ref = ref[E.stored_rows]
+            tol = SPMV_TOL if dt == torch.float32 else 1e-14
+            assert normalised_error(y, ref, a, vals, x) <= tol
+
+
+def test_spmv_t_and_grad_values():
+    a = random_csr(8, 1200, 900, per_row=10)
+    g = W.uniform_vector(a.n, 5)
+    x = W.uniform_vector(a.m, 6)
+    for fmt, D in [("fp16", 15), ("e8my", 9), ("e8my", 1), ("fix", 15)]:
+        A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 256, B.IMPLICIT, DEV)
+        q = P.quantized_values(a.rowptr, a.col, a.val, a.n, FMTS[fmt], D)
+        yt = B.spmv_t(A, torch.from_numpy(g).to(DEV)).cpu().numpy()
+        ref = L.spmv_t(a.rowptr, a.col, q, g, a.m)
+        # normalised by ||A_q^T||_inf ||g||_inf (largest absolute column sum)
+        colsum = np.bincount(a.col, weights=np.abs(q), minlength=a.m).max()
+        assert np.max(np.abs(yt - ref)) / (colsum * np.abs(g).max()) <= SPMV_TOL
+        gv = B.grad_values(A, torch.from_numpy(a.rowptr).to(DEV), torch.from_numpy(g).to(DEV),
+                           torch.from_numpy(x).to(DEV)).cpu().numpy()
+        # one float32 product per entry: exact to the float32 rounding of g_i x_j
+        assert np.array_equal(gv, (g[a.rows()] * x[a.col]).astype(np.float32))
+
+
+def test_edge_shapes():
+    # empty matrix, all-empty rows, one column, tall matrix with empty rows
+    cases = [W.csr_from_triplets(0, 0, [], [], []),
+             W.csr_from_triplets(100, 50, [], [], []),
+             W.csr_from_triplets(70, 1, np.arange(0, 70, 3), np.zeros(24, int), np.ones(24)),
+             W.csr_from_triplets(300, 5, [0, 1, 2, 3, 4], [0, 1, 2, 3, 4], [1., 2, 3, 4, 5])]
+    for a in cases:
+        x = W.uniform_vector(max(a.m, 1), 2)[:a.m]
+        for fmt, D in [("fp16", 15), ("e8my", 3)]:
+            for sigma in (1, 64):
+                A, E = both(a, fmt, D, 64, sigma)
+                assert_same_encoding(A, E)
+                y = B.spmv(A, torch.from_numpy(x).to(DEV)).cpu().numpy()
+                ref, q = oracle_product(a, FMTS[fmt], D, x)
+                # at most one product per row: float32 rounding of the exact value
+                assert np.array_equal(y, ref.astype(np.float32)), (a.n, a.m, fmt, sigma)
+
+
+def test_errors_from_device_checks():
+    a = W.csr_from_triplets(3, 5, [0, 0, 1], [1, 3, 2], [1.0, 2.0, 3.0])
+    bad_order = a.col.copy()
+    bad_order[[0, 1]] = bad_order[[1, 0]]
+    with pytest.raises(B.PackSELLError) as e:
+        B.encode(a.rowptr, bad_order, a.val, 3, 5, "fp16", 15, 64, 256, B.IMPLICIT, DEV)
+    assert e.value.status == B.EINVAL
+    with pytest.raises(B.PackSELLError):
+        B.encode(a.rowptr, a.col, a.val, 3, 3, "fp16", 15, 64, 256, B.IMPLICIT, DEV)
+    with pytest.raises(B.PackSELLError):
+        B.encode(a.rowptr, a.col, np.array([1.0, np.inf, 2.0]), 3, 5, "fix", 15, 64, 256,
+                 B.IMPLICIT, DEV)
+    bad_rp = a.rowptr.copy()
+    bad_rp[1] = 7
+    with pytest.raises(B.PackSELLError):
+        B.encode(bad_rp, a.col, a.val, 3, 5, "fp16", 15, 64, 256, B.IMPLICIT, DEV)
+
+
+def test_float64_input_rounds_through_float32():
+    # 1 + 2^-11 + 2^-40 rounds to float32 1 + 2^-11, a half-precision tie
+    # that goes to even (1.0); a direct float64 -> half rounding would give
+    # 1 + 2^-10.  The encoder must round float64 -> float32 -> format.
+    v = np.array([1 + 2.0 ** -11 + 2.0 ** -40, -(1 + 3 * 2.0 ** -11 + 2.0 ** -40), 3.0])
+    a = W.csr_from_triplets(3, 3, [0, 1, 2], [0, 1, 2], v)
+    A, E = both(a, "fp16", 15, 64, 256)
+    assert_same_encoding(A, E)
+    assert int(words(A)[0]) >> 16 == 0x3C00
+    A, E = both(a, "e8my", 13, 64, 256)
+    assert_same_encoding(A, E)
