@@ -202,6 +202,43 @@ int pksell_sell_encode(const int64_t *rowptr, const int32_t *col,
 int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y,
                      void *stream);
 
+/* ------------------------------------------------------------------------
+ * Solvers (sec. 5.2): A x = b with ||b - A x||_2 / ||b||_2 < tol (eq. 6).
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes pksell_pcg needs for these matrices (A_lo may be NULL). */
+int pksell_pcg_workspace(const pksell_matrix *A_lo, const pksell_sell *A_hi,
+                         size_t *ws_bytes);
+
+/* Solves A x = b for a symmetric positive definite A given as A_hi, a
+ * float64 SELL matrix in implicit row order.  x (float64, n) holds the
+ * initial guess on entry and the solution on return; b (float64, n).
+ *
+ *  - A_lo != NULL: the inner-outer CG of sec. 5.2.2.  Outer iterations are
+ *    flexible CG (one previous direction kept) in float64 on A_hi; each is
+ *    preconditioned by m_in float32 CG iterations on A_lo, the PackSELL
+ *    encoding of the same matrix (implicit row order), started from zero on
+ *    the right-hand side r / ||r||.  Inner dot products, alpha and beta are
+ *    accumulated in float64.  max_outer bounds outer iterations.
+ *  - A_lo == NULL: plain float64 CG on A_hi (the baseline); max_outer bounds
+ *    iterations, m_in is ignored.
+ *
+ * No preconditioner is applied beyond the inner solve: scale the system
+ * symmetrically (Gbar^-1 A Gbar^-1, unit diagonal, sec. 5.2) beforehand so
+ * that Jacobi is the identity.  Convergence is judged on the recursively
+ * updated residual and confirmed on the true residual b - A x in float64
+ * (otherwise the iteration restarts from it).  ``info`` (host) receives
+ * iteration counts, the final true relative residual and the wall time.
+ * The call SYNCHRONISES: it waits for ``stream``, runs on a private stream
+ * (iterations replayed from captured HIP graphs, the host polling a few
+ * device scalars per replay) and returns when done.
+ * Returns PKSELL_ENOTCONV at the iteration limit (x holds the last
+ * iterate), PKSELL_EBREAKDOWN when p^T A p <= 0 or is not finite. */
+int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi,
+               const double *b, double *x, double tol, int32_t m_in,
+               int32_t max_outer, pksell_pcg_info *info, void *ws,
+               size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

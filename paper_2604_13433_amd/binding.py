@@ -71,10 +71,14 @@ _PROTOS = {
     "pksell_sell_spmv": ([ctypes.POINTER(CSell), vp, vp, vp], ctypes.c_int),
 }
 
-OPTIONAL = {
+_PROTOS.update({
+    "pksell_pcg_workspace": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CSell),
+                              ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_pcg": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CSell), vp, vp, ctypes.c_double,
                     i32, i32, ctypes.POINTER(CPcgInfo), vp, ctypes.c_size_t, vp], ctypes.c_int),
-}
+})
+
+OPTIONAL: dict = {}
 
 
 def lib():
@@ -340,3 +344,30 @@ def sell_spmv(S: SellMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> 
     assert x.dtype == S.dtype and y.dtype == S.dtype and x.numel() == S.m
     _check(lib().pksell_sell_spmv(ctypes.byref(S.desc), _ptr(x), _ptr(y), _stream(x.device)))
     return y
+
+
+class SolveInfo(dict):
+    """Iteration counts, final true relative residual, wall seconds, status."""
+
+
+def pcg(A_lo: PackSELLMatrix | None, A_hi: SellMatrix, b: torch.Tensor,
+        x0: torch.Tensor | None = None, tol: float = 1e-10, m_in: int = 50,
+        max_outer: int = 10000, check: bool = True):
+    """Solve A x = b: inner-outer CG with a PackSELL inner operator, or plain
+    float64 CG when ``A_lo`` is None.  Returns (x, info)."""
+    assert b.dtype == torch.float64 and b.numel() == A_hi.n
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    ws_bytes = ctypes.c_size_t()
+    lo = ctypes.byref(A_lo.desc) if A_lo is not None else None
+    L = lib()
+    _check(L.pksell_pcg_workspace(lo, ctypes.byref(A_hi.desc), ctypes.byref(ws_bytes)))
+    ws = torch.empty(max(1, ws_bytes.value), dtype=torch.uint8, device=b.device)
+    info = CPcgInfo()
+    st = L.pksell_pcg(lo, ctypes.byref(A_hi.desc), _ptr(b), _ptr(x), tol, m_in, max_outer,
+                      ctypes.byref(info), _ptr(ws), ws_bytes.value, _stream(b.device))
+    out = SolveInfo(outer_iterations=info.outer_iterations,
+                    inner_iterations=info.inner_iterations,
+                    rel_residual=info.rel_residual, seconds=info.seconds, status=st)
+    if check and st not in (OK,):
+        raise PackSELLError(st, L.pksell_last_error().decode())
+    return x, out

@@ -1,0 +1,740 @@
+// Solvers on the device (sec. 5.2): float64 conjugate gradients on a SELL
+// matrix, and the inner-outer CG of sec. 5.2.2 -- a flexible CG outer
+// iteration in float64 whose preconditioner is m_in float32 CG iterations
+// on the PackSELL matrix.  Dot products, alpha/beta and the convergence test
+// are float64 on the device; the host polls a few device scalars once per
+// captured graph replay.
+//
+// One CG iteration is two kernels: (A) the product q = A p, where p is
+// formed on the fly as r + beta * p_old at every gathered column and
+// written once by its row's lane (two p buffers alternate), fused with the
+// p.q reduction and alpha; (B) the vector updates fused with the r.r
+// reduction, beta and the convergence flag.  Reductions finish in the last
+// workgroup to arrive, summing per-workgroup partials in a fixed order, so
+// results do not depend on scheduling.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "rowdot.hpp"
+
+namespace pksell {
+
+namespace {
+
+constexpr int kB = kRowBlock;
+constexpr uint32_t kVecBlocks = 1024;
+
+struct State {
+  double rr, bnorm2, tol2, alpha, beta;  // outer / plain-CG scalars
+  double pq_prev, beta_o, nr;            // flexible CG
+  double in_rr, in_alpha, in_beta;       // inner CG
+  int32_t done, breakdown, inner_stop, iters, inner_iters, max_iters;
+  uint32_t counter;
+  int32_t pad;
+};
+
+// ---- reductions -----------------------------------------------------------------
+
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV]) {
+  __shared__ double sh[NV][kB / kWave];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[q][w] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int i = 0; i < kB / kWave; ++i) s += sh[q][i];
+      v[q] = s;
+    }
+  __syncthreads();
+}
+
+// Adds this workgroup's partial sums; returns true in the last workgroup to
+// arrive, whose thread 0 then holds the totals in ``tot``.
+template <int NV>
+__device__ inline bool reduce_last(double (&v)[NV], double *partials, State *st,
+                                   double (&tot)[NV]) {
+  __shared__ int amlast;
+  const uint32_t nb = gridDim.x;
+  block_sum(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      __hip_atomic_store(&partials[q * nb + blockIdx.x], v[q], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    uint32_t prev =
+        __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    amlast = prev == nb - 1;
+  }
+  __syncthreads();
+  if (!amlast) return false;
+  __threadfence();
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  for (uint32_t i = threadIdx.x; i < nb; i += kB)
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      acc[q] += __hip_atomic_load(&partials[q * nb + i], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  block_sum(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) tot[q] = acc[q];
+    __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return true;
+}
+
+__device__ inline bool outer_stopped(const State *st) {
+  return st->done || st->iters >= st->max_iters;
+}
+
+// ---- matrix views ---------------------------------------------------------------
+
+struct PackView {
+  const uint32_t *pack;
+  const int64_t *offset;
+  const void *perm;
+  const int16_t *row_exp;
+  uint32_t n, n_slices;
+  int32_t C, perm_bytes;
+  RowGeo geo;
+  Codec cd;
+};
+
+struct SellView {
+  const int64_t *offset;
+  const int32_t *col;
+  const double *val;
+  const void *perm;
+  uint32_t n, n_slices;
+  int32_t C, perm_bytes;
+  RowGeo geo;
+};
+
+// Row dot product of a SELL lane: sum over its w slots of val * gather(col).
+template <typename Gather>
+__device__ inline double sell_row(const SellView &S, const Lane &ln, uint32_t stride,
+                                  Gather gather) {
+  const int32_t *pc = S.col + ln.s + ln.l;
+  const double *pv = S.val + ln.s + ln.l;
+  double acc = 0.0;
+  for (uint32_t j = 0; j < ln.w; j += kUnroll) {
+    int32_t cc[kUnroll];
+    double vv[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const uint32_t jj = min(j + q, ln.w - 1);
+      cc[q] = __builtin_nontemporal_load(pc + jj * stride);
+      vv[q] = j + q < ln.w ? __builtin_nontemporal_load(pv + jj * stride) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) acc = fma(vv[q], gather(cc[q]), acc);
+  }
+  return acc;
+}
+
+// ---- CG kernels -----------------------------------------------------------------
+
+// (A) float32 inner step on PackSELL: p_new = r + beta p_old, q = A_q p_new,
+// p_new . q -> alpha = rr / pq (inner_stop on breakdown).
+template <int FMT, bool CWAVE>
+__global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restrict__ r,
+                                               const float *__restrict__ p_old,
+                                               float *__restrict__ p_new, float *__restrict__ q,
+                                               State *st, double *partials) {
+  if (outer_stopped(st) || st->inner_stop) return;
+  const float beta = (float)st->in_beta;
+  Lane ln;
+  const bool live = lane_slice<CWAVE>(A.offset, A.n_slices, A.geo, ln);
+  double part = 0.0;
+  if (live) {
+    const __amdgpu_buffer_rsrc_t rr = make_rsrc(r, A.n * 4u);
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(p_old, A.n * 4u);
+    float acc[1] = {0.0f};
+    const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)A.C;
+    packsell_row<FMT, 1>(A.pack + ln.s + ln.l, stride, ln.w, left_offset32(ln.t, A.geo), A.cd,
+                         [&](uint32_t c, int) {
+                           return fmaf(beta, buffer_load_f32(rp, c << 2),
+                                       buffer_load_f32(rr, c << 2));
+                         },
+                         acc);
+    if (ln.t < A.n) {
+      float qi = acc[0];
+      if constexpr (FMT == PKSELL_FIX) qi = ldexpf(qi, (int)A.row_exp[ln.t] - (A.cd.D + 1));
+      const uint32_t i = out_row(A.perm, A.perm_bytes, ln.t, A.geo);
+      const float pn = fmaf(beta, p_old[i], r[i]);
+      p_new[i] = pn;
+      q[i] = qi;
+      part = (double)pn * (double)qi;
+    }
+  }
+  double v[1] = {part}, tot[1];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+    if (tot[0] > 0.0 && isfinite(tot[0]))
+      st->in_alpha = st->in_rr / tot[0];
+    else
+      st->inner_stop = 1;
+  }
+}
+
+// (B) float32 inner update: z += alpha p, r -= alpha q, rr -> beta.
+__global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ z,
+                                               float *__restrict__ r, const float *__restrict__ p,
+                                               const float *__restrict__ q, State *st,
+                                               double *partials) {
+  if (outer_stopped(st) || st->inner_stop) return;
+  const float alpha = (float)st->in_alpha;
+  double part = 0.0;
+  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
+    z[i] = fmaf(alpha, p[i], z[i]);
+    const float ri = fmaf(-alpha, q[i], r[i]);
+    r[i] = ri;
+    part += (double)ri * (double)ri;
+  }
+  double v[1] = {part}, tot[1];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+    st->inner_iters += 1;
+    if (tot[0] > 0.0 && isfinite(tot[0])) {
+      st->in_beta = tot[0] / st->in_rr;
+      st->in_rr = tot[0];
+    } else {
+      st->inner_stop = 1;
+    }
+  }
+}
+
+// (A) float64 CG step on SELL: p_new = r + beta p_old, q = A p_new, alpha.
+template <bool CWAVE>
+__global__ __launch_bounds__(kB) void k_cg_a(SellView S, const double *__restrict__ r,
+                                            const double *__restrict__ p_old,
+                                            double *__restrict__ p_new, double *__restrict__ q,
+                                            State *st, double *partials) {
+  if (outer_stopped(st)) return;
+  const double beta = st->beta;
+  Lane ln;
+  const bool live = lane_slice<CWAVE>(S.offset, S.n_slices, S.geo, ln);
+  double part = 0.0;
+  if (live) {
+    const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
+    const double qi = sell_row(S, ln, stride, [&](int32_t c) { return fma(beta, p_old[c], r[c]); });
+    if (ln.t < S.n) {
+      const uint32_t i = out_row(S.perm, S.perm_bytes, ln.t, S.geo);
+      const double pn = fma(beta, p_old[i], r[i]);
+      p_new[i] = pn;
+      q[i] = qi;
+      part = pn * qi;
+    }
+  }
+  double v[1] = {part}, tot[1];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+    if (tot[0] > 0.0 && isfinite(tot[0])) {
+      st->alpha = st->rr / tot[0];
+    } else {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  }
+}
+
+// (B) float64 CG update: x += alpha p, r -= alpha q, rr -> beta, converged?
+__global__ __launch_bounds__(kB) void k_cg_b(uint32_t n, double *__restrict__ x,
+                                            double *__restrict__ r, const double *__restrict__ p,
+                                            const double *__restrict__ q, State *st,
+                                            double *partials) {
+  if (outer_stopped(st)) return;
+  const double alpha = st->alpha;
+  double part = 0.0;
+  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
+    x[i] = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    part += ri * ri;
+  }
+  double v[1] = {part}, tot[1];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+    st->iters += 1;
+    st->beta = tot[0] / st->rr;
+    st->rr = tot[0];
+    if (!(tot[0] >= st->tol2)) st->done = 1;  // also stops on NaN
+  }
+}
+
+// ---- flexible-CG outer kernels (sec. 5.2.2) -----------------------------------
+
+// nr = ||r||: the inner right-hand side is r / nr.
+__global__ __launch_bounds__(kB) void k_outer_norm(uint32_t n, const double *__restrict__ r,
+                                                  State *st, double *partials) {
+  if (outer_stopped(st)) return;
+  double part = 0.0;
+  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) part += r[i] * r[i];
+  double v[1] = {part}, tot[1];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+    st->nr = sqrt(tot[0]);
+    st->inner_stop = !(st->nr > 0.0 && isfinite(st->nr));
+  }
+}
+
+// Inner start: r_in = r / nr (float32), z = 0, p_old = 0, beta = 0, rr_in.
+__global__ __launch_bounds__(kB) void k_inner_init(uint32_t n, const double *__restrict__ r,
+                                                  float *__restrict__ rin, float *__restrict__ zin,
+                                                  float *__restrict__ p0, State *st,
+                                                  double *partials) {
+  if (outer_stopped(st) || st->inner_stop) return;
+  const double inv = 1.0 / st->nr;
+  double part = 0.0;
+  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
+    const float v = (float)(r[i] * inv);
+    rin[i] = v;
+    zin[i] = 0.0f;
+    p0[i] = 0.0f;
+    part += (double)v * (double)v;
+  }
+  double v[1] = {part}, tot[1];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+    st->in_rr = tot[0];
+    st->in_beta = 0.0;
+    if (!(tot[0] > 0.0)) st->inner_stop = 1;
+  }
+}
+
+// beta_o = (z, q_prev) / (p_prev, q_prev) with z = nr * z_in (0 on the
+// first outer step or after a restart, when pq_prev = 0).
+__global__ __launch_bounds__(kB) void k_outer_zq(uint32_t n, const float *__restrict__ zin,
+                                                const double *__restrict__ q, State *st,
+                                                double *partials) {
+  if (outer_stopped(st)) return;
+  if (st->pq_prev == 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->beta_o = 0.0;
+    return;
+  }
+  const double nr = st->inner_stop && !(st->nr > 0.0) ? 0.0 : st->nr;
+  double part = 0.0;
+  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB)
+    part += (double)zin[i] * nr * q[i];
+  double v[1] = {part}, tot[1];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) st->beta_o = tot[0] / st->pq_prev;
+}
+
+// p = z - beta_o p (in place; p holds the previous direction).
+__global__ __launch_bounds__(kB) void k_outer_p(uint32_t n, const float *__restrict__ zin,
+                                               double *__restrict__ p, const State *st) {
+  if (outer_stopped(st)) return;
+  const double nr = st->nr, bo = st->beta_o;
+  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB)
+    p[i] = (double)zin[i] * nr - bo * p[i];
+}
+
+// q = A p (float64 SELL) with p.q and p.r -> alpha = (p, r) / (p, q).
+template <bool CWAVE>
+__global__ __launch_bounds__(kB) void k_outer_aq(SellView S, const double *__restrict__ p,
+                                                const double *__restrict__ r,
+                                                double *__restrict__ q, State *st,
+                                                double *partials) {
+  if (outer_stopped(st)) return;
+  Lane ln;
+  const bool live = lane_slice<CWAVE>(S.offset, S.n_slices, S.geo, ln);
+  double pq = 0.0, pr = 0.0;
+  if (live) {
+    const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
+    const double qi = sell_row(S, ln, stride, [&](int32_t c) { return p[c]; });
+    if (ln.t < S.n) {
+      const uint32_t i = out_row(S.perm, S.perm_bytes, ln.t, S.geo);
+      q[i] = qi;
+      pq = p[i] * qi;
+      pr = p[i] * r[i];
+    }
+  }
+  double v[2] = {pq, pr}, tot[2];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+    if (tot[0] > 0.0 && isfinite(tot[0])) {
+      st->alpha = tot[1] / tot[0];
+      st->pq_prev = tot[0];
+    } else {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  }
+}
+
+// x += alpha p, r -= alpha q, rr; converged when rr < tol^2 ||b||^2.
+__global__ __launch_bounds__(kB) void k_outer_update(uint32_t n, double *__restrict__ x,
+                                                    double *__restrict__ r,
+                                                    const double *__restrict__ p,
+                                                    const double *__restrict__ q, State *st,
+                                                    double *partials) {
+  if (outer_stopped(st)) return;
+  const double alpha = st->alpha;
+  double part = 0.0;
+  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
+    x[i] = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    part += ri * ri;
+  }
+  double v[1] = {part}, tot[1];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+    st->iters += 1;
+    st->rr = tot[0];
+    if (!(tot[0] >= st->tol2)) st->done = 1;
+  }
+}
+
+// True residual r = b - A x with r.r and b.b (float64 SELL).
+template <bool CWAVE>
+__global__ __launch_bounds__(kB) void k_residual(SellView S, const double *__restrict__ b,
+                                                const double *__restrict__ x,
+                                                double *__restrict__ r, State *st,
+                                                double *partials) {
+  Lane ln;
+  const bool live = lane_slice<CWAVE>(S.offset, S.n_slices, S.geo, ln);
+  double rr = 0.0, bb = 0.0;
+  if (live) {
+    const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
+    const double ax = sell_row(S, ln, stride, [&](int32_t c) { return x[c]; });
+    if (ln.t < S.n) {
+      const uint32_t i = out_row(S.perm, S.perm_bytes, ln.t, S.geo);
+      const double ri = b[i] - ax;
+      r[i] = ri;
+      rr = ri * ri;
+      bb = b[i] * b[i];
+    }
+  }
+  double v[2] = {rr, bb}, tot[2];
+  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+    st->rr = tot[0];
+    st->bnorm2 = tot[1];
+  }
+}
+
+template <typename T>
+__global__ void k_zero(T *p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) p[i] = T(0);
+}
+
+// ---- host side ------------------------------------------------------------------
+
+struct Work {
+  State *st;
+  double *partials, *r, *q, *pa, *pb;
+  float *rin, *zin, *p0, *p1, *qin;
+  size_t bytes;
+};
+
+Work carve_work(void *ws, int64_t n, int64_t max_blocks) {
+  Carver cv(ws);
+  Work w;
+  const size_t nn = n > 0 ? (size_t)n : 1;
+  w.st = cv.take<State>(1);
+  w.partials = cv.take<double>(2 * (size_t)max_blocks);
+  w.r = cv.take<double>(nn);
+  w.q = cv.take<double>(nn);
+  w.pa = cv.take<double>(nn);
+  w.pb = cv.take<double>(nn);
+  w.rin = cv.take<float>(nn);
+  w.zin = cv.take<float>(nn);
+  w.p0 = cv.take<float>(nn);
+  w.p1 = cv.take<float>(nn);
+  w.qin = cv.take<float>(nn);
+  w.bytes = cv.used;
+  return w;
+}
+
+int64_t max_blocks_of(const pksell_sell *S, const pksell_matrix *A) {
+  int64_t mb = (int64_t)kVecBlocks;
+  mb = std::max<int64_t>(mb, cdiv(S->n_slices * S->C, kB));
+  if (A) mb = std::max<int64_t>(mb, cdiv(A->n_slices * A->C, kB));
+  return mb;
+}
+
+SellView sell_view(const pksell_sell *S) {
+  SellView v;
+  v.offset = S->offset;
+  v.col = S->col;
+  v.val = static_cast<const double *>(S->val);
+  v.perm = S->perm;
+  v.n = (uint32_t)S->n;
+  v.n_slices = (uint32_t)S->n_slices;
+  v.C = S->C;
+  v.perm_bytes = S->perm_bytes;
+  v.geo = make_geo(S->sigma, 0, S->C);
+  return v;
+}
+
+PackView pack_view(const pksell_matrix *A) {
+  PackView v;
+  v.pack = A->pack;
+  v.offset = A->offset;
+  v.perm = A->perm;
+  v.row_exp = A->row_exp;
+  v.n = (uint32_t)A->n;
+  v.n_slices = (uint32_t)A->n_slices;
+  v.C = A->C;
+  v.perm_bytes = A->perm_bytes;
+  v.geo = make_geo(A->sigma, A->k_left, A->C);
+  v.cd = make_codec(A->D);
+  return v;
+}
+
+struct Solve {
+  const pksell_matrix *lo;
+  const pksell_sell *hi;
+  const double *b;
+  double *x;
+  Work w;
+  hipStream_t s;
+  uint32_t n, vb;
+  int64_t gs, gp;  // grids of the SELL and PackSELL product kernels
+
+  int residual() {
+    const SellView S = sell_view(hi);
+    if (hi->C == kWave)
+      k_residual<true><<<gs, kB, 0, s>>>(S, b, x, w.r, w.st, w.partials);
+    else
+      k_residual<false><<<gs, kB, 0, s>>>(S, b, x, w.r, w.st, w.partials);
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
+
+  // Enqueues ``count`` float64 CG iterations (count even: p buffers alternate).
+  int cg_iterations(int count) {
+    const SellView S = sell_view(hi);
+    for (int it = 0; it < count; ++it) {
+      double *po = (it & 1) ? w.pb : w.pa;
+      double *pn = (it & 1) ? w.pa : w.pb;
+      if (hi->C == kWave)
+        k_cg_a<true><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, w.partials);
+      else
+        k_cg_a<false><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, w.partials);
+      PKS_LAUNCHED();
+      k_cg_b<<<vb, kB, 0, s>>>(n, x, w.r, pn, w.q, w.st, w.partials);
+      PKS_LAUNCHED();
+    }
+    return PKSELL_OK;
+  }
+
+  template <int FMT, bool CW>
+  void inner_a(const PackView &A, const float *po, float *pn) {
+    k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, w.partials);
+  }
+
+  // Enqueues one flexible-CG outer iteration with m_in inner iterations.
+  int outer_iteration(int m_in) {
+    const SellView S = sell_view(hi);
+    const PackView A = pack_view(lo);
+    k_outer_norm<<<vb, kB, 0, s>>>(n, w.r, w.st, w.partials);
+    PKS_LAUNCHED();
+    k_inner_init<<<vb, kB, 0, s>>>(n, w.r, w.rin, w.zin, w.p0, w.st, w.partials);
+    PKS_LAUNCHED();
+    for (int it = 0; it < m_in; ++it) {
+      const float *po = (it & 1) ? w.p1 : w.p0;
+      float *pn = (it & 1) ? w.p0 : w.p1;
+      const bool cw = lo->C == kWave;
+      switch (lo->fmt) {
+        case PKSELL_FP16: cw ? inner_a<PKSELL_FP16, true>(A, po, pn) : inner_a<PKSELL_FP16, false>(A, po, pn); break;
+        case PKSELL_E8MY: cw ? inner_a<PKSELL_E8MY, true>(A, po, pn) : inner_a<PKSELL_E8MY, false>(A, po, pn); break;
+        default: cw ? inner_a<PKSELL_FIX, true>(A, po, pn) : inner_a<PKSELL_FIX, false>(A, po, pn); break;
+      }
+      PKS_LAUNCHED();
+      k_inner_b<<<vb, kB, 0, s>>>(n, w.zin, w.rin, pn, w.qin, w.st, w.partials);
+      PKS_LAUNCHED();
+    }
+    k_outer_zq<<<vb, kB, 0, s>>>(n, w.zin, w.q, w.st, w.partials);
+    PKS_LAUNCHED();
+    k_outer_p<<<vb, kB, 0, s>>>(n, w.zin, w.pa, w.st);
+    PKS_LAUNCHED();
+    if (hi->C == kWave)
+      k_outer_aq<true><<<gs, kB, 0, s>>>(S, w.pa, w.r, w.q, w.st, w.partials);
+    else
+      k_outer_aq<false><<<gs, kB, 0, s>>>(S, w.pa, w.r, w.q, w.st, w.partials);
+    PKS_LAUNCHED();
+    k_outer_update<<<vb, kB, 0, s>>>(n, x, w.r, w.pa, w.q, w.st, w.partials);
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
+};
+
+int read_state(const Work &w, State &h, hipStream_t s) {
+  PKS_HIP(hipMemcpyAsync(&h, w.st, sizeof(State), hipMemcpyDeviceToHost, s));
+  PKS_HIP(hipStreamSynchronize(s));
+  return PKSELL_OK;
+}
+
+int write_state(const Work &w, const State &h, hipStream_t s) {
+  PKS_HIP(hipMemcpyAsync(w.st, &h, sizeof(State), hipMemcpyHostToDevice, s));
+  PKS_HIP(hipStreamSynchronize(s));
+  return PKSELL_OK;
+}
+
+// Captures the work ``enqueue`` puts on stream s into an executable graph.
+template <typename F>
+int capture(hipStream_t s, F enqueue, hipGraphExec_t *exec) {
+  hipGraph_t g = nullptr;
+  PKS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue();
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  PKS_CHECK(e == hipSuccess, PKSELL_EHIP, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  PKS_CHECK(e == hipSuccess, PKSELL_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+  return PKSELL_OK;
+}
+
+int solve(Solve &sv, double tol, int32_t m_in, int32_t max_outer, pksell_pcg_info *info) {
+  hipStream_t s = sv.s;
+  const uint32_t n = sv.n;
+  const Work &w = sv.w;
+  k_zero<double><<<sv.vb, kB, 0, s>>>(w.pa, n);
+  k_zero<double><<<sv.vb, kB, 0, s>>>(w.pb, n);
+  k_zero<double><<<sv.vb, kB, 0, s>>>(w.q, n);
+  PKS_LAUNCHED();
+  State h{};
+  h.max_iters = max_outer;
+  int rc = write_state(w, h, s);
+  if (rc) return rc;
+  rc = sv.residual();
+  if (rc) return rc;
+  rc = read_state(w, h, s);
+  if (rc) return rc;
+  if (h.bnorm2 == 0.0) {  // b = 0: x = 0 solves it
+    k_zero<double><<<sv.vb, kB, 0, s>>>(sv.x, n);
+    PKS_LAUNCHED();
+    PKS_HIP(hipStreamSynchronize(s));
+    info->rel_residual = 0.0;
+    return PKSELL_OK;
+  }
+  h.tol2 = tol * tol * h.bnorm2;
+  h.beta = 0.0;
+  h.pq_prev = 0.0;
+  if (!(h.rr >= h.tol2)) {  // the initial guess already satisfies the test
+    info->rel_residual = std::sqrt(h.rr / h.bnorm2);
+    return PKSELL_OK;
+  }
+  rc = write_state(w, h, s);
+  if (rc) return rc;
+
+  const bool plain = sv.lo == nullptr;
+  constexpr int kCgPerGraph = 16;
+  hipGraphExec_t exec = nullptr;
+  rc = plain ? capture(s, [&] { return sv.cg_iterations(kCgPerGraph); }, &exec)
+             : capture(s, [&] { return sv.outer_iteration(m_in); }, &exec);
+  if (rc) return rc;
+  int status = PKSELL_OK;
+  for (;;) {
+    hipError_t e = hipGraphLaunch(exec, s);
+    if (e != hipSuccess) {
+      set_error("graph launch: %s", hipGetErrorString(e));
+      status = PKSELL_EHIP;
+      break;
+    }
+    if ((status = read_state(w, h, s))) break;
+    if (h.breakdown) {
+      set_error("breakdown after %d iterations (p^T A p <= 0 or not finite)", h.iters);
+      status = PKSELL_EBREAKDOWN;
+      break;
+    }
+    if (h.done) {
+      // confirm on the true residual b - A x; otherwise restart from it
+      if ((status = sv.residual())) break;
+      if ((status = read_state(w, h, s))) break;
+      if (h.rr < h.tol2) break;
+      h.done = 0;
+      h.beta = 0.0;
+      h.pq_prev = 0.0;
+      k_zero<double><<<sv.vb, kB, 0, s>>>(w.pa, n);
+      if ((status = write_state(w, h, s))) break;
+    }
+    if (h.iters >= max_outer) {
+      set_error("no convergence in %d iterations (relative residual %.3e)", h.iters,
+                std::sqrt(h.rr / h.bnorm2));
+      status = PKSELL_ENOTCONV;
+      break;
+    }
+  }
+  (void)hipGraphExecDestroy(exec);
+  info->outer_iterations = h.iters;
+  info->inner_iterations = h.inner_iters;
+  if (status == PKSELL_OK || status == PKSELL_ENOTCONV) {
+    int rc2 = sv.residual();
+    if (rc2 == PKSELL_OK) rc2 = read_state(w, h, s);
+    if (rc2) return rc2;
+  }
+  info->rel_residual = std::sqrt(h.rr / h.bnorm2);
+  return status;
+}
+
+}  // namespace
+}  // namespace pksell
+
+using namespace pksell;
+
+extern "C" {
+
+int pksell_pcg_workspace(const pksell_matrix *A_lo, const pksell_sell *A_hi, size_t *ws_bytes) {
+  PKS_CHECK(A_hi && ws_bytes, PKSELL_EINVAL, "null argument");
+  *ws_bytes = carve_work(nullptr, A_hi->n, max_blocks_of(A_hi, A_lo)).bytes;
+  return PKSELL_OK;
+}
+
+int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi, const double *b, double *x,
+               double tol, int32_t m_in, int32_t max_outer, pksell_pcg_info *info, void *ws,
+               size_t ws_bytes, void *stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  PKS_CHECK(A_hi && b && x && info, PKSELL_EINVAL, "null argument");
+  std::memset(info, 0, sizeof(*info));
+  PKS_CHECK(A_hi->n == A_hi->m, PKSELL_EINVAL, "the matrix must be square");
+  PKS_CHECK(A_hi->dtype == PKSELL_F64, PKSELL_EINVAL, "the outer matrix must be float64 SELL");
+  PKS_CHECK(A_hi->perm_mode == PKSELL_IMPLICIT, PKSELL_EINVAL,
+            "the solver needs implicit row order (original ordering)");
+  PKS_CHECK(A_hi->n > 0 && A_hi->offset && A_hi->col && A_hi->val && A_hi->perm, PKSELL_EINVAL,
+            "outer matrix arrays not set");
+  if (A_lo) {
+    PKS_CHECK(A_lo->n == A_hi->n && A_lo->m == A_hi->m, PKSELL_EINVAL, "shape mismatch");
+    PKS_CHECK(A_lo->perm_mode == PKSELL_IMPLICIT && A_lo->perm && A_lo->pack && A_lo->offset,
+              PKSELL_EINVAL, "inner PackSELL matrix must be implicit with arrays set");
+    PKS_CHECK(A_lo->fmt != PKSELL_FIX || A_lo->row_exp, PKSELL_EINVAL, "FIX needs row_exp");
+    PKS_CHECK(m_in >= 1 && m_in <= 10000, PKSELL_EINVAL, "m_in must be in [1, 10000]");
+  }
+  PKS_CHECK(tol > 0.0 && max_outer >= 1, PKSELL_EINVAL, "tol must be > 0, max_outer >= 1");
+  Solve sv;
+  sv.lo = A_lo;
+  sv.hi = A_hi;
+  sv.b = b;
+  sv.x = x;
+  sv.n = (uint32_t)A_hi->n;
+  sv.vb = (uint32_t)std::min<int64_t>(kVecBlocks, cdiv(A_hi->n, kB));
+  sv.gs = cdiv(A_hi->n_slices * A_hi->C, kB);
+  sv.gp = A_lo ? cdiv(A_lo->n_slices * A_lo->C, kB) : 0;
+  sv.w = carve_work(ws, A_hi->n, max_blocks_of(A_hi, A_lo));
+  PKS_CHECK(ws && ws_bytes >= sv.w.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes",
+            sv.w.bytes);
+  // The solve runs on a private stream (graph capture needs a non-default
+  // stream), ordered after the caller's prior work and finished on return.
+  PKS_HIP(hipStreamSynchronize(as_stream(stream)));
+  PKS_HIP(hipStreamCreateWithFlags(&sv.s, hipStreamNonBlocking));
+  int rc = solve(sv, tol, m_in, max_outer, info);
+  hipError_t e = hipStreamSynchronize(sv.s);
+  (void)hipStreamDestroy(sv.s);
+  if (rc == PKSELL_OK && e != hipSuccess) {
+    set_error("solver: %s", hipGetErrorString(e));
+    rc = PKSELL_EHIP;
+  }
+  info->seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+}  // extern "C"

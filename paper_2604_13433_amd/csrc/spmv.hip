@@ -10,14 +10,13 @@
 // past the end (padding of empty rows can point past m).  Accumulation is
 // float32, in word order.  Workgroups are remapped so each XCD walks one
 // contiguous range of slices and its L2 serves the x window they share.
-#include "codec.hpp"
+#include "rowdot.hpp"
 
 namespace pksell {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kUnroll = 8;
+constexpr int kBlock = kRowBlock;
 
 struct SpmvArgs {
   const uint32_t *pack;
@@ -32,89 +31,25 @@ struct SpmvArgs {
   Codec cd;
 };
 
-__device__ inline uint32_t out_row(const void *perm, int32_t perm_bytes, uint32_t t,
-                                   const RowGeo &g) {
-  if (perm == nullptr) return t;
-  return block_start(t, g) + (perm_bytes == 1 ? (uint32_t) static_cast<const uint8_t *>(perm)[t]
-                                              : (uint32_t) static_cast<const uint16_t *>(perm)[t]);
-}
-
-// Slice coordinates of the calling lane: stored row t, slice k = t / C,
-// lane l, slice start s (words) and width w.  With C = 64 a wave is exactly
-// one slice, so k, s and w are made wave-uniform (scalar loads, scalar loop).
-struct Lane {
-  uint32_t k, l, t, w;
-  int64_t s;
-};
-
-template <bool CWAVE>
-__device__ inline bool lane_slice(const int64_t *offset, uint32_t n_slices, const RowGeo &g,
-                                  Lane &ln) {
-  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-  if constexpr (CWAVE) {
-    ln.k = __builtin_amdgcn_readfirstlane(b * (kBlock / kWave) + (threadIdx.x / kWave));
-    ln.l = threadIdx.x & (kWave - 1);
-    ln.t = ln.k * kWave + ln.l;
-  } else {
-    ln.t = b * kBlock + threadIdx.x;
-    ln.k = ln.t >> g.c_log2;
-    ln.l = ln.t - (ln.k << g.c_log2);
-  }
-  if (ln.k >= n_slices) return false;
-  ln.s = offset[ln.k];
-  ln.w = (uint32_t)((offset[ln.k + 1] - ln.s) >> g.c_log2);
-  return true;
-}
-
 // KB right-hand sides (columns r0 .. r0+KB-1 of the row-major x / y blocks;
-// K1: k == 1, so the x offset is a shift).  Words are processed in groups
-// of kUnroll: all loads of a group are issued together, the columns are
-// the running sums of the deltas, then all gathers are issued together and
-// the products are accumulated in word order.  The last partial group
-// re-reads the slice's last word (clamped, in bounds) and turns the extra
-// words into padding (delta 0, value 0).
+// K1: k == 1, so the x offset is a shift).
 template <int FMT, bool CWAVE, int KB, bool K1>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
   Lane ln;
   if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
-  const uint32_t t = ln.t, w = ln.w;
+  const uint32_t t = ln.t;
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, (uint32_t)a.m * (uint32_t)a.k * 4u);
   const uint32_t kx = (uint32_t)a.k * 4u, x0 = (uint32_t)a.r0 * 4u;
-  uint32_t c = left_offset32(t, a.geo);
   float acc[KB];
 #pragma unroll
   for (int r = 0; r < KB; ++r) acc[r] = 0.0f;
-  const uint32_t *P = a.pack + ln.s + ln.l;
   const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)a.C;
-  auto group = [&](uint32_t j, bool full) {
-    uint32_t p[kUnroll];
-#pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      const uint32_t jj = full ? j + q : min(j + q, w - 1);
-      p[q] = __builtin_nontemporal_load(P + jj * stride);
-      if (!full && j + q >= w) p[q] = 0u;
-    }
-    uint32_t xo[kUnroll];
-    float v[kUnroll];
-#pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      const Unpacked u = unpack(p[q], a.cd);
-      c += u.delta;
-      xo[q] = K1 ? (c << 2) : (c * kx + x0);
-      v[q] = decode_value<FMT>(u.vbits);
-    }
-#pragma unroll
-    for (int r = 0; r < KB; ++r) {
-      float xv[kUnroll];
-#pragma unroll
-      for (int q = 0; q < kUnroll; ++q) xv[q] = buffer_load_f32(rx, xo[q] + 4u * r);
-#pragma unroll
-      for (int q = 0; q < kUnroll; ++q) acc[r] = fmaf(v[q], xv[q], acc[r]);
-    }
-  };
-  uint32_t j = 0;
-  for (; j + kUnroll <= w; j += kUnroll) group(j, true);
-  if (j < w) group(j, false);
+  packsell_row<FMT, KB>(a.pack + ln.s + ln.l, stride, ln.w, left_offset32(t, a.geo), a.cd,
+                        [&](uint32_t c, int r) {
+                          const uint32_t xo = K1 ? (c << 2) : (c * kx + x0 + 4u * r);
+                          return buffer_load_f32(rx, xo);
+                        },
+                        acc);
   if (t >= a.n) return;
   if constexpr (FMT == PKSELL_FIX) {
     const int sh = (int)a.row_exp[t] - (a.cd.D + 1);

@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every entry point its header declares;
+host-only argument checks return the documented status codes (no GPU work).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2604_13433_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(HEADER_DIR):
+        if fn.endswith(".h"):
+            text = open(os.path.join(HEADER_DIR, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(pksell_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_symbols()
+    for n in ("pksell_encode", "pksell_spmv", "pksell_spmv_t", "pksell_pcg"):
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+    # every declared entry point also has a Python prototype
+    assert set(declared_symbols()) <= set(B.exported_symbols())
+
+
+def test_version_and_status_strings():
+    lib = B.lib()
+    assert lib.pksell_version() >= 100
+    assert lib.pksell_status_string(0) == b"ok"
+    assert lib.pksell_status_string(-1) == b"invalid argument"
+    assert lib.pksell_status_string(-5) == b"solver did not converge"
+
+
+def _query(n=100, m=100, nnz=500, C=64, sigma=256, D=15, fmt=B.FP16, mode=B.IMPLICIT):
+    desc = B.CMatrix()
+    ws = ctypes.c_size_t()
+    rc = B.lib().pksell_encode_query(n, m, nnz, C, sigma, D, fmt, mode, ctypes.byref(desc),
+                                     ctypes.byref(ws))
+    return rc, desc, ws.value
+
+
+def test_encode_query_sizes():
+    rc, d, ws = _query(n=1000, C=32, sigma=256)
+    assert rc == 0 and d.n_slices == 32 and d.perm_bytes == 1 and ws > 0
+    rc, d, ws = _query(n=1000, C=64, sigma=4096)
+    assert rc == 0 and d.n_slices == 16 and d.perm_bytes == 2
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(C=3), B.EINVAL), (dict(C=128), B.EINVAL), (dict(C=0), B.EINVAL),
+    (dict(sigma=0), B.EINVAL), (dict(sigma=65537), B.EINVAL),
+    (dict(fmt=B.FP16, D=14), B.EINVAL), (dict(fmt=B.E8MY, D=0), B.EINVAL),
+    (dict(fmt=B.E8MY, D=23), B.EINVAL), (dict(fmt=B.FIX, D=30), B.EINVAL),
+    (dict(fmt=7), B.EINVAL), (dict(mode=3), B.EINVAL), (dict(n=-1), B.EINVAL),
+    (dict(n=1 << 30), B.ERANGE), (dict(m=1 << 30), B.ERANGE),
+])
+def test_encode_query_rejects(kw, code):
+    rc, _, _ = _query(**kw)
+    assert rc == code
+    assert B.lib().pksell_last_error()
+
+
+def test_sell_query_rejects_bad_dtype():
+    desc = B.CSell()
+    ws = ctypes.c_size_t()
+    rc = B.lib().pksell_sell_query(10, 10, 10, 64, 256, 2, B.IMPLICIT, ctypes.byref(desc),
+                                   ctypes.byref(ws))
+    assert rc == B.EINVAL

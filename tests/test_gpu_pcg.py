@@ -1,0 +1,106 @@
+"""GPU parity for the solvers: float64 CG and inner-outer CG (sec. 5.2.2).
+
+b = A 1 on a symmetrically scaled SPD stencil, so x* = 1 (closed form); the
+oracle's CG / IO-CG run on the same inputs.  Error paths are forced from the
+host (iteration limit, a negative definite matrix, b = 0), never on the GPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import formats as F
+from oracle import linalg as L
+from oracle import packsell as P
+from paper_2604_13433_amd import binding as B
+from paper_2604_13433_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def system(g=24, seed=6, sign=1.0):
+    a = W.symmetric_diag_scale(W.stencil((g, g, g), "box", seed, 1.0))
+    a = a.with_values(sign * a.val)
+    return a, W.ones_rhs(a)
+
+
+def operators(a, fmt="e8my", D=9, C=64, sigma=256):
+    hi = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float64, C, sigma, B.IMPLICIT, DEV)
+    lo = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, C, sigma, B.IMPLICIT, DEV)
+    return lo, hi
+
+
+def test_fp64_cg_matches_oracle():
+    a, b = system()
+    _, hi = operators(a)
+    x, info = B.pcg(None, hi, torch.from_numpy(b).to(DEV), tol=1e-10, max_outer=5000)
+    x = x.cpu().numpy()
+    ref = L.cg(a.rowptr, a.col, a.val, b, tol=1e-10)
+    assert info["rel_residual"] < 1e-10
+    true = np.linalg.norm(b - L.spmv(a.rowptr, a.col, a.val, x)) / np.linalg.norm(b)
+    assert true < 1e-10
+    assert np.max(np.abs(x - 1.0)) < 1e-7
+    assert np.max(np.abs(x - ref.x)) < 1e-7
+    # same arithmetic up to reduction order: iteration counts agree closely
+    assert abs(info["outer_iterations"] - ref.iterations) <= max(3, ref.iterations // 50)
+
+
+@pytest.mark.parametrize("fmt,D,m_in", [("e8my", 9, 20), ("e8my", 12, 50), ("fp16", 15, 20),
+                                        ("fix", 15, 30)])
+def test_iocg_converges(fmt, D, m_in):
+    a, b = system(20, 4)
+    lo, hi = operators(a, fmt, D)
+    x, info = B.pcg(lo, hi, torch.from_numpy(b).to(DEV), tol=1e-10, m_in=m_in, max_outer=500)
+    x = x.cpu().numpy()
+    assert info["rel_residual"] < 1e-10
+    true = np.linalg.norm(b - L.spmv(a.rowptr, a.col, a.val, x)) / np.linalg.norm(b)
+    assert true < 1e-10
+    assert np.max(np.abs(x - 1.0)) < 1e-7
+    q = P.quantized_values(a.rowptr, a.col, a.val, a.n,
+                           {"e8my": F.FMT_E8MY, "fp16": F.FMT_FP16, "fix": F.FMT_FIX}[fmt], D)
+    ref = L.iocg(a.rowptr, a.col, a.val, q, b, m_in=m_in, tol=1e-10)
+    assert ref.converged
+    # the inner solve runs in float32 on the GPU and in float64 in the
+    # oracle, so outer counts may differ slightly
+    assert abs(info["outer_iterations"] - ref.iterations) <= max(2, ref.iterations // 3)
+    assert info["inner_iterations"] <= info["outer_iterations"] * m_in
+
+
+def test_iteration_limit_reports_not_converged():
+    a, b = system(16, 5)
+    lo, hi = operators(a)
+    x, info = B.pcg(None, hi, torch.from_numpy(b).to(DEV), tol=1e-10, max_outer=3, check=False)
+    assert info["status"] == B.ENOTCONV and info["outer_iterations"] == 3
+    assert info["rel_residual"] > 1e-10
+    x, info = B.pcg(lo, hi, torch.from_numpy(b).to(DEV), tol=1e-12, m_in=2, max_outer=2,
+                    check=False)
+    assert info["status"] == B.ENOTCONV and info["outer_iterations"] == 2
+
+
+def test_breakdown_on_negative_definite():
+    a, b = system(12, 3, sign=-1.0)
+    lo, hi = operators(a)
+    _, info = B.pcg(None, hi, torch.from_numpy(b).to(DEV), tol=1e-10, max_outer=100, check=False)
+    assert info["status"] == B.EBREAKDOWN
+    _, info = B.pcg(lo, hi, torch.from_numpy(b).to(DEV), tol=1e-10, m_in=5, max_outer=100,
+                    check=False)
+    assert info["status"] == B.EBREAKDOWN
+
+
+def test_zero_rhs_and_exact_guess():
+    a, b = system(10, 2)
+    lo, hi = operators(a)
+    x, info = B.pcg(lo, hi, torch.zeros(a.n, dtype=torch.float64, device=DEV), tol=1e-10)
+    assert info["status"] == B.OK and float(x.abs().max()) == 0.0
+    x0 = torch.ones(a.n, dtype=torch.float64, device=DEV)
+    x, info = B.pcg(lo, hi, torch.from_numpy(b).to(DEV), x0=x0, tol=1e-10)
+    assert info["status"] == B.OK and info["outer_iterations"] == 0
+    assert info["rel_residual"] < 1e-10
+
+
+def test_rejects_explicit_order():
+    a, b = system(8, 2)
+    hi = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float64, 64, 256, B.EXPLICIT, DEV)
+    with pytest.raises(B.PackSELLError) as e:
+        B.pcg(None, hi, torch.from_numpy(b).to(DEV))
+    assert e.value.status == B.EINVAL
