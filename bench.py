@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+EXTRA_CHECKS = []  # (name, matrix, x, {variant: y}) checked by the CPU leg
 METRIC = "PackSELL SpMV GB/s and % HBM roofline vs FP32 SELL at stated err; PCG time-to-1e-10"
 
 
@@ -48,6 +49,14 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--only", default="", help="comma list of variants to time")
+    p.add_argument("--no-pcg", action="store_true", help="skip the solver leg")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the power-law and block-stencil legs")
+    p.add_argument("--calib-copy-mb", type=int, default=0,
+                   help="first run one plain device copy of this many MiB (a known-size "
+                        "kernel to scale hardware byte counters)")
     return p.parse_args()
 
 
@@ -109,6 +118,15 @@ def main():
 
     dev = torch.device("cuda:0")
     B.lib()  # fail loudly if the library is missing
+    if args.calib_copy_mb:
+        nbytes = args.calib_copy_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
     g = args.grid
     t0 = time.time()
     a = W.m2_laplace3d(g)
@@ -203,9 +221,189 @@ def main():
             v["speedup_vs_sell_fp32"] = round(base32["ms"] / r["ms"], 3)
         out["variants"][name] = v
 
+    if not args.no_adjoint and "packsell_fp16" in results:
+        out["adjoint"] = adjoint_leg(args, a, results["packsell_fp16"]["A"], torch, B, W)
+    out["encode_ms"] = encode_leg(a, torch, B)
+    if not args.no_extra:
+        out["powerlaw"] = powerlaw_leg(args, torch, B, W)
+        out["block3_27pt"] = block_leg(args, torch, B, W)
+    if not args.no_batched:
+        out["batched"] = batched_leg(args, torch, B, W)
+    if not args.no_pcg:
+        out["pcg"] = pcg_leg(args, torch, B, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_leg(args, a, x_np, results, H, torch)
     print(json.dumps(out), flush=True)
+
+
+def adjoint_leg(args, a, A, torch, B, W):
+    """grad_x = A^T g over the same words (atomic scatter) and the value
+    gradient, on the same matrix and replica rotation as the forward."""
+    dev = A.device
+    per = A.bytes_per_spmv()
+    R = max(2, int(math.ceil(args.replica_bytes / per)))
+    reps = [A] + [A.replicate() for _ in range(R - 1)]
+    gs = [torch.from_numpy(W.uniform_vector(a.n, 5)).to(dev) for _ in range(R)]
+    outs = [torch.empty(a.m, dtype=torch.float32, device=dev) for _ in range(R)]
+    ms = Timed(torch, lambda i: B.spmv_t(reps[i], gs[i], outs[i]), R, args.steps,
+               args.warmup).run()
+    # bytes: words + offsets + g once + the m outputs zeroed and accumulated
+    bytes_t = 4 * A.n_words + 8 * (A.desc.n_slices + 1) + 4 * a.n + 8 * a.m
+    log(f"[bench] spmv_t fp16: {ms * 1e3:.2f} us {bytes_t / (ms * 1e-3) / 1e9:.0f} GB/s")
+    return {"spmv_t_us": round(ms * 1e3, 2),
+            "spmv_t_GB/s": round(bytes_t / (ms * 1e-3) / 1e9, 1)}
+
+
+def encode_leg(a, torch, B):
+    """Wall time of the device encoder (analyse + fill) for the headline matrix."""
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(a.rowptr).to(dev)
+    cl = torch.from_numpy(a.col).to(dev)
+    vl = torch.from_numpy(a.val.astype(np.float32)).to(dev)
+    B.encode(rp, cl, vl, a.n, a.m, "fp16", 15, 64, 256, B.EXPLICIT, dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(3):
+        B.encode(rp, cl, vl, a.n, a.m, "fp16", 15, 64, 256, B.EXPLICIT, dev)
+    torch.cuda.synchronize()
+    return round((time.time() - t0) / 3 * 1e3, 2)
+
+
+def time_variant(args, torch, B, A, m, n, mk_y=None):
+    """ms per product for one PackSELL or SELL matrix with replica rotation."""
+    dev = torch.device("cuda:0")
+    per = A.bytes_per_spmv()
+    R = max(2, int(math.ceil(args.replica_bytes / per)))
+    reps = [A] + [A.replicate() for _ in range(R - 1)]
+    if isinstance(A, B.SellMatrix):
+        xs = [(torch.rand(m, device=dev, dtype=A.dtype) * 2 - 1) for _ in range(R)]
+        ys = [torch.empty(n, dtype=A.dtype, device=dev) for _ in range(R)]
+        fn = lambda i: B.sell_spmv(reps[i], xs[i], ys[i])
+    else:
+        xs = [(torch.rand(m, device=dev) * 2 - 1) for _ in range(R)]
+        ys = [torch.empty(n, device=dev) for _ in range(R)]
+        fn = lambda i: B.spmv(reps[i], xs[i], ys[i])
+    ms = Timed(torch, fn, R, min(args.steps, 200), min(args.warmup, 20)).run()
+    return ms, per, R
+
+
+def powerlaw_leg(args, torch, B, W):
+    """Irregular power-law rows, n = 10^6 (mean 30, max 5000, RSD 4.3):
+    PackSELL FP16 and E8M10 (D = 12) at sigma = 65536 against FP32 SELL."""
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    a = W.m3_powerlaw()
+    log(f"[bench] powerlaw n={a.n} nnz={a.nnz} generated in {time.time() - t0:.1f}s")
+    res = {"n": a.n, "nnz": a.nnz}
+    for name, fmt, D in [("packsell_fp16", "fp16", 15), ("packsell_e8m10", "e8my", 12)]:
+        A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 65536, B.EXPLICIT, dev)
+        ms, per, R = time_variant(args, torch, B, A, a.m, a.n)
+        res[name] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
+                     "GFLOP/s": round(2 * a.nnz / (ms * 1e-3) / 1e9, 1),
+                     "words_per_nnz": round(A.n_words / a.nnz, 3), "sigma": 65536}
+        log(f"[bench] powerlaw {name}: {res[name]}")
+        del A
+    S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 65536, B.EXPLICIT, dev)
+    ms, per, R = time_variant(args, torch, B, S, a.m, a.n)
+    res["sell_fp32"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
+                        "slots_per_nnz": round(S.n_slots / a.nnz, 3)}
+    log(f"[bench] powerlaw sell_fp32: {res['sell_fp32']}")
+    for name in ("packsell_fp16", "packsell_e8m10"):
+        res[name]["speedup_vs_sell_fp32"] = round(res["sell_fp32"]["us"] / res[name]["us"], 3)
+    return res
+
+
+def block_leg(args, torch, B, W):
+    """Extra (not one of the benchmark configs): a 3-unknown 27-point block
+    stencil on a 48^3 grid (81 nonzeros per row in runs of 9), where a tiny
+    delta field suffices -- PackSELL E8M20 (D = 2) against FP32 SELL, with
+    the backward error (eq. 5) of both against the float64 product."""
+    dev = torch.device("cuda:0")
+    a = W.block_stencil((48, 48, 48), 3, 8)
+    x = torch.from_numpy(W.uniform_vector(a.m, 9)).to(dev)
+    res = {"n": a.n, "nnz": a.nnz}
+    A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e8my", 2, 64, 256, B.IMPLICIT, dev)
+    S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 256, B.IMPLICIT, dev)
+    ms_p, per_p, _ = time_variant(args, torch, B, A, a.m, a.n)
+    ms_s, per_s, _ = time_variant(args, torch, B, S, a.m, a.n)
+    res["packsell_e8m20"] = {"us": round(ms_p * 1e3, 2), "GB/s": round(per_p / (ms_p * 1e-3) / 1e9, 1),
+                             "words": A.n_words, "dummies": A.n_dummies}
+    res["sell_fp32"] = {"us": round(ms_s * 1e3, 2), "GB/s": round(per_s / (ms_s * 1e-3) / 1e9, 1)}
+    res["speedup_vs_sell_fp32"] = round(ms_s / ms_p, 3)
+    # errors against the float64 oracle are computed in the CPU leg
+    x_np = x.cpu().numpy()
+    EXTRA_CHECKS.append(("block3_27pt", a, x_np, {"packsell_e8m20": B.spmv(A, x).cpu().numpy(),
+                                                  "sell_fp32": B.sell_spmv(S, x).cpu().numpy()}))
+    log(f"[bench] block3_27pt: {res}")
+    return res
+
+
+def batched_leg(args, torch, B, W):
+    """64 stencils (n log-uniform in [1e4, 5e5]), E8M13, k = 1, 8, 32: one
+    persistent launch over all matrices per step, replayed from a graph."""
+    dev = torch.device("cuda:0")
+    mats = W.m5_batch()
+    enc = [B.encode(m.rowptr, m.col, m.val, m.n, m.m, "e8my", 9, 64, 256, B.IMPLICIT, dev)
+           for m in mats]
+    nnz = sum(m.nnz for m in mats)
+    res = {"matrices": len(mats), "rows": sum(m.n for m in mats), "nnz": nnz,
+           "words": sum(A.n_words for A in enc)}
+    for k in (1, 8, 32):
+        per = sum(A.bytes_per_spmv(k) for A in enc)
+        R = max(1, min(4, int(math.ceil(args.replica_bytes / per))))
+        sets = [enc] + [[A.replicate() for A in enc] for _ in range(R - 1)]
+        bats = []
+        for r in range(R):
+            xs = [torch.from_numpy(W.uniform_vector(m.m, i, k=k)).to(dev) for i, m in enumerate(mats)]
+            ys = [torch.empty((m.n,) if k == 1 else (m.n, k), device=dev) for m in mats]
+            bats.append(B.BatchedSpMV(sets[r], xs, ys))
+        steps = max(R, min(args.steps, 100) // R * R)
+        ms = Timed(torch, lambda i: bats[i](), R, steps, min(args.warmup, 10)).run()
+        res[f"k{k}"] = {"us": round(ms * 1e3, 1), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
+                        "GFLOP/s": round(2 * nnz * k / (ms * 1e-3) / 1e9, 1),
+                        "bytes": per, "replicas": R}
+        log(f"[bench] batched k={k}: {ms * 1e3:.1f} us {per / (ms * 1e-3) / 1e9:.0f} GB/s")
+        del bats, sets
+    return res
+
+
+def pcg_leg(args, torch, B, W):
+    """Time to a 1e-10 relative residual on the SPD 27-point 100^3 stencil
+    (lognormal(0, 1) edges, symmetrically scaled, b = A 1, x0 = 0): float64
+    CG against the inner-outer CG with PackSELL E8MY inner products."""
+    dev = torch.device("cuda:0")
+    a = W.symmetric_diag_scale(W.m4_stencil27())
+    b = torch.from_numpy(W.ones_rhs(a)).to(dev)
+    hi = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float64, 64, 256, B.IMPLICIT, dev)
+    res = {"workload": "stencil27 100^3 lognormal(0,1), Gbar^-1 A Gbar^-1, b = A 1, tol 1e-10",
+           "n": a.n, "nnz": a.nnz}
+
+    def run(lo, m_in, reps=3):
+        times, info = [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            x, info = B.pcg(lo, hi, b, tol=1e-10, m_in=m_in, max_outer=20000)
+            times.append(info["seconds"])
+        err = float((x - 1.0).abs().max())
+        return dict(ms=round(1e3 * sorted(times)[len(times) // 2], 2),
+                    iterations=info["outer_iterations"], inner=info["inner_iterations"],
+                    rel_residual=info["rel_residual"], max_abs_err_vs_ones=err)
+
+    res["fp64_cg"] = run(None, 0)
+    log(f"[bench] fp64 CG: {res['fp64_cg']}")
+    best = None
+    for D in (9, 12):
+        lo = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e8my", D, 64, 256, B.IMPLICIT, dev)
+        for m_in in (20, 50):
+            r = run(lo, m_in)
+            r["speedup_vs_fp64_cg"] = round(res["fp64_cg"]["ms"] / r["ms"], 3)
+            res[f"iocg_e8m{22 - D}_min{m_in}"] = r
+            log(f"[bench] IO-CG E8M{22 - D} m_in={m_in}: {r}")
+            if best is None or r["ms"] < best[1]["ms"]:
+                best = (f"iocg_e8m{22 - D}_min{m_in}", r)
+    res["best"] = best[0]
+    res["best_speedup_vs_fp64_cg"] = best[1]["speedup_vs_fp64_cg"]
+    return res
 
 
 def cpu_leg(args, a, x_np, results, H, torch):
@@ -253,6 +451,12 @@ def cpu_leg(args, a, x_np, results, H, torch):
             den = L.inf_norm(a.rowptr, vals) * np.abs(x_np).max()
             errors[name] = {"vs_oracle_same_values": float(np.abs(y - ref).max() / den),
                             "backward_error_eq5": float(np.abs(y - full).max() / den)}
+    for name, m, xx, ys in EXTRA_CHECKS:
+        xd = xx.astype(np.float64)
+        full = L.spmv(m.rowptr, m.col, m.val, xd)
+        den = L.inf_norm(m.rowptr, m.val) * np.abs(xd).max()
+        for var, y in ys.items():
+            errors[f"{name}.{var}"] = {"backward_error_eq5": float(np.abs(y - full).max() / den)}
     return {"value": round(H["bytes"] / dt / 1e9, 2), "unit": "GB/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{reps} full float64 CSR SpMVs of the same matrix on the host "

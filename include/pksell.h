@@ -169,11 +169,14 @@ int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k,
 int pksell_spmv_t(const pksell_matrix *A, const float *g, float *y,
                   int64_t k, void *stream);
 
-/* grad[e] = g_i * x_j for every stored nonzero e = (i, j) of the CSR matrix
- * the words were encoded from, in that CSR's order (rowptr int64[n+1] of the
- * ORIGINAL matrix).  g (n) in pksell_spmv's row order, x (m).  k = 1. */
+/* Gradient of <g, A x> with respect to every stored value:
+ * grad[e] = sum_s g[i, s] * x[j, s] for each stored nonzero e = (i, j) of the
+ * CSR matrix the words were encoded from, in that CSR's order (rowptr
+ * int64[n+1] of the ORIGINAL matrix; quantisation is treated as the
+ * identity).  g (n x k) in pksell_spmv's row order, x (m x k), row-major.
+ * Needs A->perm (the stored-to-original row map) in both modes. */
 int pksell_grad_values(const pksell_matrix *A, const int64_t *rowptr,
-                       const float *g, const float *x, float *grad,
+                       const float *g, const float *x, float *grad, int64_t k,
                        void *stream);
 
 /* Decodes every word position: cols[p] = column reconstructed at word p
@@ -201,6 +204,46 @@ int pksell_sell_encode(const int64_t *rowptr, const int32_t *col,
 /* y = S x in S->dtype (x: m, y: n, of S->dtype), accumulated in S->dtype. */
 int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y,
                      void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched products: many PackSELL matrices (uneven sizes, one value format,
+ * C = 64, each with its own D) and k right-hand sides in one persistent
+ * launch.  Not in the paper; the per-matrix arithmetic is pksell_spmv's.
+ * ---------------------------------------------------------------------- */
+
+/* One matrix of a batch: A (host pointer to its descriptor) and its input
+ * and output blocks (device, row-major).  Forward: in = x (m x k),
+ * out = y (n x k).  Transposed: in = g (n x k), out = A^T g (m x k). */
+typedef struct pksell_batch_item {
+  const pksell_matrix *A;
+  const float *in;
+  float *out;
+} pksell_batch_item;
+
+/* A batch plan (host struct; ``items`` and ``unit_start`` point into the
+ * plan workspace on the device). */
+typedef struct pksell_batch {
+  int32_t count, fmt, k, transpose;
+  int64_t total_units;      /* slices over all matrices */
+  int32_t units_per_wave, waves;
+  void *items;
+  void *unit_start;
+} pksell_batch;
+
+/* Device workspace bytes of a plan for ``count`` matrices (host call). */
+int pksell_batch_plan_bytes(int32_t count, size_t *bytes);
+
+/* Validates the items and writes the plan's device table into ``ws`` (which
+ * must stay alive and unchanged while the plan is used); SYNCHRONISES once.
+ * transpose != 0 plans out = A^T in. */
+int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
+                      int32_t transpose, pksell_batch *plan, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Runs a plan: one persistent launch per pass of up to 32 right-hand sides
+ * (a transposed plan first zeroes its outputs with a kernel, then scatters
+ * with float32 atomics).  Asynchronous, and safe to capture in a graph. */
+int pksell_spmv_batched(const pksell_batch *plan, void *stream);
 
 /* ------------------------------------------------------------------------
  * Solvers (sec. 5.2): A x = b with ||b - A x||_2 / ||b||_2 < tol (eq. 6).

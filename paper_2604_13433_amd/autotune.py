@@ -1,0 +1,111 @@
+"""Autotuner for PackSELL parameters: delta width D (the delta/value bit
+split), slice height C and window sigma.
+
+Model first, measurement second.  The encoder's analyse phase alone gives
+the exact stored-word count (nonzeros + dummies + padding) of every
+candidate, so the algorithmic bytes of one product are known without
+building any words.  The product is bandwidth-bound, so the cheapest few
+candidates by bytes are then encoded and timed on the GPU (HIP events over
+graph replays), and the fastest wins.  Precision is a constraint, not a
+goal: E8MY candidates keep at least ``min_mantissa`` mantissa bits
+(Y = 22 - D), FIX at least ``min_mantissa`` value bits.
+
+Results are cached in a JSON file keyed by a hash of the sparsity pattern
+and the request.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+DEFAULT_C = (32, 64)
+DEFAULT_SIGMA = (64, 256, 1024, 8192, 65536)
+
+
+def signature(rowptr, col, n: int, m: int, fmt: str, min_mantissa: int, k: int) -> str:
+    h = hashlib.blake2b(digest_size=16)
+    h.update(np.asarray(rowptr, np.int64).tobytes())
+    h.update(np.asarray(col, np.int32).tobytes())
+    h.update(f"{n},{m},{fmt},{min_mantissa},{k}".encode())
+    return h.hexdigest()
+
+
+def d_candidates(fmt: str, min_mantissa: int):
+    if fmt == "fp16":
+        return [15]
+    if fmt == "e8my":
+        return list(range(1, 22 - min_mantissa + 1))
+    if fmt == "fix":
+        return list(range(1, 31 - min_mantissa + 1))
+    raise ValueError(fmt)
+
+
+def _time_spmv(A, x, y, reps=50):
+    for _ in range(3):
+        B.spmv(A, x, y)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(10):
+            B.spmv(A, x, y)
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps // 10):
+        g.replay()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / (reps // 10 * 10)
+
+
+def tune(rowptr, col, val, n: int, m: int, fmt: str = "e8my", min_mantissa: int = 13,
+         perm_mode: int = B.IMPLICIT, k: int = 1, C_list=DEFAULT_C, sigma_list=DEFAULT_SIGMA,
+         time_top: int = 3, cache_path: str | None = None, device="cuda") -> dict:
+    """Returns {"fmt", "D", "C", "sigma", "bytes", "us", "candidates": [...]}."""
+    key = signature(rowptr, col, n, m, fmt, min_mantissa, k)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return cache[key]
+    device = torch.device(device)
+    rp = torch.as_tensor(np.asarray(rowptr, np.int64)).to(device)
+    cl = torch.as_tensor(np.asarray(col, np.int32)).to(device)
+    vl = torch.as_tensor(np.asarray(val, np.float32)).to(device)
+    cands = []
+    for D in d_candidates(fmt, min_mantissa):
+        for C in C_list:
+            for sigma in sigma_list:
+                if sigma < C:
+                    continue
+                A = B.encode(rp, cl, vl, n, m, fmt, D, C, sigma, perm_mode, device,
+                             analyse_only=True)
+                cands.append(dict(D=D, C=C, sigma=sigma, words=int(A.n_words),
+                                  dummies=int(A.n_dummies), bytes=A.bytes_per_spmv(k)))
+    cands.sort(key=lambda c: (c["bytes"], -c["C"], c["sigma"]))
+    x = torch.rand((m,) if k == 1 else (m, k), device=device) * 2 - 1
+    y = torch.empty((n,) if k == 1 else (n, k), device=device)
+    for c in cands[:time_top]:
+        A = B.encode(rp, cl, vl, n, m, fmt, c["D"], c["C"], c["sigma"], perm_mode, device)
+        c["us"] = round(_time_spmv(A, x, y) * 1e3, 3)
+        del A
+    timed = [c for c in cands if "us" in c]
+    best = min(timed, key=lambda c: c["us"])
+    out = dict(fmt=fmt, D=best["D"], C=best["C"], sigma=best["sigma"], bytes=best["bytes"],
+               us=best["us"], min_mantissa=min_mantissa, k=k, candidates=cands[: max(10, time_top)])
+    if cache_path:
+        cache[key] = out
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f)
+        os.replace(tmp, cache_path)
+    return out

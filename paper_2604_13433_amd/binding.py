@@ -47,6 +47,16 @@ class CSell(ctypes.Structure):
                 ("offset", vp), ("perm", vp), ("col", vp), ("val", vp)]
 
 
+class CBatchItem(ctypes.Structure):
+    _fields_ = [("A", ctypes.POINTER(CMatrix)), ("inp", vp), ("out", vp)]
+
+
+class CBatch(ctypes.Structure):
+    _fields_ = [("count", i32), ("fmt", i32), ("k", i32), ("transpose", i32),
+                ("total_units", i64), ("units_per_wave", i32), ("waves", i32),
+                ("items", vp), ("unit_start", vp)]
+
+
 class CPcgInfo(ctypes.Structure):
     _fields_ = [("outer_iterations", i32), ("inner_iterations", i32),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
@@ -63,7 +73,7 @@ _PROTOS = {
     "pksell_encode": ([vp, vp, vp, i32, ctypes.POINTER(CMatrix), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "pksell_spmv": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
     "pksell_spmv_t": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
-    "pksell_grad_values": ([ctypes.POINTER(CMatrix), vp, vp, vp, vp, vp], ctypes.c_int),
+    "pksell_grad_values": ([ctypes.POINTER(CMatrix), vp, vp, vp, vp, i64, vp], ctypes.c_int),
     "pksell_decode": ([ctypes.POINTER(CMatrix), vp, vp, vp], ctypes.c_int),
     "pksell_sell_query": ([i64, i64, i64, i32, i32, i32, i32,
                            ctypes.POINTER(CSell), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -72,6 +82,10 @@ _PROTOS = {
 }
 
 _PROTOS.update({
+    "pksell_batch_plan_bytes": ([i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pksell_batch_plan": ([ctypes.POINTER(CBatchItem), i32, i64, i32, ctypes.POINTER(CBatch), vp,
+                           ctypes.c_size_t, vp], ctypes.c_int),
+    "pksell_spmv_batched": ([ctypes.POINTER(CBatch), vp], ctypes.c_int),
     "pksell_pcg_workspace": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CSell),
                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_pcg": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CSell), vp, vp, ctypes.c_double,
@@ -191,8 +205,10 @@ class PackSELLMatrix:
 
 def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 64,
            sigma: int = 256, perm_mode: int = IMPLICIT, device="cuda",
-           keep_perm: bool = True) -> PackSELLMatrix:
-    """CSR (numpy or torch; values float32 or float64) -> PackSELL on the GPU."""
+           keep_perm: bool = True, analyse_only: bool = False) -> PackSELLMatrix:
+    """CSR (numpy or torch; values float32 or float64) -> PackSELL on the GPU.
+    With ``analyse_only`` only the analyse phase runs: the descriptor then
+    holds n_words, n_dummies and k_left, and no words are written."""
     if isinstance(fmt, str):
         fmt = FMT_BY_NAME[fmt]
     device = torch.device(device)
@@ -219,6 +235,8 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
     vcode = F64 if vdt == torch.float64 else F32
     _check(L.pksell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
                            _ptr(ws), ws_bytes.value, st))
+    if analyse_only:
+        return A
     t["pack"] = torch.empty(max(1, desc.n_words), dtype=torch.int32, device=device)
     if fmt == FIX:
         t["row_exp"] = torch.empty(max(1, n), dtype=torch.int16, device=device)
@@ -251,11 +269,14 @@ def spmv_t(A: PackSELLMatrix, g: torch.Tensor, y: torch.Tensor | None = None) ->
 
 def grad_values(A: PackSELLMatrix, rowptr: torch.Tensor, g: torch.Tensor,
                 x: torch.Tensor) -> torch.Tensor:
-    """g_i * x_j at every stored nonzero, in the CSR order of ``rowptr``."""
+    """sum_s g[i, s] x[j, s] at every stored nonzero, in the CSR order of
+    ``rowptr`` (g: n or n x k, x: m or m x k)."""
+    k = 1 if g.dim() == 1 else g.shape[1]
+    assert g.is_contiguous() and x.is_contiguous() and x.shape[0] == A.m
     out = torch.empty(max(1, A.nnz), dtype=torch.float32, device=g.device)
     rp = _dev(rowptr, torch.int64, g.device)
     _check(lib().pksell_grad_values(ctypes.byref(A.desc), _ptr(rp), _ptr(g), _ptr(x),
-                                    _ptr(out), _stream(g.device)))
+                                    _ptr(out), k, _stream(g.device)))
     return out[:A.nnz]
 
 
@@ -371,3 +392,51 @@ def pcg(A_lo: PackSELLMatrix | None, A_hi: SellMatrix, b: torch.Tensor,
     if check and st not in (OK,):
         raise PackSELLError(st, L.pksell_last_error().decode())
     return x, out
+
+
+class BatchedSpMV:
+    """Y_b = A_b X_b (or A_b^T G_b with ``transpose``) for a list of PackSELL
+    matrices in one persistent launch; ``capture()`` records the launch in
+    a HIP graph that ``replay()`` re-runs with the same buffers."""
+
+    def __init__(self, mats: list, inputs: list, outputs: list, transpose: bool = False):
+        assert len(mats) == len(inputs) == len(outputs) and mats
+        self.mats, self.inputs, self.outputs = mats, inputs, outputs
+        k = 1 if inputs[0].dim() == 1 else inputs[0].shape[1]
+        dev = inputs[0].device
+        arr = (CBatchItem * len(mats))()
+        for i, (A, x, y) in enumerate(zip(mats, inputs, outputs)):
+            assert x.dtype == torch.float32 and y.dtype == torch.float32
+            assert x.is_contiguous() and y.is_contiguous()
+            kk = 1 if x.dim() == 1 else x.shape[1]
+            assert kk == k, "every item needs the same k"
+            arr[i].A = ctypes.pointer(A.desc)
+            arr[i].inp = x.data_ptr()
+            arr[i].out = y.data_ptr()
+        self._arr = arr
+        nbytes = ctypes.c_size_t()
+        L = lib()
+        _check(L.pksell_batch_plan_bytes(len(mats), ctypes.byref(nbytes)))
+        self.ws = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=dev)
+        self.plan = CBatch()
+        _check(L.pksell_batch_plan(arr, len(mats), k, 1 if transpose else 0,
+                                   ctypes.byref(self.plan), _ptr(self.ws), nbytes.value,
+                                   _stream(dev)))
+        self.device = dev
+        self.graph = None
+
+    def __call__(self):
+        _check(lib().pksell_spmv_batched(ctypes.byref(self.plan), _stream(self.device)))
+        return self.outputs
+
+    def capture(self):
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self()
+        self.graph = g
+        return self
+
+    def replay(self):
+        self.graph.replay()
+        return self.outputs

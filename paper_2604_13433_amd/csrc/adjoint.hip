@@ -59,7 +59,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_t(AdjArgs a, bool implicit, con
   }
 }
 
-// grad[rowptr[r] + q] = g_r * x_c for the q-th flag-1 word of original row r.
+// grad[rowptr[r] + q] = sum over right-hand sides s of g[r, s] * x[c, s]
+// for the q-th flag-1 word of original row r (column c).
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_grad_values(AdjArgs a, bool implicit,
                                                         const int64_t *__restrict__ rowptr,
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_values(AdjArgs a, bool implicit
   const int64_t s = a.offset[k];
   const int64_t w = (a.offset[k + 1] - s) / a.C;
   const int64_t r = orig_row(a, t);
-  const float gr = g[implicit ? r : t];
+  const float *gr = g + (implicit ? r : t) * a.k;
   int64_t e = rowptr[r];
   uint32_t c = left_offset(t, a.sigma, a.k_left);
   const uint32_t *P = a.pack + s + l;
@@ -81,7 +82,12 @@ __global__ __launch_bounds__(kBlock) void k_grad_values(AdjArgs a, bool implicit
     const uint32_t p = P[j * a.C];
     Unpacked u = unpack(p, a.cd);
     c += u.delta;
-    if (p & 1u) grad[e++] = gr * x[c];
+    if (p & 1u) {
+      const float *xc = x + (int64_t)c * a.k;
+      float acc = gr[0] * xc[0];
+      for (int q = 1; q < a.k; ++q) acc = fmaf(gr[q], xc[q], acc);
+      grad[e++] = acc;
+    }
   }
 }
 
@@ -132,15 +138,16 @@ int pksell_spmv_t(const pksell_matrix *A, const float *g, float *y, int64_t k, v
 }
 
 int pksell_grad_values(const pksell_matrix *A, const int64_t *rowptr, const float *g,
-                       const float *x, float *grad, void *stream) {
+                       const float *x, float *grad, int64_t k, void *stream) {
   int rc = check_matrix_public(A);
   if (rc) return rc;
+  PKS_CHECK(k >= 1 && k <= 64, PKSELL_EINVAL, "k must be in [1, 64]");
   PKS_CHECK(A->n == 0 || A->perm, PKSELL_EINVAL,
             "grad_values needs perm (the stored-to-original row map) in both modes");
   PKS_CHECK(A->nnz == 0 || (rowptr && g && x && grad), PKSELL_EINVAL, "null argument");
   if (A->nnz == 0) return PKSELL_OK;
   hipStream_t st = as_stream(stream);
-  AdjArgs a = make_adj(A, 1);
+  AdjArgs a = make_adj(A, k);
   const bool implicit = A->perm_mode == PKSELL_IMPLICIT;
   const int64_t grid = cdiv(A->n, kBlock);
   switch (A->fmt) {

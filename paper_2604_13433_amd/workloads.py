@@ -190,6 +190,31 @@ def stencil(dims, kind: str, seed: int | None, ln_sigma: float = 0.5,
     return CSR(n, n, rowptr, cols[mask].astype(np.int32), vals[mask], name)
 
 
+def block_stencil(dims, dof: int, seed: int, name: str = "") -> CSR:
+    """Vector (``dof`` unknowns per grid point) 27-point stencil: every
+    unknown couples to all ``dof`` unknowns of each of its 27 neighbours
+    (itself included), so a row holds up to 27 * dof entries in runs of
+    3 * dof consecutive columns (unknowns numbered point-major).  Values are
+    N(0, 1) with a dominant positive diagonal, then row-sum scaled.  A
+    high-locality pattern of the kind the paper credits for small-D gains
+    (sec. 5.1.2); an extra workload, not one of the five benchmark configs."""
+    g = stencil(dims, "box", seed=None)
+    rng = np.random.default_rng(seed)
+    rows_p = g.rows()
+    cols_p = g.col.astype(np.int64)
+    # every point entry (p, q) becomes the dof x dof block (p*dof+a, q*dof+b)
+    blk_a = np.arange(dof)[None, :, None]
+    blk_b = np.arange(dof)[None, None, :]
+    rr = np.broadcast_to(rows_p[:, None, None] * dof + blk_a, (rows_p.size, dof, dof)).reshape(-1)
+    cc = np.broadcast_to(cols_p[:, None, None] * dof + blk_b, (rows_p.size, dof, dof)).reshape(-1)
+    vals = rng.standard_normal(rr.size)
+    diag = rr == cc
+    vals[diag] = np.abs(vals[diag]) + 27 * dof
+    n = g.n * dof
+    a = csr_from_triplets(n, n, rr, cc, vals, name or f"block{dof}_27pt")
+    return row_sum_scale(a)
+
+
 def poisson2d(g: int) -> CSR:
     """2D 5-point Poisson on a g x g grid: diagonal 4, off-diagonals -1."""
     a = stencil((g, g), "star", seed=None, name=f"poisson2d_{g}")
@@ -239,7 +264,7 @@ def _sample_distinct(lo, size, k, rng):
         rr = np.repeat(rows, sz)
         off = np.arange(rr.size) - np.repeat(np.cumsum(sz) - sz, sz)
         pri = rng.random(rr.size)
-        order = np.lexsort((pri, rr))
+        order = np.argsort(rr + pri, kind="stable")  # by row, then priority
         rr, off = rr[order], off[order]
         start = np.cumsum(sz) - sz
         kk = k[rows]
@@ -256,7 +281,7 @@ def _sample_distinct(lo, size, k, rng):
         key, first = np.unique(key, return_index=True)
         rr, vv = rr[first], vv[first]
         pri = rng.random(rr.size)
-        order = np.lexsort((pri, rr))
+        order = np.argsort(rr + pri, kind="stable")  # by row, then priority
         rr, vv = rr[order], vv[order]
         starts = np.searchsorted(rr, todo)
         ends = np.searchsorted(rr, todo, side="right")

@@ -226,3 +226,23 @@ def test_float64_input_rounds_through_float32():
     assert int(words(A)[0]) >> 16 == 0x3C00
     A, E = both(a, "e8my", 13, 64, 256)
     assert_same_encoding(A, E)
+
+
+@pytest.mark.parametrize("fmt,D,C,sigma", [("fp16", 15, 64, 4096), ("e8my", 12, 64, 65536),
+                                           ("e8my", 2, 32, 256), ("fix", 15, 64, 1024)])
+def test_powerlaw_parity(fmt, D, C, sigma):
+    """Irregular power-law rows (the high-RSD regime): n = 200,000."""
+    a = W.powerlaw(200_000, seed=4)
+    x = W.uniform_vector(a.m, 5)
+    A, E = both(a, fmt, D, C, sigma)
+    assert_same_encoding(A, E)
+    check_spmv(A, a, fmt, D, x, B.IMPLICIT, E)
+
+
+def test_m3_powerlaw_full_size():
+    """n = 1,000,000 power-law rows (mean 30, max 5000), FP16, sigma = 65536."""
+    a = W.m3_powerlaw()
+    x = W.uniform_vector(a.m, 5)
+    A, E = both(a, "fp16", 15, 64, 65536)
+    assert_same_encoding(A, E)
+    check_spmv(A, a, "fp16", 15, x, B.IMPLICIT, E)
