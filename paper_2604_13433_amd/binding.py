@@ -169,7 +169,9 @@ class PackSELLMatrix:
         p = self.t.get("perm")
         if p is None:
             return None
-        return p.view(torch.uint8) if self.desc.perm_bytes == 1 else p.view(torch.int16)
+        if self.desc.perm_bytes == 1:
+            return p.view(torch.uint8)
+        return p.view(torch.int16).to(torch.int32) & 0xFFFF  # unsigned 16-bit values
 
     @property
     def row_exp(self):

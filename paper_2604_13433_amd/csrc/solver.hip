@@ -7,11 +7,17 @@
 //
 // One CG iteration is two kernels: (A) the product q = A p, where p is
 // formed on the fly as r + beta * p_old at every gathered column and
-// written once by its row's lane (two p buffers alternate), fused with the
-// p.q reduction and alpha; (B) the vector updates fused with the r.r
-// reduction, beta and the convergence flag.  Reductions finish in the last
-// workgroup to arrive, summing per-workgroup partials in a fixed order, so
-// results do not depend on scheduling.
+// written once by its row's lane (two p buffers alternate), writing the
+// workgroup partial sums of p.q; (B) the vector updates, writing the
+// partial sums of r.r.  There is no communication between workgroups inside
+// a kernel: every workgroup of the next kernel sums the previous kernel's
+// partials itself, in one fixed order, so all of them reach the same alpha,
+// beta and stopping decision (deterministically), and workgroup 0 records
+// the scalars for the next kernels and the host.  Partial buffers alternate
+// so a kernel never overwrites the partials its own workgroups are still
+// reading, and no kernel reads a state field it writes (workgroups start at
+// different times) unless every workgroup would reach the same outcome
+// either way.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -23,15 +29,25 @@ namespace pksell {
 namespace {
 
 constexpr int kB = kRowBlock;
-constexpr uint32_t kVecBlocks = 1024;
+constexpr uint32_t kVecBlocks = 512;
 
 struct State {
-  double rr, bnorm2, tol2, alpha, beta;  // outer / plain-CG scalars
-  double pq_prev, beta_o, nr;            // flexible CG
-  double in_rr, in_alpha, in_beta;       // inner CG
+  double rr;        // r.r of the outer residual (host-visible)
+  double rr0;       // r.r at a (re)start: read by the first CG step
+  double rr_cur;    // r.r the current CG step works with (written by step A)
+  double rr_used;   // r.r of the last CG update (alpha's numerator, beta's denominator)
+  double bnorm2, tol2, alpha, beta;
+  double pq_prev, beta_o, nr;                  // flexible CG
+  double in_rr_cur, in_rr_used, in_alpha, in_beta;  // inner CG
   int32_t done, breakdown, inner_stop, iters, inner_iters, max_iters;
-  uint32_t counter;
-  int32_t pad;
+  int32_t first, in_first;     // the next step starts a fresh direction
+  int32_t step_ok, in_step_ok;  // step A ran, so step B must run
+};
+
+// A set of per-workgroup partial sums: slot q of workgroup b at q * count + b.
+struct Parts {
+  double *p;
+  uint32_t count;
 };
 
 // ---- reductions -----------------------------------------------------------------
@@ -46,52 +62,34 @@ __device__ inline void block_sum(double (&v)[NV]) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) sh[q][w] = v[q];
   __syncthreads();
-  if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      double s = 0.0;
-      for (int i = 0; i < kB / kWave; ++i) s += sh[q][i];
-      v[q] = s;
-    }
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+    for (int i = 0; i < kB / kWave; ++i) s += sh[q][i];
+    v[q] = s;  // every thread holds the total
+  }
   __syncthreads();
 }
 
-// Adds this workgroup's partial sums; returns true in the last workgroup to
-// arrive, whose thread 0 then holds the totals in ``tot``.
+// Writes this workgroup's partial sums.
 template <int NV>
-__device__ inline bool reduce_last(double (&v)[NV], double *partials, State *st,
-                                   double (&tot)[NV]) {
-  __shared__ int amlast;
-  const uint32_t nb = gridDim.x;
+__device__ inline void put_partials(double (&v)[NV], Parts out) {
   block_sum(v);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
-      __hip_atomic_store(&partials[q * nb + blockIdx.x], v[q], __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    uint32_t prev =
-        __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    amlast = prev == nb - 1;
-  }
-  __syncthreads();
-  if (!amlast) return false;
-  __threadfence();
-  double acc[NV];
+    for (int q = 0; q < NV; ++q) out.p[q * out.count + blockIdx.x] = v[q];
+}
+
+// Sums a previous kernel's partials; every thread of every workgroup gets the
+// same totals (same order of additions everywhere).
+template <int NV>
+__device__ inline void get_totals(Parts in, double (&tot)[NV]) {
 #pragma unroll
-  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-  for (uint32_t i = threadIdx.x; i < nb; i += kB)
+  for (int q = 0; q < NV; ++q) tot[q] = 0.0;
+  for (uint32_t i = threadIdx.x; i < in.count; i += kB)
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
-      acc[q] += __hip_atomic_load(&partials[q * nb + i], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  block_sum(acc);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) tot[q] = acc[q];
-    __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  return true;
+    for (int q = 0; q < NV; ++q) tot[q] += in.p[q * in.count + i];
+  block_sum(tot);
 }
 
 __device__ inline bool outer_stopped(const State *st) {
@@ -145,27 +143,40 @@ __device__ inline double sell_row(const SellView &S, const Lane &ln, uint32_t st
 
 // ---- CG kernels -----------------------------------------------------------------
 
-// (A) float32 inner step on PackSELL: p_new = r + beta p_old, q = A_q p_new,
-// p_new . q -> alpha = rr / pq (inner_stop on breakdown).
+// (A) float32 inner step on PackSELL.  Totals of the previous r.r give
+// beta (0 on the first inner step); then p_new = r + beta p_old, q = A_q
+// p_new, and the partials of p_new . q.
 template <int FMT, bool CWAVE>
 __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restrict__ r,
                                                const float *__restrict__ p_old,
                                                float *__restrict__ p_new, float *__restrict__ q,
-                                               State *st, double *partials) {
-  if (outer_stopped(st) || st->inner_stop) return;
-  const float beta = (float)st->in_beta;
+                                               State *st, Parts rr_in, Parts pq_out) {
+  const bool stop = outer_stopped(st) || st->inner_stop;
+  const bool first = st->in_first;
+  double rr[1] = {0.0};
+  if (!stop) get_totals(rr_in, rr);
+  const double beta_d = first ? 0.0 : rr[0] / st->in_rr_used;
+  const bool quit = !stop && !(rr[0] > 0.0 && isfinite(beta_d));  // inner residual vanished
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->in_step_ok = !(stop || quit);
+    if (quit) st->inner_stop = 1;
+    st->in_rr_cur = rr[0];
+    st->in_beta = beta_d;
+  }
+  if (stop || quit) return;
+  const float beta = (float)beta_d;
   Lane ln;
   const bool live = lane_slice<CWAVE>(A.offset, A.n_slices, A.geo, ln);
   double part = 0.0;
   if (live) {
-    const __amdgpu_buffer_rsrc_t rr = make_rsrc(r, A.n * 4u);
+    const __amdgpu_buffer_rsrc_t rr_r = make_rsrc(r, A.n * 4u);
     const __amdgpu_buffer_rsrc_t rp = make_rsrc(p_old, A.n * 4u);
     float acc[1] = {0.0f};
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)A.C;
     packsell_row<FMT, 1>(A.pack + ln.s + ln.l, stride, ln.w, left_offset32(ln.t, A.geo), A.cd,
                          [&](uint32_t c, int) {
                            return fmaf(beta, buffer_load_f32(rp, c << 2),
-                                       buffer_load_f32(rr, c << 2));
+                                       buffer_load_f32(rr_r, c << 2));
                          },
                          acc);
     if (ln.t < A.n) {
@@ -178,22 +189,26 @@ __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restr
       part = (double)pn * (double)qi;
     }
   }
-  double v[1] = {part}, tot[1];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
-    if (tot[0] > 0.0 && isfinite(tot[0]))
-      st->in_alpha = st->in_rr / tot[0];
-    else
-      st->inner_stop = 1;
-  }
+  double v[1] = {part};
+  put_partials(v, pq_out);
 }
 
-// (B) float32 inner update: z += alpha p, r -= alpha q, rr -> beta.
+// (B) float32 inner update: alpha = rr / pq; z += alpha p, r -= alpha q;
+// partials of the new r.r.
 __global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ z,
                                                float *__restrict__ r, const float *__restrict__ p,
                                                const float *__restrict__ q, State *st,
-                                               double *partials) {
-  if (outer_stopped(st) || st->inner_stop) return;
-  const float alpha = (float)st->in_alpha;
+                                               Parts pq_in, Parts rr_out) {
+  if (!st->in_step_ok) return;
+  double pq[1];
+  get_totals(pq_in, pq);
+  if (!(pq[0] > 0.0 && isfinite(pq[0]))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->inner_stop = 1;
+    return;
+  }
+  const double rr = st->in_rr_cur;
+  const double alpha_d = rr / pq[0];
+  const float alpha = (float)alpha_d;
   double part = 0.0;
   for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
     z[i] = fmaf(alpha, p[i], z[i]);
@@ -201,26 +216,41 @@ __global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ 
     r[i] = ri;
     part += (double)ri * (double)ri;
   }
-  double v[1] = {part}, tot[1];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+  double v[1] = {part};
+  put_partials(v, rr_out);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->in_rr_used = rr;
+    st->in_alpha = alpha_d;
     st->inner_iters += 1;
-    if (tot[0] > 0.0 && isfinite(tot[0])) {
-      st->in_beta = tot[0] / st->in_rr;
-      st->in_rr = tot[0];
-    } else {
-      st->inner_stop = 1;
-    }
+    st->in_first = 0;
   }
 }
 
-// (A) float64 CG step on SELL: p_new = r + beta p_old, q = A p_new, alpha.
+// (A) float64 CG step on SELL.  The current r.r (st->rr0 on a fresh start,
+// else the totals of the previous update's partials) gives the stopping
+// test and beta; then p_new = r + beta p_old, q = A p_new, partials of
+// p_new . q.
 template <bool CWAVE>
 __global__ __launch_bounds__(kB) void k_cg_a(SellView S, const double *__restrict__ r,
                                             const double *__restrict__ p_old,
                                             double *__restrict__ p_new, double *__restrict__ q,
-                                            State *st, double *partials) {
-  if (outer_stopped(st)) return;
-  const double beta = st->beta;
+                                            State *st, Parts rr_in, Parts pq_out) {
+  const bool stop = outer_stopped(st);
+  const bool first = st->first;
+  double rr[1] = {st->rr0};
+  if (!stop && !first) get_totals(rr_in, rr);
+  const bool conv = !stop && !(rr[0] >= st->tol2);  // converged (or NaN)
+  const double beta = first ? 0.0 : rr[0] / st->rr_used;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->step_ok = !(stop || conv);
+    st->rr_cur = rr[0];
+    st->beta = beta;
+    if (conv) {
+      st->rr = rr[0];
+      st->done = 1;  // every workgroup takes the same exit
+    }
+  }
+  if (stop || conv) return;
   Lane ln;
   const bool live = lane_slice<CWAVE>(S.offset, S.n_slices, S.geo, ln);
   double part = 0.0;
@@ -235,24 +265,28 @@ __global__ __launch_bounds__(kB) void k_cg_a(SellView S, const double *__restric
       part = pn * qi;
     }
   }
-  double v[1] = {part}, tot[1];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
-    if (tot[0] > 0.0 && isfinite(tot[0])) {
-      st->alpha = st->rr / tot[0];
-    } else {
+  double v[1] = {part};
+  put_partials(v, pq_out);
+}
+
+// (B) float64 CG update: alpha = rr / pq, x += alpha p, r -= alpha q;
+// partials of the new r.r.
+__global__ __launch_bounds__(kB) void k_cg_b(uint32_t n, double *__restrict__ x,
+                                            double *__restrict__ r, const double *__restrict__ p,
+                                            const double *__restrict__ q, State *st, Parts pq_in,
+                                            Parts rr_out) {
+  if (!st->step_ok) return;
+  double pq[1];
+  get_totals(pq_in, pq);
+  if (!(pq[0] > 0.0 && isfinite(pq[0]))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->breakdown = 1;
       st->done = 1;
     }
+    return;
   }
-}
-
-// (B) float64 CG update: x += alpha p, r -= alpha q, rr -> beta, converged?
-__global__ __launch_bounds__(kB) void k_cg_b(uint32_t n, double *__restrict__ x,
-                                            double *__restrict__ r, const double *__restrict__ p,
-                                            const double *__restrict__ q, State *st,
-                                            double *partials) {
-  if (outer_stopped(st)) return;
-  const double alpha = st->alpha;
+  const double rr = st->rr_cur;
+  const double alpha = rr / pq[0];
   double part = 0.0;
   for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
     x[i] = fma(alpha, p[i], x[i]);
@@ -260,37 +294,28 @@ __global__ __launch_bounds__(kB) void k_cg_b(uint32_t n, double *__restrict__ x,
     r[i] = ri;
     part += ri * ri;
   }
-  double v[1] = {part}, tot[1];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
+  double v[1] = {part};
+  put_partials(v, rr_out);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rr_used = rr;
+    st->alpha = alpha;
     st->iters += 1;
-    st->beta = tot[0] / st->rr;
-    st->rr = tot[0];
-    if (!(tot[0] >= st->tol2)) st->done = 1;  // also stops on NaN
+    st->first = 0;
   }
 }
 
 // ---- flexible-CG outer kernels (sec. 5.2.2) -----------------------------------
 
-// nr = ||r||: the inner right-hand side is r / nr.
-__global__ __launch_bounds__(kB) void k_outer_norm(uint32_t n, const double *__restrict__ r,
-                                                  State *st, double *partials) {
-  if (outer_stopped(st)) return;
-  double part = 0.0;
-  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) part += r[i] * r[i];
-  double v[1] = {part}, tot[1];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
-    st->nr = sqrt(tot[0]);
-    st->inner_stop = !(st->nr > 0.0 && isfinite(st->nr));
-  }
-}
-
-// Inner start: r_in = r / nr (float32), z = 0, p_old = 0, beta = 0, rr_in.
+// Inner start: nr = ||r|| (from st->rr), r_in = r / nr (float32), z = 0,
+// p_old = 0, partials of r_in . r_in.
 __global__ __launch_bounds__(kB) void k_inner_init(uint32_t n, const double *__restrict__ r,
                                                   float *__restrict__ rin, float *__restrict__ zin,
                                                   float *__restrict__ p0, State *st,
-                                                  double *partials) {
-  if (outer_stopped(st) || st->inner_stop) return;
-  const double inv = 1.0 / st->nr;
+                                                  Parts rr_out) {
+  if (outer_stopped(st)) return;
+  const double nr = sqrt(st->rr);
+  const bool stop = !(nr > 0.0 && isfinite(nr));
+  const double inv = stop ? 0.0 : 1.0 / nr;
   double part = 0.0;
   for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
     const float v = (float)(r[i] * inv);
@@ -299,47 +324,49 @@ __global__ __launch_bounds__(kB) void k_inner_init(uint32_t n, const double *__r
     p0[i] = 0.0f;
     part += (double)v * (double)v;
   }
-  double v[1] = {part}, tot[1];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
-    st->in_rr = tot[0];
-    st->in_beta = 0.0;
-    if (!(tot[0] > 0.0)) st->inner_stop = 1;
+  double v[1] = {part};
+  put_partials(v, rr_out);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->nr = stop ? 0.0 : nr;
+    st->inner_stop = stop;
+    st->in_first = 1;
   }
 }
 
-// beta_o = (z, q_prev) / (p_prev, q_prev) with z = nr * z_in (0 on the
-// first outer step or after a restart, when pq_prev = 0).
+// Partials of (z, q_prev) with z = nr * z_in (skipped on a fresh start,
+// when pq_prev = 0).
 __global__ __launch_bounds__(kB) void k_outer_zq(uint32_t n, const float *__restrict__ zin,
                                                 const double *__restrict__ q, State *st,
-                                                double *partials) {
-  if (outer_stopped(st)) return;
-  if (st->pq_prev == 0.0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->beta_o = 0.0;
-    return;
-  }
-  const double nr = st->inner_stop && !(st->nr > 0.0) ? 0.0 : st->nr;
+                                                Parts zq_out) {
+  if (outer_stopped(st) || st->pq_prev == 0.0) return;
+  const double nr = st->nr;
   double part = 0.0;
   for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB)
     part += (double)zin[i] * nr * q[i];
-  double v[1] = {part}, tot[1];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) st->beta_o = tot[0] / st->pq_prev;
+  double v[1] = {part};
+  put_partials(v, zq_out);
 }
 
-// p = z - beta_o p (in place; p holds the previous direction).
+// beta_o = (z, q_prev) / (p_prev, q_prev); p = z - beta_o p (in place).
 __global__ __launch_bounds__(kB) void k_outer_p(uint32_t n, const float *__restrict__ zin,
-                                               double *__restrict__ p, const State *st) {
+                                               double *__restrict__ p, State *st, Parts zq_in) {
   if (outer_stopped(st)) return;
-  const double nr = st->nr, bo = st->beta_o;
+  double zq[1] = {0.0};
+  const bool fresh = st->pq_prev == 0.0;
+  if (!fresh) get_totals(zq_in, zq);
+  const double bo = fresh ? 0.0 : zq[0] / st->pq_prev;
+  const double nr = st->nr;
   for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB)
     p[i] = (double)zin[i] * nr - bo * p[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->beta_o = bo;
 }
 
-// q = A p (float64 SELL) with p.q and p.r -> alpha = (p, r) / (p, q).
+// q = A p (float64 SELL) with partials of p.q and p.r.
 template <bool CWAVE>
 __global__ __launch_bounds__(kB) void k_outer_aq(SellView S, const double *__restrict__ p,
                                                 const double *__restrict__ r,
                                                 double *__restrict__ q, State *st,
-                                                double *partials) {
+                                                Parts out) {
   if (outer_stopped(st)) return;
   Lane ln;
   const bool live = lane_slice<CWAVE>(S.offset, S.n_slices, S.geo, ln);
@@ -354,26 +381,27 @@ __global__ __launch_bounds__(kB) void k_outer_aq(SellView S, const double *__res
       pr = p[i] * r[i];
     }
   }
-  double v[2] = {pq, pr}, tot[2];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
-    if (tot[0] > 0.0 && isfinite(tot[0])) {
-      st->alpha = tot[1] / tot[0];
-      st->pq_prev = tot[0];
-    } else {
-      st->breakdown = 1;
-      st->done = 1;
-    }
-  }
+  double v[2] = {pq, pr};
+  put_partials(v, out);
 }
 
-// x += alpha p, r -= alpha q, rr; converged when rr < tol^2 ||b||^2.
+// alpha = (p, r) / (p, q); x += alpha p, r -= alpha q; partials of r.r.
 __global__ __launch_bounds__(kB) void k_outer_update(uint32_t n, double *__restrict__ x,
                                                     double *__restrict__ r,
                                                     const double *__restrict__ p,
                                                     const double *__restrict__ q, State *st,
-                                                    double *partials) {
+                                                    Parts pq_pr_in, Parts rr_out) {
   if (outer_stopped(st)) return;
-  const double alpha = st->alpha;
+  double t[2];
+  get_totals(pq_pr_in, t);
+  if (!(t[0] > 0.0 && isfinite(t[0]))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+    return;
+  }
+  const double alpha = t[1] / t[0];
   double part = 0.0;
   for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
     x[i] = fma(alpha, p[i], x[i]);
@@ -381,20 +409,32 @@ __global__ __launch_bounds__(kB) void k_outer_update(uint32_t n, double *__restr
     r[i] = ri;
     part += ri * ri;
   }
-  double v[1] = {part}, tot[1];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
-    st->iters += 1;
-    st->rr = tot[0];
-    if (!(tot[0] >= st->tol2)) st->done = 1;
+  double v[1] = {part};
+  put_partials(v, rr_out);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->alpha = alpha;
+    st->pq_prev = t[0];
   }
 }
 
-// True residual r = b - A x with r.r and b.b (float64 SELL).
+// One workgroup: the new r.r, the outer iteration count and the stopping
+// test of a flexible-CG step.
+__global__ __launch_bounds__(kB) void k_outer_check(State *st, Parts rr_in) {
+  if (outer_stopped(st)) return;
+  double rr[1];
+  get_totals(rr_in, rr);
+  if (threadIdx.x == 0) {
+    st->rr = rr[0];
+    st->iters += 1;
+    if (!(rr[0] >= st->tol2)) st->done = 1;
+  }
+}
+
+// True residual r = b - A x with partials of r.r and b.b (float64 SELL).
 template <bool CWAVE>
 __global__ __launch_bounds__(kB) void k_residual(SellView S, const double *__restrict__ b,
                                                 const double *__restrict__ x,
-                                                double *__restrict__ r, State *st,
-                                                double *partials) {
+                                                double *__restrict__ r, Parts out) {
   Lane ln;
   const bool live = lane_slice<CWAVE>(S.offset, S.n_slices, S.geo, ln);
   double rr = 0.0, bb = 0.0;
@@ -409,10 +449,18 @@ __global__ __launch_bounds__(kB) void k_residual(SellView S, const double *__res
       bb = b[i] * b[i];
     }
   }
-  double v[2] = {rr, bb}, tot[2];
-  if (reduce_last(v, partials, st, tot) && threadIdx.x == 0) {
-    st->rr = tot[0];
-    st->bnorm2 = tot[1];
+  double v[2] = {rr, bb};
+  put_partials(v, out);
+}
+
+// One workgroup: totals of the residual kernel into the state.
+__global__ __launch_bounds__(kB) void k_residual_totals(State *st, Parts in) {
+  double t[2];
+  get_totals(in, t);
+  if (threadIdx.x == 0) {
+    st->rr = t[0];
+    st->rr0 = t[0];
+    st->bnorm2 = t[1];
   }
 }
 
@@ -425,8 +473,9 @@ __global__ void k_zero(T *p, uint32_t n) {
 
 struct Work {
   State *st;
-  double *partials, *r, *q, *pa, *pb;
-  float *rin, *zin, *p0, *p1, *qin;
+  Parts pa, pb0, pb1;  // product-grid partials; two alternating vector-grid sets
+  double *r, *q, *p0, *p1;
+  float *rin, *zin, *f0, *f1, *qin;
   size_t bytes;
 };
 
@@ -435,25 +484,26 @@ Work carve_work(void *ws, int64_t n, int64_t max_blocks) {
   Work w;
   const size_t nn = n > 0 ? (size_t)n : 1;
   w.st = cv.take<State>(1);
-  w.partials = cv.take<double>(2 * (size_t)max_blocks);
+  w.pa = {cv.take<double>(2 * (size_t)max_blocks), 0};
+  w.pb0 = {cv.take<double>(2 * (size_t)kVecBlocks), 0};
+  w.pb1 = {cv.take<double>(2 * (size_t)kVecBlocks), 0};
   w.r = cv.take<double>(nn);
   w.q = cv.take<double>(nn);
-  w.pa = cv.take<double>(nn);
-  w.pb = cv.take<double>(nn);
+  w.p0 = cv.take<double>(nn);
+  w.p1 = cv.take<double>(nn);
   w.rin = cv.take<float>(nn);
   w.zin = cv.take<float>(nn);
-  w.p0 = cv.take<float>(nn);
-  w.p1 = cv.take<float>(nn);
+  w.f0 = cv.take<float>(nn);
+  w.f1 = cv.take<float>(nn);
   w.qin = cv.take<float>(nn);
   w.bytes = cv.used;
   return w;
 }
 
 int64_t max_blocks_of(const pksell_sell *S, const pksell_matrix *A) {
-  int64_t mb = (int64_t)kVecBlocks;
-  mb = std::max<int64_t>(mb, cdiv(S->n_slices * S->C, kB));
+  int64_t mb = cdiv(S->n_slices * S->C, kB);
   if (A) mb = std::max<int64_t>(mb, cdiv(A->n_slices * A->C, kB));
-  return mb;
+  return std::max<int64_t>(mb, 1);
 }
 
 SellView sell_view(const pksell_sell *S) {
@@ -493,71 +543,86 @@ struct Solve {
   Work w;
   hipStream_t s;
   uint32_t n, vb;
-  int64_t gs, gp;  // grids of the SELL and PackSELL product kernels
+  uint32_t gs, gp;  // grids of the SELL and PackSELL product kernels
 
+  Parts pa_for(uint32_t grid) const { return {w.pa.p, grid}; }
+  Parts vec(const Parts &p) const { return {p.p, vb}; }
+
+  // r = b - A x, then rr and bnorm2 into the state (two launches).
   int residual() {
     const SellView S = sell_view(hi);
+    const Parts out = pa_for(gs);
     if (hi->C == kWave)
-      k_residual<true><<<gs, kB, 0, s>>>(S, b, x, w.r, w.st, w.partials);
+      k_residual<true><<<gs, kB, 0, s>>>(S, b, x, w.r, out);
     else
-      k_residual<false><<<gs, kB, 0, s>>>(S, b, x, w.r, w.st, w.partials);
+      k_residual<false><<<gs, kB, 0, s>>>(S, b, x, w.r, out);
+    PKS_LAUNCHED();
+    k_residual_totals<<<1, kB, 0, s>>>(w.st, out);
     PKS_LAUNCHED();
     return PKSELL_OK;
   }
 
-  // Enqueues ``count`` float64 CG iterations (count even: p buffers alternate).
+  // Enqueues ``count`` float64 CG iterations (count even: the p buffers and
+  // the r.r partial sets alternate, so a replay starts where the last ended).
   int cg_iterations(int count) {
     const SellView S = sell_view(hi);
     for (int it = 0; it < count; ++it) {
-      double *po = (it & 1) ? w.pb : w.pa;
-      double *pn = (it & 1) ? w.pa : w.pb;
+      double *po = (it & 1) ? w.p1 : w.p0;
+      double *pn = (it & 1) ? w.p0 : w.p1;
+      const Parts rr_in = vec((it & 1) ? w.pb0 : w.pb1);
+      const Parts rr_out = vec((it & 1) ? w.pb1 : w.pb0);
+      const Parts pq = pa_for(gs);
       if (hi->C == kWave)
-        k_cg_a<true><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, w.partials);
+        k_cg_a<true><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, rr_in, pq);
       else
-        k_cg_a<false><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, w.partials);
+        k_cg_a<false><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, rr_in, pq);
       PKS_LAUNCHED();
-      k_cg_b<<<vb, kB, 0, s>>>(n, x, w.r, pn, w.q, w.st, w.partials);
+      k_cg_b<<<vb, kB, 0, s>>>(n, x, w.r, pn, w.q, w.st, pq, rr_out);
       PKS_LAUNCHED();
     }
     return PKSELL_OK;
   }
 
   template <int FMT, bool CW>
-  void inner_a(const PackView &A, const float *po, float *pn) {
-    k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, w.partials);
+  void inner_a(const PackView &A, const float *po, float *pn, Parts rr_in, Parts pq_out) {
+    k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
   }
 
   // Enqueues one flexible-CG outer iteration with m_in inner iterations.
   int outer_iteration(int m_in) {
     const SellView S = sell_view(hi);
     const PackView A = pack_view(lo);
-    k_outer_norm<<<vb, kB, 0, s>>>(n, w.r, w.st, w.partials);
-    PKS_LAUNCHED();
-    k_inner_init<<<vb, kB, 0, s>>>(n, w.r, w.rin, w.zin, w.p0, w.st, w.partials);
+    const Parts ppq = pa_for(gp);
+    k_inner_init<<<vb, kB, 0, s>>>(n, w.r, w.rin, w.zin, w.f0, w.st, vec(w.pb0));
     PKS_LAUNCHED();
     for (int it = 0; it < m_in; ++it) {
-      const float *po = (it & 1) ? w.p1 : w.p0;
-      float *pn = (it & 1) ? w.p0 : w.p1;
+      const float *po = (it & 1) ? w.f1 : w.f0;
+      float *pn = (it & 1) ? w.f0 : w.f1;
+      const Parts rr_in = vec((it & 1) ? w.pb1 : w.pb0);
+      const Parts rr_out = vec((it & 1) ? w.pb0 : w.pb1);
       const bool cw = lo->C == kWave;
       switch (lo->fmt) {
-        case PKSELL_FP16: cw ? inner_a<PKSELL_FP16, true>(A, po, pn) : inner_a<PKSELL_FP16, false>(A, po, pn); break;
-        case PKSELL_E8MY: cw ? inner_a<PKSELL_E8MY, true>(A, po, pn) : inner_a<PKSELL_E8MY, false>(A, po, pn); break;
-        default: cw ? inner_a<PKSELL_FIX, true>(A, po, pn) : inner_a<PKSELL_FIX, false>(A, po, pn); break;
+        case PKSELL_FP16: cw ? inner_a<PKSELL_FP16, true>(A, po, pn, rr_in, ppq) : inner_a<PKSELL_FP16, false>(A, po, pn, rr_in, ppq); break;
+        case PKSELL_E8MY: cw ? inner_a<PKSELL_E8MY, true>(A, po, pn, rr_in, ppq) : inner_a<PKSELL_E8MY, false>(A, po, pn, rr_in, ppq); break;
+        default: cw ? inner_a<PKSELL_FIX, true>(A, po, pn, rr_in, ppq) : inner_a<PKSELL_FIX, false>(A, po, pn, rr_in, ppq); break;
       }
       PKS_LAUNCHED();
-      k_inner_b<<<vb, kB, 0, s>>>(n, w.zin, w.rin, pn, w.qin, w.st, w.partials);
+      k_inner_b<<<vb, kB, 0, s>>>(n, w.zin, w.rin, pn, w.qin, w.st, ppq, rr_out);
       PKS_LAUNCHED();
     }
-    k_outer_zq<<<vb, kB, 0, s>>>(n, w.zin, w.q, w.st, w.partials);
+    k_outer_zq<<<vb, kB, 0, s>>>(n, w.zin, w.q, w.st, vec(w.pb0));
     PKS_LAUNCHED();
-    k_outer_p<<<vb, kB, 0, s>>>(n, w.zin, w.pa, w.st);
+    k_outer_p<<<vb, kB, 0, s>>>(n, w.zin, w.p0, w.st, vec(w.pb0));
     PKS_LAUNCHED();
+    const Parts paq = pa_for(gs);
     if (hi->C == kWave)
-      k_outer_aq<true><<<gs, kB, 0, s>>>(S, w.pa, w.r, w.q, w.st, w.partials);
+      k_outer_aq<true><<<gs, kB, 0, s>>>(S, w.p0, w.r, w.q, w.st, paq);
     else
-      k_outer_aq<false><<<gs, kB, 0, s>>>(S, w.pa, w.r, w.q, w.st, w.partials);
+      k_outer_aq<false><<<gs, kB, 0, s>>>(S, w.p0, w.r, w.q, w.st, paq);
     PKS_LAUNCHED();
-    k_outer_update<<<vb, kB, 0, s>>>(n, x, w.r, w.pa, w.q, w.st, w.partials);
+    k_outer_update<<<vb, kB, 0, s>>>(n, x, w.r, w.p0, w.q, w.st, paq, vec(w.pb1));
+    PKS_LAUNCHED();
+    k_outer_check<<<1, kB, 0, s>>>(w.st, vec(w.pb1));
     PKS_LAUNCHED();
     return PKSELL_OK;
   }
@@ -593,22 +658,30 @@ int capture(hipStream_t s, F enqueue, hipGraphExec_t *exec) {
   return PKSELL_OK;
 }
 
+// A fresh start from the current residual: plain CG takes p = r, flexible
+// CG forgets its previous direction.
+int restart(Solve &sv, State &h) {
+  h.done = 0;
+  h.first = 1;
+  h.beta = 0.0;
+  h.pq_prev = 0.0;
+  k_zero<double><<<sv.vb, kB, 0, sv.s>>>(sv.w.p0, sv.n);
+  k_zero<double><<<sv.vb, kB, 0, sv.s>>>(sv.w.p1, sv.n);
+  PKS_LAUNCHED();
+  return write_state(sv.w, h, sv.s);
+}
+
 int solve(Solve &sv, double tol, int32_t m_in, int32_t max_outer, pksell_pcg_info *info) {
   hipStream_t s = sv.s;
   const uint32_t n = sv.n;
   const Work &w = sv.w;
-  k_zero<double><<<sv.vb, kB, 0, s>>>(w.pa, n);
-  k_zero<double><<<sv.vb, kB, 0, s>>>(w.pb, n);
   k_zero<double><<<sv.vb, kB, 0, s>>>(w.q, n);
   PKS_LAUNCHED();
   State h{};
   h.max_iters = max_outer;
   int rc = write_state(w, h, s);
   if (rc) return rc;
-  rc = sv.residual();
-  if (rc) return rc;
-  rc = read_state(w, h, s);
-  if (rc) return rc;
+  if ((rc = sv.residual()) || (rc = read_state(w, h, s))) return rc;
   if (h.bnorm2 == 0.0) {  // b = 0: x = 0 solves it
     k_zero<double><<<sv.vb, kB, 0, s>>>(sv.x, n);
     PKS_LAUNCHED();
@@ -617,14 +690,11 @@ int solve(Solve &sv, double tol, int32_t m_in, int32_t max_outer, pksell_pcg_inf
     return PKSELL_OK;
   }
   h.tol2 = tol * tol * h.bnorm2;
-  h.beta = 0.0;
-  h.pq_prev = 0.0;
   if (!(h.rr >= h.tol2)) {  // the initial guess already satisfies the test
     info->rel_residual = std::sqrt(h.rr / h.bnorm2);
     return PKSELL_OK;
   }
-  rc = write_state(w, h, s);
-  if (rc) return rc;
+  if ((rc = restart(sv, h))) return rc;
 
   const bool plain = sv.lo == nullptr;
   constexpr int kCgPerGraph = 16;
@@ -648,14 +718,9 @@ int solve(Solve &sv, double tol, int32_t m_in, int32_t max_outer, pksell_pcg_inf
     }
     if (h.done) {
       // confirm on the true residual b - A x; otherwise restart from it
-      if ((status = sv.residual())) break;
-      if ((status = read_state(w, h, s))) break;
+      if ((status = sv.residual()) || (status = read_state(w, h, s))) break;
       if (h.rr < h.tol2) break;
-      h.done = 0;
-      h.beta = 0.0;
-      h.pq_prev = 0.0;
-      k_zero<double><<<sv.vb, kB, 0, s>>>(w.pa, n);
-      if ((status = write_state(w, h, s))) break;
+      if ((status = restart(sv, h))) break;
     }
     if (h.iters >= max_outer) {
       set_error("no convergence in %d iterations (relative residual %.3e)", h.iters,
@@ -667,7 +732,7 @@ int solve(Solve &sv, double tol, int32_t m_in, int32_t max_outer, pksell_pcg_inf
   (void)hipGraphExecDestroy(exec);
   info->outer_iterations = h.iters;
   info->inner_iterations = h.inner_iters;
-  if (status == PKSELL_OK || status == PKSELL_ENOTCONV) {
+  if (status == PKSELL_ENOTCONV) {
     int rc2 = sv.residual();
     if (rc2 == PKSELL_OK) rc2 = read_state(w, h, s);
     if (rc2) return rc2;
@@ -716,8 +781,8 @@ int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi, const double 
   sv.x = x;
   sv.n = (uint32_t)A_hi->n;
   sv.vb = (uint32_t)std::min<int64_t>(kVecBlocks, cdiv(A_hi->n, kB));
-  sv.gs = cdiv(A_hi->n_slices * A_hi->C, kB);
-  sv.gp = A_lo ? cdiv(A_lo->n_slices * A_lo->C, kB) : 0;
+  sv.gs = (uint32_t)cdiv(A_hi->n_slices * A_hi->C, kB);
+  sv.gp = A_lo ? (uint32_t)cdiv(A_lo->n_slices * A_lo->C, kB) : 0u;
   sv.w = carve_work(ws, A_hi->n, max_blocks_of(A_hi, A_lo));
   PKS_CHECK(ws && ws_bytes >= sv.w.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes",
             sv.w.bytes);
