@@ -39,6 +39,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Hardware-counter HBM traffic of the headline kernel, from the committed
+# rocprofv3 summary.  It is reported only while the kernel sources hash to
+# the value recorded there (a changed kernel invalidates the counters).
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_pair_fp16_laplace3d_128.md")
+
+
+def profiled_traffic(path=TRAFFIC_PROFILE):
+    import hashlib
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.split(":", 1)[0] in ("sources", "source_sha256",
+                                                     "traffic_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    if len(fields) != 3:
+        return None
+    h = hashlib.sha256()
+    for src in fields["sources"].split():
+        try:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != fields["source_sha256"]:
+        log("[bench] headline kernel sources changed since the counters were taken: traffic null")
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -208,7 +240,7 @@ def main():
                    "bytes_per_step": H["bytes"], "replicas": H["replicas"]},
         "roofline": {"bound": "hbm", "achieved": round(H["gbs"], 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(H["gbs"] / PEAK_HBM_GBS, 4),
-                     "traffic": None},
+                     "traffic": profiled_traffic() if head == "packsell_fp16" else None},
         "gflops": round(H["gflops"], 1),
         "variants": {},
     }
@@ -289,18 +321,25 @@ def time_variant(args, torch, B, A, m, n, mk_y=None):
 
 def powerlaw_leg(args, torch, B, W):
     """Irregular power-law rows, n = 10^6 (mean 30, max 5000, RSD 4.3):
-    PackSELL FP16 and E8M10 (D = 12) at sigma = 65536 against FP32 SELL."""
+    PackSELL FP16 and E8M10 (D = 12) at sigma = 65536 against FP32 SELL,
+    with and without wide-slice splitting (J words per work unit)."""
     dev = torch.device("cuda:0")
     t0 = time.time()
     a = W.m3_powerlaw()
     log(f"[bench] powerlaw n={a.n} nnz={a.nnz} generated in {time.time() - t0:.1f}s")
     res = {"n": a.n, "nnz": a.nnz}
-    for name, fmt, D in [("packsell_fp16", "fp16", 15), ("packsell_e8m10", "e8my", 12)]:
-        A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 65536, B.EXPLICIT, dev)
+    variants = [("packsell_fp16", "fp16", 15, 0), ("packsell_e8m10", "e8my", 12, 0)]
+    variants += [(f"packsell_fp16_split{J}", "fp16", 15, J) for J in (128, 256, 512)]
+    variants += [("packsell_e8m10_split256", "e8my", 12, 256)]
+    for name, fmt, D, J in variants:
+        A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 65536, B.EXPLICIT, dev,
+                     split_words=J)
         ms, per, R = time_variant(args, torch, B, A, a.m, a.n)
         res[name] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
                      "GFLOP/s": round(2 * a.nnz / (ms * 1e-3) / 1e9, 1),
                      "words_per_nnz": round(A.n_words / a.nnz, 3), "sigma": 65536}
+        if J:
+            res[name].update(split_words=J, units=A.n_units, split_units=A.n_split_units)
         log(f"[bench] powerlaw {name}: {res[name]}")
         del A
     S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 65536, B.EXPLICIT, dev)
@@ -308,7 +347,7 @@ def powerlaw_leg(args, torch, B, W):
     res["sell_fp32"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
                         "slots_per_nnz": round(S.n_slots / a.nnz, 3)}
     log(f"[bench] powerlaw sell_fp32: {res['sell_fp32']}")
-    for name in ("packsell_fp16", "packsell_e8m10"):
+    for name, *_ in variants:
         res[name]["speedup_vs_sell_fp32"] = round(res["sell_fp32"]["us"] / res[name]["us"], 3)
     return res
 

@@ -70,6 +70,21 @@ extern "C" {
  *                                only; may be NULL in explicit mode)
  *   row_exp  int16[n]            FIX only: row scale exponent e, stored order
  *                                (decoded value = q * 2^e)
+ *
+ * Wide-slice splitting (C = 64 only; optional).  Set split_words = J (a
+ * multiple of 8, 0 = off) after pksell_encode_query.  The analyse phase then
+ * counts the work units: a slice wider than J words per lane becomes
+ * ceil(w / J) units of J words, a narrower slice one unit.  When some slice
+ * is split (n_split_units > 0) the caller also allocates
+ *   units    uint32[4 * n_units]        {slice, chunk, chunks, base} per unit
+ *   splits   uint32[4 * n_split_slices] {slice, base, chunks, 0} per split slice
+ *   ckpt     uint32[64 * n_split_units] column reached by each lane at the
+ *                                       start of each chunk (index base + chunk)
+ *   partial  float[64 * n_split_units]  per-chunk sums (scratch of pksell_spmv:
+ *                                       one product at a time per matrix)
+ * and the fill phase writes units, splits and ckpt.  Products with k = 1 then
+ * run one work unit per wave and add each split slice's chunk sums in chunk
+ * order (deterministic); other calls ignore the split arrays.
  */
 typedef struct pksell_matrix {
   int64_t n, m, nnz;
@@ -80,6 +95,12 @@ typedef struct pksell_matrix {
   int64_t *offset;
   void *perm;
   int16_t *row_exp;
+  int32_t split_words, reserved;
+  int64_t n_units, n_split_units, n_split_slices;
+  uint32_t *units;
+  uint32_t *splits;
+  uint32_t *ckpt;
+  float *partial;
 } pksell_matrix;
 
 /* Plain SELL-C-sigma (sec. 3) with float32 or float64 values and int32
@@ -159,7 +180,8 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val,
 
 /* y = A_q x with float32 accumulation; y is overwritten (no beta term).  In
  * implicit mode y is in the original row order, in explicit mode in stored
- * order.  1 <= k <= 64. */
+ * order.  1 <= k <= 64.  With k a multiple of 4 and x, y 16-byte aligned, x
+ * is gathered and y stored four columns at a time. */
 int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k,
                 void *stream);
 
@@ -226,6 +248,8 @@ typedef struct pksell_batch {
   int32_t count, fmt, k, transpose;
   int64_t total_units;      /* slices over all matrices */
   int32_t units_per_wave, waves;
+  int32_t vec4;             /* k % 4 == 0 and 16-byte aligned blocks: 16-byte gathers */
+  int32_t reserved;
   void *items;
   void *unit_start;
 } pksell_batch;

@@ -36,7 +36,10 @@ class CMatrix(ctypes.Structure):
                 ("C", i32), ("sigma", i32), ("D", i32), ("fmt", i32),
                 ("perm_mode", i32), ("perm_bytes", i32),
                 ("n_slices", i64), ("n_words", i64), ("n_dummies", i64), ("k_left", i64),
-                ("pack", vp), ("offset", vp), ("perm", vp), ("row_exp", vp)]
+                ("pack", vp), ("offset", vp), ("perm", vp), ("row_exp", vp),
+                ("split_words", i32), ("reserved", i32),
+                ("n_units", i64), ("n_split_units", i64), ("n_split_slices", i64),
+                ("units", vp), ("splits", vp), ("ckpt", vp), ("partial", vp)]
 
 
 class CSell(ctypes.Structure):
@@ -54,7 +57,7 @@ class CBatchItem(ctypes.Structure):
 class CBatch(ctypes.Structure):
     _fields_ = [("count", i32), ("fmt", i32), ("k", i32), ("transpose", i32),
                 ("total_units", i64), ("units_per_wave", i32), ("waves", i32),
-                ("items", vp), ("unit_start", vp)]
+                ("vec4", i32), ("reserved", i32), ("items", vp), ("unit_start", vp)]
 
 
 class CPcgInfo(ctypes.Structure):
@@ -203,14 +206,37 @@ class PackSELLMatrix:
         d.offset = self.t["offset"].data_ptr()
         d.perm = self.t["perm"].data_ptr() if self.t.get("perm") is not None else None
         d.row_exp = self.t["row_exp"].data_ptr() if self.t.get("row_exp") is not None else None
+        for name in ("units", "splits", "ckpt", "partial"):
+            v = self.t.get(name)
+            setattr(d, name, v.data_ptr() if v is not None else None)
+
+    @property
+    def split_words(self) -> int:
+        return self.desc.split_words
+
+    @property
+    def n_units(self) -> int:
+        return self.desc.n_units
+
+    @property
+    def n_split_units(self) -> int:
+        return self.desc.n_split_units
+
+    @property
+    def n_split_slices(self) -> int:
+        return self.desc.n_split_slices
 
 
 def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 64,
            sigma: int = 256, perm_mode: int = IMPLICIT, device="cuda",
-           keep_perm: bool = True, analyse_only: bool = False) -> PackSELLMatrix:
+           keep_perm: bool = True, analyse_only: bool = False,
+           split_words: int = 0) -> PackSELLMatrix:
     """CSR (numpy or torch; values float32 or float64) -> PackSELL on the GPU.
     With ``analyse_only`` only the analyse phase runs: the descriptor then
-    holds n_words, n_dummies and k_left, and no words are written."""
+    holds n_words, n_dummies, k_left and the work-unit counts, and no words
+    are written.  ``split_words`` = J > 0 (C = 64, a multiple of 8) splits
+    slices wider than J words per lane into chunks of J words for the
+    single-vector product."""
     if isinstance(fmt, str):
         fmt = FMT_BY_NAME[fmt]
     device = torch.device(device)
@@ -227,6 +253,7 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
     L = lib()
     _check(L.pksell_encode_query(n, m, nnz, C, sigma, D, fmt, perm_mode,
                                  ctypes.byref(desc), ctypes.byref(ws_bytes)))
+    desc.split_words = int(split_words)
     t = {"offset": torch.empty(desc.n_slices + 1, dtype=torch.int64, device=device)}
     if perm_mode == IMPLICIT or keep_perm:
         t["perm"] = torch.empty(max(1, n * desc.perm_bytes), dtype=torch.uint8, device=device)
@@ -242,6 +269,11 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
     t["pack"] = torch.empty(max(1, desc.n_words), dtype=torch.int32, device=device)
     if fmt == FIX:
         t["row_exp"] = torch.empty(max(1, n), dtype=torch.int16, device=device)
+    if desc.n_split_units > 0:
+        t["units"] = torch.empty(4 * desc.n_units, dtype=torch.int32, device=device)
+        t["splits"] = torch.empty(4 * desc.n_split_slices, dtype=torch.int32, device=device)
+        t["ckpt"] = torch.empty(64 * desc.n_split_units, dtype=torch.int32, device=device)
+        t["partial"] = torch.empty(64 * desc.n_split_units, dtype=torch.float32, device=device)
     A._bind()
     _check(L.pksell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
                            _ptr(ws), ws_bytes.value, st))

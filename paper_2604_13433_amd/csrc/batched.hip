@@ -44,7 +44,7 @@ __device__ inline uint32_t find_item(const uint32_t *unit_start, uint32_t count,
   return lo;
 }
 
-template <int FMT, int KB, bool TRANS>
+template <int FMT, int KB, bool TRANS, bool V4>
 __device__ inline void do_unit(const Item &it, uint32_t k_slice, uint32_t lane, int k, int r0) {
   const uint32_t t = k_slice * kWave + lane;
   const int64_t s = it.offset[k_slice];
@@ -60,13 +60,31 @@ __device__ inline void do_unit(const Item &it, uint32_t k_slice, uint32_t lane, 
     float acc[KB];
 #pragma unroll
     for (int r = 0; r < KB; ++r) acc[r] = 0.0f;
-    packsell_row<FMT, KB>(P, kWave, w, c, it.cd,
-                          [&](uint32_t cc, int r) { return buffer_load_f32(rx, cc * kx + x0 + 4u * r); },
-                          acc);
+    if constexpr (V4) {
+      packsell_row_v4<FMT, KB>(P, kWave, w, c, it.cd,
+                               [&](uint32_t cc, int g) {
+                                 return buffer_load_f32x4(rx, cc * kx + x0 + 16u * g);
+                               },
+                               acc);
+    } else {
+      packsell_row<FMT, KB>(P, kWave, w, c, it.cd,
+                            [&](uint32_t cc, int r) { return buffer_load_f32(rx, cc * kx + x0 + 4u * r); },
+                            acc);
+    }
     if (t < it.n) {
       const int64_t o = (int64_t)out_row(it.perm, it.perm_bytes, t, it.geo) * k + r0;
 #pragma unroll
-      for (int r = 0; r < KB; ++r) it.out[o + r] = FMT == PKSELL_FIX ? ldexpf(acc[r], sh) : acc[r];
+      for (int r = 0; r < KB; ++r)
+        if constexpr (FMT == PKSELL_FIX) acc[r] = ldexpf(acc[r], sh);
+      if constexpr (V4) {
+        f32x4 *yo = reinterpret_cast<f32x4 *>(it.out + o);
+#pragma unroll
+        for (int g = 0; g < KB / 4; ++g)
+          yo[g] = f32x4{acc[4 * g], acc[4 * g + 1], acc[4 * g + 2], acc[4 * g + 3]};
+      } else {
+#pragma unroll
+        for (int r = 0; r < KB; ++r) it.out[o + r] = acc[r];
+      }
     }
   } else {
     if (t >= it.n) return;
@@ -88,7 +106,7 @@ __device__ inline void do_unit(const Item &it, uint32_t k_slice, uint32_t lane, 
   }
 }
 
-template <int FMT, int KB, bool TRANS>
+template <int FMT, int KB, bool TRANS, bool V4>
 __global__ __launch_bounds__(kB) void k_batched(const Item *__restrict__ items,
                                                const uint32_t *__restrict__ unit_start,
                                                uint32_t count, uint32_t total, uint32_t per_wave,
@@ -102,7 +120,7 @@ __global__ __launch_bounds__(kB) void k_batched(const Item *__restrict__ items,
   uint32_t it = find_item(unit_start, count, u);
   for (; u < u1; ++u) {
     while (u >= unit_start[it + 1]) ++it;
-    do_unit<FMT, KB, TRANS>(items[it], u - unit_start[it], lane, k, r0);
+    do_unit<FMT, KB, TRANS, V4>(items[it], u - unit_start[it], lane, k, r0);
   }
 }
 
@@ -187,6 +205,12 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
   plan->fmt = fmt;
   plan->k = (int32_t)k;
   plan->transpose = transpose ? 1 : 0;
+  // 16-byte gathers and stores need k % 4 == 0 and 16-byte aligned blocks
+  bool aligned = k % 4 == 0;
+  for (int32_t i = 0; i < count; ++i)
+    aligned &= ((reinterpret_cast<uintptr_t>(items[i].in) |
+                 reinterpret_cast<uintptr_t>(items[i].out)) & 15) == 0;
+  plan->vec4 = aligned ? 1 : 0;
   plan->total_units = start[(size_t)count];
   // a chip-filling grid: 8 waves per SIMD, 4 SIMDs per CU
   const int64_t max_waves = (int64_t)cus * 32;
@@ -212,15 +236,24 @@ int pksell_spmv_batched(const pksell_batch *plan, void *stream) {
   const int64_t grid = cdiv(plan->waves, kB / kWave);
   const uint32_t cnt = (uint32_t)plan->count, tot = (uint32_t)plan->total_units,
                  pw = (uint32_t)plan->units_per_wave;
+  // 16-byte gathers and stores when every x / y row group is aligned
+  const bool v4 = plan->vec4 && !plan->transpose;
   for (int r0 = 0; r0 < k;) {
     const int left = k - r0;
     const int kb = left >= 32 ? 32 : left >= 8 ? 8 : 1;
-#define PKS_B(F, KB, T) k_batched<F, KB, T><<<grid, kB, 0, st>>>(items, start, cnt, tot, pw, k, r0)
-#define PKS_BK(F, T)                          \
-  do {                                        \
-    if (kb == 32) PKS_B(F, 32, T);            \
-    else if (kb == 8) PKS_B(F, 8, T);         \
-    else PKS_B(F, 1, T);                      \
+#define PKS_B(F, KB, T, V) \
+  k_batched<F, KB, T, V><<<grid, kB, 0, st>>>(items, start, cnt, tot, pw, k, r0)
+#define PKS_BK(F, T)                                  \
+  do {                                                \
+    if (kb == 32) {                                   \
+      if (v4) PKS_B(F, 32, T, true);                  \
+      else PKS_B(F, 32, T, false);                    \
+    } else if (kb == 8) {                             \
+      if (v4) PKS_B(F, 8, T, true);                   \
+      else PKS_B(F, 8, T, false);                     \
+    } else {                                          \
+      PKS_B(F, 1, T, false);                          \
+    }                                                 \
   } while (0)
 #define PKS_BT(F) do { if (plan->transpose) PKS_BK(F, true); else PKS_BK(F, false); } while (0)
     switch (plan->fmt) {

@@ -5,8 +5,11 @@
 // deltas >= 2^D (eq. 2 with the left offset of eq. 4, sec. 4.3); rank the
 // rows of every sigma-window by descending count, ties by row index (the
 // SELL-C-sigma sort, sec. 3, counting dummies as sec. 4.3 asks); take slice
-// widths and scan them into offsets.  Fill phase: one thread per stored row
-// writes its words down its slice lane and pads the lane with zero words.
+// widths and scan them into offsets; with wide-slice splitting on, count
+// each slice's work units and scan those too.  Fill phase: one thread per
+// stored row writes its words down its slice lane, pads the lane with zero
+// words and records, for split slices, the column reached at every chunk
+// start.
 #include "codec.hpp"
 
 #include <cstdarg>
@@ -29,7 +32,8 @@ struct EncInfo {
   int32_t k_left;
   unsigned long long n_dummies;
   long long n_words;
-  long long reserved;
+  long long units;         // low 32 bits: work units, high 32: units of split slices
+  long long split_slices;
 };
 
 // ---- analyse -----------------------------------------------------------------
@@ -211,8 +215,61 @@ __global__ void k_scan_apply(int64_t *__restrict__ a, int64_t len, const int64_t
   }
 }
 
-__global__ void k_finish(const int64_t *__restrict__ offset, int64_t n_slices, EncInfo *info) {
+// ---- work units of wide-slice splitting (C = 64) --------------------------------
+
+// A slice of w > J words per lane is split into ceil(w / J) units of J
+// words (the last one shorter); a narrower slice is one unit.  ucnt[k + 1]
+// packs the slice's unit count (low 32 bits) and its split-unit count (high
+// 32 bits), scnt[k + 1] is 1 for a split slice; both are scanned afterwards
+// so that index k holds the exclusive prefix.
+__global__ void k_unit_counts(const int64_t *__restrict__ offset, int64_t n_slices, int32_t J,
+                              int64_t *__restrict__ ucnt, int64_t *__restrict__ scnt) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) {
+    ucnt[0] = 0;
+    scnt[0] = 0;
+  }
+  if (k >= n_slices) return;
+  const int64_t w = (offset[k + 1] - offset[k]) / kWave;
+  const int64_t u = w > J ? (w + J - 1) / J : 1;
+  ucnt[k + 1] = u | (w > J ? u << 32 : 0);
+  scnt[k + 1] = w > J ? 1 : 0;
+}
+
+// Unit table {slice, chunk, chunks, base} and split table {slice, base,
+// chunks, 0}; base is the index of the slice's first chunk among all split
+// units (it addresses the checkpoints and the chunk sums).
+__global__ void k_unit_tables(const int64_t *__restrict__ ucnt, const int64_t *__restrict__ scnt,
+                              int64_t n_slices, uint32_t *__restrict__ units,
+                              uint32_t *__restrict__ splits) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_slices) return;
+  const uint64_t u0 = (uint64_t)ucnt[k], u1 = (uint64_t)ucnt[k + 1];
+  const uint32_t first = (uint32_t)u0, base = (uint32_t)(u0 >> 32);
+  const uint32_t chunks = (uint32_t)u1 - first;
+  const bool split = (uint32_t)(u1 >> 32) != base;
+  for (uint32_t c = 0; c < chunks; ++c) {
+    uint32_t *d = units + 4 * (uint64_t)(first + c);
+    d[0] = (uint32_t)k;
+    d[1] = c;
+    d[2] = chunks;
+    d[3] = split ? base : 0u;
+  }
+  if (split) {
+    uint32_t *d = splits + 4 * (uint64_t)scnt[k];
+    d[0] = (uint32_t)k;
+    d[1] = base;
+    d[2] = chunks;
+    d[3] = 0u;
+  }
+}
+
+__global__ void k_finish(const int64_t *__restrict__ offset, int64_t n_slices,
+                         const int64_t *__restrict__ ucnt, const int64_t *__restrict__ scnt,
+                         EncInfo *info) {
   info->n_words = offset[n_slices];
+  info->units = ucnt ? ucnt[n_slices] : 0;
+  info->split_slices = scnt ? scnt[n_slices] : 0;
 }
 
 // ---- fill --------------------------------------------------------------------
@@ -235,7 +292,8 @@ __global__ void k_fill_packsell(const int64_t *__restrict__ rowptr, const int32_
                                 int64_t k_left, int32_t D, int64_t n_slices,
                                 const int32_t *__restrict__ stored_rows,
                                 const int64_t *__restrict__ offset, uint32_t *__restrict__ pack,
-                                int16_t *__restrict__ row_exp) {
+                                int16_t *__restrict__ row_exp, int32_t J,
+                                const int64_t *__restrict__ ucnt, uint32_t *__restrict__ ckpt) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_slices * C) return;
   int64_t k = i / C, l = i - k * C;
@@ -243,6 +301,17 @@ __global__ void k_fill_packsell(const int64_t *__restrict__ rowptr, const int32_
   int64_t w = (offset[k + 1] - s) / C;
   uint32_t *out = pack + s + l;
   int64_t j = 0;
+  // Split slice (J > 0 and w > J): the column reached before word j is
+  // recorded whenever j starts a chunk (j a multiple of J).
+  uint32_t *ck = nullptr;
+  if (J > 0 && w > J) ck = ckpt + (uint64_t)(((uint64_t)ucnt[k]) >> 32) * kWave + l;
+  uint32_t run = left_offset(i < n ? stored_rows[i] : i, sigma, k_left);
+  auto put = [&](uint32_t word, uint32_t col_after) {
+    if (ck && j % J == 0) ck[(j / J) * kWave] = run;
+    out[j * C] = word;
+    run = col_after;
+    ++j;
+  };
   if (i < n) {
     int64_t r = stored_rows[i];
     int64_t rb = rowptr[r], re = rowptr[r + 1];
@@ -268,15 +337,13 @@ __global__ void k_fill_packsell(const int64_t *__restrict__ rowptr, const int32_
       else
         vb = quant_fix(v, ex, D);
       if (d >= lim) {
-        out[j * C] = d << 1;  // dummy at the same column
-        ++j;
+        put(d << 1, c);  // dummy at the same column
         d = 0;
       }
-      out[j * C] = vb | (d << 1) | 1u;
-      ++j;
+      put(vb | (d << 1) | 1u, c);
     }
   }
-  for (; j < w; ++j) out[j * C] = 0u;
+  while (j < w) put(0u, run);
 }
 
 template <typename VT, typename OT>
@@ -314,6 +381,8 @@ struct Plan {
   int32_t *cnt;
   int32_t *stored_rows;
   int64_t *tile_sums;
+  int64_t *ucnt;  // per-slice unit counts, scanned (n_slices + 1)
+  int64_t *scnt;  // per-slice split flags, scanned (n_slices + 1)
   size_t bytes;
 };
 
@@ -324,6 +393,8 @@ Plan carve(void *ws, int64_t n, int64_t n_slices) {
   p.cnt = cv.take<int32_t>(n > 0 ? n : 1);
   p.stored_rows = cv.take<int32_t>(n > 0 ? n : 1);
   p.tile_sums = cv.take<int64_t>(cdiv(n_slices > 0 ? n_slices : 1, kScanTile));
+  p.ucnt = cv.take<int64_t>(n_slices + 1);
+  p.scnt = cv.take<int64_t>(n_slices + 1);
   p.bytes = cv.used;
   return p;
 }
@@ -347,7 +418,7 @@ int check_common(int64_t n, int64_t m, int64_t nnz, int32_t C, int32_t sigma,
 int analyse(const int64_t *rowptr, const int32_t *col, const void *finite_val,
             int32_t val_dtype, int64_t n, int64_t m, int64_t nnz, int32_t C, int32_t sigma,
             int32_t D, int64_t n_slices, int64_t *offset, void *perm, int32_t perm_bytes,
-            const Plan &p, hipStream_t st, EncInfo *host) {
+            int32_t split_words, const Plan &p, hipStream_t st, EncInfo *host) {
   PKS_HIP(hipMemsetAsync(p.info, 0, sizeof(EncInfo), st));
   const int64_t rb = cdiv(n, kBlock);
   if (n > 0) {
@@ -382,11 +453,26 @@ int analyse(const int64_t *rowptr, const int32_t *col, const void *finite_val,
     PKS_LAUNCHED();
     k_scan_apply<<<ntiles, kBlock, 0, st>>>(offset + 1, n_slices, p.tile_sums);
     PKS_LAUNCHED();
+    if (split_words > 0) {
+      k_unit_counts<<<cdiv(n_slices, kBlock), kBlock, 0, st>>>(offset, n_slices, split_words,
+                                                              p.ucnt, p.scnt);
+      PKS_LAUNCHED();
+      for (int64_t *a : {p.ucnt, p.scnt}) {
+        k_scan_tiles<<<ntiles, kBlock, 0, st>>>(a + 1, n_slices, p.tile_sums);
+        PKS_LAUNCHED();
+        k_scan_sums<<<1, kBlock, 0, st>>>(p.tile_sums, ntiles);
+        PKS_LAUNCHED();
+        k_scan_apply<<<ntiles, kBlock, 0, st>>>(a + 1, n_slices, p.tile_sums);
+        PKS_LAUNCHED();
+      }
+    }
   } else {
     int64_t zero = 0;
     PKS_HIP(hipMemcpyAsync(offset, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
   }
-  k_finish<<<1, 1, 0, st>>>(offset, n_slices, p.info);
+  const bool units = split_words > 0 && n > 0;
+  k_finish<<<1, 1, 0, st>>>(offset, n_slices, units ? p.ucnt : nullptr,
+                            units ? p.scnt : nullptr, p.info);
   PKS_LAUNCHED();
   PKS_HIP(hipMemcpyAsync(host, p.info, sizeof(EncInfo), hipMemcpyDeviceToHost, st));
   PKS_HIP(hipStreamSynchronize(st));
@@ -464,28 +550,43 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val, in
             "implicit mode needs perm");
   Plan p = carve(ws, A->n, A->n_slices);
   PKS_CHECK(ws && ws_bytes >= p.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes", p.bytes);
+  PKS_CHECK(A->split_words == 0 || (A->C == kWave && A->split_words % 8 == 0 &&
+                                    A->split_words >= 8 && A->split_words <= (1 << 24)),
+            PKSELL_EINVAL, "split_words must be 0 or a multiple of 8 in [8, 2^24], with C = 64");
   hipStream_t st = as_stream(stream);
   if (A->pack == nullptr) {
     EncInfo h{};
     int rc = analyse(rowptr, col, A->fmt == PKSELL_FIX ? val : nullptr, val_dtype, A->n, A->m,
                      A->nnz, A->C, A->sigma, A->D, A->n_slices, A->offset, A->perm,
-                     A->perm_bytes, p, st, &h);
+                     A->perm_bytes, A->split_words, p, st, &h);
     if (rc) return rc;
     A->k_left = h.k_left;
     A->n_dummies = (int64_t)h.n_dummies;
     A->n_words = h.n_words;
     PKS_CHECK(A->n_words < (int64_t(1) << 40), PKSELL_ERANGE, "too many words");
+    A->n_units = (int64_t)(uint32_t)h.units;
+    A->n_split_units = (int64_t)((uint64_t)h.units >> 32);
+    A->n_split_slices = h.split_slices;
     return PKSELL_OK;
   }
   PKS_CHECK(A->fmt != PKSELL_FIX || A->row_exp, PKSELL_EINVAL, "FIX needs row_exp");
   const int64_t rows = A->n_slices * A->C;
   if (rows == 0) return PKSELL_OK;
+  const bool split = A->split_words > 0 && A->n_split_units > 0;
+  PKS_CHECK(!split || (A->units && A->splits && A->ckpt), PKSELL_EINVAL,
+            "split slices need units, splits and ckpt");
+  if (split) {
+    k_unit_tables<<<cdiv(A->n_slices, kBlock), kBlock, 0, st>>>(p.ucnt, p.scnt, A->n_slices,
+                                                               A->units, A->splits);
+    PKS_LAUNCHED();
+  }
   const int64_t g = cdiv(rows, kBlock);
 #define PKS_FILL(F, VT)                                                                      \
   k_fill_packsell<F, VT><<<g, kBlock, 0, st>>>(rowptr, col, static_cast<const VT *>(val),   \
                                                A->n, A->C, A->sigma, A->k_left, A->D,       \
                                                A->n_slices, p.stored_rows, A->offset,       \
-                                               A->pack, A->row_exp)
+                                               A->pack, A->row_exp,                         \
+                                               split ? A->split_words : 0, p.ucnt, A->ckpt)
   if (val_dtype == PKSELL_F32) {
     if (A->fmt == PKSELL_FP16) PKS_FILL(PKSELL_FP16, float);
     else if (A->fmt == PKSELL_E8MY) PKS_FILL(PKSELL_E8MY, float);
@@ -534,7 +635,7 @@ int pksell_sell_encode(const int64_t *rowptr, const int32_t *col, const void *va
   if (S->val == nullptr) {
     EncInfo h{};
     int rc = analyse(rowptr, col, nullptr, val_dtype, S->n, S->m, S->nnz, S->C, S->sigma, 31,
-                     S->n_slices, S->offset, S->perm, S->perm_bytes, p, st, &h);
+                     S->n_slices, S->offset, S->perm, S->perm_bytes, 0, p, st, &h);
     if (rc) return rc;
     S->n_slots = h.n_words;
     return PKSELL_OK;

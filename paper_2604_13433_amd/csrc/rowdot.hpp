@@ -85,4 +85,55 @@ __device__ inline void packsell_row(const uint32_t *P, uint32_t stride, uint32_t
   if (j < w) group(j, false);
 }
 
+// Four consecutive right-hand sides as one 16-byte gather (x rows hold k
+// floats with k a multiple of 4, so every such group is 16-byte aligned).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f32x4 buffer_load_f32x4(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0));
+}
+
+// packsell_row for KB right-hand sides (KB a multiple of 4) gathered four at
+// a time: ``gather4(c, g)`` returns columns 4g .. 4g+3 of x row c.  Each
+// accumulator still adds its products in word order.
+template <int FMT, int KB, typename Gather4>
+__device__ inline void packsell_row_v4(const uint32_t *P, uint32_t stride, uint32_t w, uint32_t c,
+                                       const Codec &cd, Gather4 gather4, float (&acc)[KB]) {
+  static_assert(KB % 4 == 0, "KB must be a multiple of 4");
+  auto group = [&](uint32_t j, bool full) {
+    uint32_t p[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const uint32_t jj = full ? j + q : min(j + q, w - 1);
+      p[q] = __builtin_nontemporal_load(P + jj * stride);
+      if (!full && j + q >= w) p[q] = 0u;
+    }
+    uint32_t cq[kUnroll];
+    float v[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const Unpacked u = unpack(p[q], cd);
+      c += u.delta;
+      cq[q] = c;
+      v[q] = decode_value<FMT>(u.vbits);
+    }
+#pragma unroll
+    for (int g = 0; g < KB / 4; ++g) {
+      f32x4 xv[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) xv[q] = gather4(cq[q], g);
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        acc[4 * g + 0] = fmaf(v[q], xv[q].x, acc[4 * g + 0]);
+        acc[4 * g + 1] = fmaf(v[q], xv[q].y, acc[4 * g + 1]);
+        acc[4 * g + 2] = fmaf(v[q], xv[q].z, acc[4 * g + 2]);
+        acc[4 * g + 3] = fmaf(v[q], xv[q].w, acc[4 * g + 3]);
+      }
+    }
+  };
+  uint32_t j = 0;
+  for (; j + kUnroll <= w; j += kUnroll) group(j, true);
+  if (j < w) group(j, false);
+}
+
 }  // namespace pksell

@@ -32,8 +32,9 @@ struct SpmvArgs {
 };
 
 // KB right-hand sides (columns r0 .. r0+KB-1 of the row-major x / y blocks;
-// K1: k == 1, so the x offset is a shift).
-template <int FMT, bool CWAVE, int KB, bool K1>
+// K1: k == 1, so the x offset is a shift; V4: k and r0 are multiples of 4,
+// so x is gathered and y stored four columns at a time).
+template <int FMT, bool CWAVE, int KB, bool K1, bool V4 = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
   Lane ln;
   if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
@@ -44,12 +45,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
 #pragma unroll
   for (int r = 0; r < KB; ++r) acc[r] = 0.0f;
   const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)a.C;
-  packsell_row<FMT, KB>(a.pack + ln.s + ln.l, stride, ln.w, left_offset32(t, a.geo), a.cd,
-                        [&](uint32_t c, int r) {
-                          const uint32_t xo = K1 ? (c << 2) : (c * kx + x0 + 4u * r);
-                          return buffer_load_f32(rx, xo);
-                        },
-                        acc);
+  if constexpr (V4) {
+    packsell_row_v4<FMT, KB>(a.pack + ln.s + ln.l, stride, ln.w, left_offset32(t, a.geo), a.cd,
+                             [&](uint32_t c, int g) {
+                               return buffer_load_f32x4(rx, c * kx + x0 + 16u * g);
+                             },
+                             acc);
+  } else {
+    packsell_row<FMT, KB>(a.pack + ln.s + ln.l, stride, ln.w, left_offset32(t, a.geo), a.cd,
+                          [&](uint32_t c, int r) {
+                            const uint32_t xo = K1 ? (c << 2) : (c * kx + x0 + 4u * r);
+                            return buffer_load_f32(rx, xo);
+                          },
+                          acc);
+  }
   if (t >= a.n) return;
   if constexpr (FMT == PKSELL_FIX) {
     const int sh = (int)a.row_exp[t] - (a.cd.D + 1);
@@ -57,8 +66,141 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
     for (int r = 0; r < KB; ++r) acc[r] = ldexpf(acc[r], sh);
   }
   const int64_t o = (int64_t)out_row(a.perm, a.perm_bytes, t, a.geo) * a.k + a.r0;
+  if constexpr (V4) {
+    f32x4 *yo = reinterpret_cast<f32x4 *>(a.y + o);
 #pragma unroll
-  for (int r = 0; r < KB; ++r) a.y[o + r] = acc[r];
+    for (int g = 0; g < KB / 4; ++g)
+      yo[g] = f32x4{acc[4 * g], acc[4 * g + 1], acc[4 * g + 2], acc[4 * g + 3]};
+  } else {
+#pragma unroll
+    for (int r = 0; r < KB; ++r) a.y[o + r] = acc[r];
+  }
+}
+
+// C = 64, k = 1: each wave walks two consecutive slices together, so the
+// words (and then the gathers) of both are in flight at once -- more bytes
+// per wave between its dependent loads (offsets, words, x) than one slice
+// gives.  Same arithmetic, in the same word order per row, as k_spmv.
+constexpr int kPairBlock = 128;
+
+template <int FMT>
+__global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
+  constexpr int S = 2;
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(b * (kPairBlock / kWave) + threadIdx.x / kWave);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t k0 = wave * S;
+  if (k0 >= a.n_slices) return;
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 4u);
+  int64_t off[S + 1];
+#pragma unroll
+  for (int i = 0; i <= S; ++i) off[i] = a.offset[min(k0 + i, a.n_slices)];
+  uint32_t w[S], c[S], wm = 0;
+  float acc[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    w[i] = (uint32_t)((off[i + 1] - off[i]) >> 6);
+    wm = max(wm, w[i]);
+    c[i] = left_offset32((k0 + i) * kWave + lane, a.geo);
+    acc[i] = 0.0f;
+  }
+  for (uint32_t j = 0; j < wm; j += kUnroll) {
+    uint32_t p[S][kUnroll];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        uint32_t v = 0u;  // past the slice's width: a padding word
+        if (j + q < w[i]) v = __builtin_nontemporal_load(a.pack + off[i] + lane + (j + q) * kWave);
+        p[i][q] = v;
+      }
+    uint32_t cq[S][kUnroll];
+    float v[S][kUnroll];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const Unpacked u = unpack(p[i][q], a.cd);
+        c[i] += u.delta;
+        cq[i][q] = c[i];
+        v[i][q] = decode_value<FMT>(u.vbits);
+      }
+    float xv[S][kUnroll];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) xv[i][q] = buffer_load_f32(rx, cq[i][q] << 2);
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) acc[i] = fmaf(v[i][q], xv[i][q], acc[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    const uint32_t t = (k0 + i) * kWave + lane;
+    if (k0 + i >= a.n_slices || t >= a.n) continue;
+    float r = acc[i];
+    if constexpr (FMT == PKSELL_FIX) r = ldexpf(r, (int)a.row_exp[t] - (a.cd.D + 1));
+    a.y[out_row(a.perm, a.perm_bytes, t, a.geo)] = r;
+  }
+}
+
+// Wide-slice splitting (C = 64, k = 1): one wave per work unit {slice,
+// chunk, chunks, base}.  A unit of an unsplit slice (chunks == 1) is the
+// whole slice and stores y; a chunk of a split slice starts from the column
+// recorded by the encoder for that chunk and stores its float32 sum in
+// ``partial``.  k_combine_chunks then adds each split slice's chunk sums in
+// chunk order, so the result is deterministic; it differs from the unsplit
+// sum only in rounding order.
+struct UnitArgs {
+  const uint32_t *units;
+  const uint32_t *splits;
+  const uint32_t *ckpt;
+  float *partial;
+  uint32_t n_units, n_split_slices, J;
+};
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_spmv_units(SpmvArgs a, UnitArgs u) {
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t unit = __builtin_amdgcn_readfirstlane(b * (kBlock / kWave) + threadIdx.x / kWave);
+  if (unit >= u.n_units) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t k = u.units[4 * unit], c = u.units[4 * unit + 1];
+  const uint32_t chunks = u.units[4 * unit + 2], base = u.units[4 * unit + 3];
+  const int64_t s = a.offset[k];
+  const uint32_t w = (uint32_t)((a.offset[k + 1] - s) >> 6);
+  const uint32_t j0 = c * u.J;
+  const uint32_t wl = chunks == 1 ? w : min(u.J, w - j0);
+  const uint32_t t = k * kWave + lane;
+  const uint32_t c0 = chunks == 1 ? left_offset32(t, a.geo) : u.ckpt[(base + c) * kWave + lane];
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 4u);
+  float acc[1] = {0.0f};
+  packsell_row<FMT, 1>(a.pack + s + (int64_t)j0 * kWave + lane, kWave, wl, c0, a.cd,
+                       [&](uint32_t col, int) { return buffer_load_f32(rx, col << 2); }, acc);
+  if (chunks > 1) {
+    u.partial[(base + c) * kWave + lane] = acc[0];
+    return;
+  }
+  if (t >= a.n) return;
+  float r = acc[0];
+  if constexpr (FMT == PKSELL_FIX) r = ldexpf(r, (int)a.row_exp[t] - (a.cd.D + 1));
+  a.y[out_row(a.perm, a.perm_bytes, t, a.geo)] = r;
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_combine_chunks(SpmvArgs a, UnitArgs u) {
+  const uint32_t sp = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
+  if (sp >= u.n_split_slices) return;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t k = u.splits[4 * sp], base = u.splits[4 * sp + 1], chunks = u.splits[4 * sp + 2];
+  const uint32_t t = k * kWave + lane;
+  if (t >= a.n) return;
+  float r = 0.0f;
+  for (uint32_t c = 0; c < chunks; ++c) r += u.partial[(base + c) * kWave + lane];
+  if constexpr (FMT == PKSELL_FIX) r = ldexpf(r, (int)a.row_exp[t] - (a.cd.D + 1));
+  a.y[out_row(a.perm, a.perm_bytes, t, a.geo)] = r;
 }
 
 // Word-by-word decode: the column reached at each word position and the
@@ -160,11 +302,32 @@ int check_matrix(const pksell_matrix *A) {
 template <int FMT, bool CW>
 int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, hipStream_t st) {
   if (k == 1) {
-    k_spmv<FMT, CW, 1, true><<<grid, kBlock, 0, st>>>(base);
+    if constexpr (CW) {
+      const int64_t waves = cdiv(base.n_slices, 2);
+      k_spmv_pair<FMT><<<cdiv(waves, kPairBlock / kWave), kPairBlock, 0, st>>>(base);
+    } else {
+      k_spmv<FMT, CW, 1, true><<<grid, kBlock, 0, st>>>(base);
+    }
     PKS_LAUNCHED();
     return PKSELL_OK;
   }
   int64_t r0 = 0;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(base.x) | reinterpret_cast<uintptr_t>(base.y)) & 15) == 0;
+  if (k % 4 == 0 && aligned) {  // 16-byte gathers and stores
+    while (r0 < k) {
+      SpmvArgs a = base;
+      a.r0 = (int32_t)r0;
+      if (k - r0 >= 8) {
+        k_spmv<FMT, CW, 8, false, true><<<grid, kBlock, 0, st>>>(a);
+        r0 += 8;
+      } else {
+        k_spmv<FMT, CW, 4, false, true><<<grid, kBlock, 0, st>>>(a);
+        r0 += 4;
+      }
+      PKS_LAUNCHED();
+    }
+    return PKSELL_OK;
+  }
   while (r0 < k) {
     SpmvArgs a = base;
     a.r0 = (int32_t)r0;
@@ -191,6 +354,16 @@ template <int FMT>
 int launch_fmt(const SpmvArgs &a, int64_t grid, int64_t k, int32_t C, hipStream_t st) {
   return C == kWave ? launch_fmt_cw<FMT, true>(a, grid, k, st)
                     : launch_fmt_cw<FMT, false>(a, grid, k, st);
+}
+
+template <int FMT>
+int launch_units(const SpmvArgs &a, const UnitArgs &u, hipStream_t st) {
+  constexpr int wpb = kBlock / kWave;
+  k_spmv_units<FMT><<<cdiv(u.n_units, wpb), kBlock, 0, st>>>(a, u);
+  PKS_LAUNCHED();
+  k_combine_chunks<FMT><<<cdiv(u.n_split_slices, wpb), kBlock, 0, st>>>(a, u);
+  PKS_LAUNCHED();
+  return PKSELL_OK;
 }
 
 }  // namespace
@@ -222,6 +395,19 @@ int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, voi
   if (A->m == 0) return zero_f32(y, A->n * k, st);
   PKS_CHECK(x, PKSELL_EINVAL, "null x");
   SpmvArgs a = make_args(A, x, y, k);
+  if (k == 1 && A->C == kWave && A->split_words > 0 && A->n_split_units > 0) {
+    PKS_CHECK(A->units && A->splits && A->ckpt && A->partial, PKSELL_EINVAL,
+              "split slices need units, splits, ckpt and partial");
+    PKS_CHECK(A->n_units < (int64_t(1) << 31) && A->n_split_units * kWave < (int64_t(1) << 32),
+              PKSELL_ERANGE, "too many work units");
+    UnitArgs u{A->units, A->splits, A->ckpt, A->partial, (uint32_t)A->n_units,
+               (uint32_t)A->n_split_slices, (uint32_t)A->split_words};
+    switch (A->fmt) {
+      case PKSELL_FP16: return launch_units<PKSELL_FP16>(a, u, st);
+      case PKSELL_E8MY: return launch_units<PKSELL_E8MY>(a, u, st);
+      default: return launch_units<PKSELL_FIX>(a, u, st);
+    }
+  }
   const int64_t grid = cdiv(A->n_slices * A->C, kBlock);
   switch (A->fmt) {
     case PKSELL_FP16: return launch_fmt<PKSELL_FP16>(a, grid, k, A->C, st);

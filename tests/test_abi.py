@@ -80,3 +80,19 @@ def test_sell_query_rejects_bad_dtype():
     rc = B.lib().pksell_sell_query(10, 10, 10, 64, 256, 2, B.IMPLICIT, ctypes.byref(desc),
                                    ctypes.byref(ws))
     assert rc == B.EINVAL
+
+
+@pytest.mark.parametrize("C,J", [(64, 12), (64, 4), (64, 1 << 25), (32, 64), (64, -8)])
+def test_encode_rejects_bad_split_words(C, J):
+    """The split check runs on the host before any device work, so dummy
+    host buffers stand in for the device arrays."""
+    rc, desc, ws = _query(n=100, C=C)
+    assert rc == 0
+    desc.split_words = J
+    buf = (ctypes.c_uint8 * max(ws, 4096))()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    desc.offset = p
+    desc.perm = p
+    rc = B.lib().pksell_encode(p, p, p, B.F32, ctypes.byref(desc), p, max(ws, 4096), None)
+    assert rc == B.EINVAL
+    assert b"split_words" in B.lib().pksell_last_error()
