@@ -255,6 +255,7 @@ def main():
 
     if not args.no_adjoint and "packsell_fp16" in results:
         out["adjoint"] = adjoint_leg(args, a, results["packsell_fp16"]["A"], torch, B, W)
+        out["multi_rhs"] = multirhs_leg(args, a, results["packsell_fp16"]["A"], torch, B, W)
     out["encode_ms"] = encode_leg(a, torch, B)
     if not args.no_extra:
         out["powerlaw"] = powerlaw_leg(args, torch, B, W)
@@ -374,6 +375,28 @@ def block_leg(args, torch, B, W):
     EXTRA_CHECKS.append(("block3_27pt", a, x_np, {"packsell_e8m20": B.spmv(A, x).cpu().numpy(),
                                                   "sell_fp32": B.sell_spmv(S, x).cpu().numpy()}))
     log(f"[bench] block3_27pt: {res}")
+    return res
+
+
+def multirhs_leg(args, a, A, torch, B, W):
+    """Y = A_q X on the headline matrix for k = 8 and 32 right-hand sides
+    (row-major blocks; lane groups of 2 and 8 lanes per row)."""
+    dev = A.device
+    res = {}
+    for k in (8, 32):
+        per = A.bytes_per_spmv(k)
+        R = max(2, int(math.ceil(args.replica_bytes / per)))
+        reps = [A] + [A.replicate() for _ in range(R - 1)]
+        xs = [torch.from_numpy(W.uniform_vector(a.m, 20 + i, k=k)).to(dev) for i in range(R)]
+        ys = [torch.empty((a.n, k), device=dev) for _ in range(R)]
+        steps = max(R, min(args.steps, 100) // R * R)
+        ms = Timed(torch, lambda i: B.spmv(reps[i], xs[i], ys[i]), R, steps,
+                   min(args.warmup, 10)).run()
+        res[f"k{k}"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
+                        "GFLOP/s": round(2 * a.nnz * k / (ms * 1e-3) / 1e9, 1), "bytes": per,
+                        "replicas": R}
+        log(f"[bench] single-matrix k={k}: {res[f'k{k}']}")
+        del reps, xs, ys
     return res
 
 

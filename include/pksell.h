@@ -246,10 +246,10 @@ typedef struct pksell_batch_item {
  * plan workspace on the device). */
 typedef struct pksell_batch {
   int32_t count, fmt, k, transpose;
-  int64_t total_units;      /* slices over all matrices */
-  int32_t units_per_wave, waves;
+  int64_t total_units;      /* work units over all matrices: slices x group */
+  int32_t units_per_wave, waves;  /* wave w takes units w, w + waves, ... */
   int32_t vec4;             /* k % 4 == 0 and 16-byte aligned blocks: 16-byte gathers */
-  int32_t reserved;
+  int32_t group;            /* lanes per row: L = 2..16 (forward, vec4, k >= 8), else 1 */
   void *items;
   void *unit_start;
 } pksell_batch;
@@ -264,7 +264,8 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
                       int32_t transpose, pksell_batch *plan, void *ws,
                       size_t ws_bytes, void *stream);
 
-/* Runs a plan: one persistent launch per pass of up to 32 right-hand sides
+/* Runs a plan: one persistent launch (lane groups, group > 1: every k in one
+ * pass; otherwise one launch per pass of up to 32 right-hand sides)
  * (a transposed plan first zeroes its outputs with a kernel, then scatters
  * with float32 atomics).  Asynchronous, and safe to capture in a graph. */
 int pksell_spmv_batched(const pksell_batch *plan, void *stream);

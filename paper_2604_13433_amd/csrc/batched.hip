@@ -3,10 +3,14 @@
 //
 // The plan flattens every (matrix, slice) pair into one list of work units
 // (slice counts prefix-summed per matrix) and stores one descriptor per
-// matrix in device memory.  Each wave of a fixed, chip-filling grid takes a
-// contiguous run of units, finds the matrix of its first unit once and
+// matrix in device memory.  Each wave of a fixed, chip-filling grid takes
+// every W-th unit (W = the grid's wave count), so at any moment the
+// resident waves work on one contiguous window of units and share the x
+// rows it touches in L2; a wave finds the matrix of its first unit once and
 // walks on; each unit is one slice (C = 64, a wave) processed like the
-// single-matrix product, with k right-hand sides in passes of up to KB.
+// single-matrix product, with k right-hand sides in passes of up to KB --
+// or, for forward products with k a multiple of 4 and k >= 8, a 64 / L-row
+// part of a slice in lane groups of L lanes per row (all k in one pass).
 // The transposed product scatters with float32 atomics after zeroing its
 // outputs in a separate launch.  Launches read only the device table, so
 // they can be captured into a graph and replayed.
@@ -60,15 +64,18 @@ __device__ inline void do_unit(const Item &it, uint32_t k_slice, uint32_t lane, 
     float acc[KB];
 #pragma unroll
     for (int r = 0; r < KB; ++r) acc[r] = 0.0f;
+    const uint32_t oob = it.m * kx;  // flag-0 words: past the resource, no request
     if constexpr (V4) {
       packsell_row_v4<FMT, KB>(P, kWave, w, c, it.cd,
-                               [&](uint32_t cc, int g) {
-                                 return buffer_load_f32x4(rx, cc * kx + x0 + 16u * g);
+                               [&](uint32_t cc, int g, bool live) {
+                                 return buffer_load_f32x4(rx, live ? cc * kx + x0 + 16u * g : oob);
                                },
                                acc);
     } else {
       packsell_row<FMT, KB>(P, kWave, w, c, it.cd,
-                            [&](uint32_t cc, int r) { return buffer_load_f32(rx, cc * kx + x0 + 4u * r); },
+                            [&](uint32_t cc, int r, bool live) {
+                              return buffer_load_f32(rx, live ? cc * kx + x0 + 4u * r : oob);
+                            },
                             acc);
     }
     if (t < it.n) {
@@ -109,19 +116,199 @@ __device__ inline void do_unit(const Item &it, uint32_t k_slice, uint32_t lane, 
 template <int FMT, int KB, bool TRANS, bool V4>
 __global__ __launch_bounds__(kB) void k_batched(const Item *__restrict__ items,
                                                const uint32_t *__restrict__ unit_start,
-                                               uint32_t count, uint32_t total, uint32_t per_wave,
-                                               int k, int r0) {
+                                               uint32_t count, uint32_t total, int k, int r0) {
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(b * (kB / kWave) + threadIdx.x / kWave);
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  uint32_t u = wave * per_wave;
-  const uint32_t u1 = min(u + per_wave, total);
-  if (u >= u1) return;
+  const uint32_t stride = gridDim.x * (kB / kWave);
+  uint32_t u = wave;
+  if (u >= total) return;
   uint32_t it = find_item(unit_start, count, u);
-  for (; u < u1; ++u) {
+  for (; u < total; u += stride) {
     while (u >= unit_start[it + 1]) ++it;
     do_unit<FMT, KB, TRANS, V4>(items[it], u - unit_start[it], lane, k, r0);
   }
+}
+
+// Software-pipelined persistent loop for k = 1 (L = 1: one lane per row)
+// and for lane groups (L >= 2, k a multiple of 4, aligned): while the
+// gathers of unit u are in flight, the slice bounds and the first eight
+// words of unit u + 1 are already loading, so a wave pays about one memory
+// round trip per unit instead of two.  Same arithmetic, in the same word
+// order, as the single-matrix kernels.
+struct Unit {
+  uint32_t item, ks, l, q, w;
+  bool live;
+  int64_t s;
+};
+
+template <int L>
+__device__ inline Unit unit_at(const Item *items, const uint32_t *unit_start, uint32_t item,
+                               uint32_t u, uint32_t lane, uint32_t k4) {
+  Unit x;
+  x.item = item;
+  const uint32_t ul = u - unit_start[item];
+  if constexpr (L == 1) {
+    x.ks = ul;
+    x.l = lane;
+    x.q = 0;
+    x.live = true;
+  } else {
+    x.ks = ul / L;
+    const GroupLane g = group_lane<L>(ul % L, lane, k4);
+    x.l = g.l;
+    x.q = g.q;
+    x.live = g.live;
+  }
+  const Item &I = items[item];
+  x.s = I.offset[x.ks];
+  x.w = (uint32_t)((I.offset[x.ks + 1] - x.s) >> 6);
+  return x;
+}
+
+// Words j .. j+7 of a slice lane (w is wave-uniform; words past w are
+// padding).  Nontemporal when one wave reads each word (L = 1).
+template <bool NT>
+__device__ inline void load_words(const uint32_t *P, uint32_t w, uint32_t j,
+                                  uint32_t (&p)[kUnroll]) {
+#pragma unroll
+  for (int q = 0; q < kUnroll; ++q) {
+    uint32_t v = 0u;
+    if (j + q < w) v = load_word<NT>(P + (j + q) * kWave);
+    p[q] = v;
+  }
+}
+
+// Decode eight words and accumulate; flag-0 words gather at ``oob`` (past
+// the resource: 0, no memory request).
+template <int FMT, int L, int NA>
+__device__ inline void fma_words(const uint32_t (&p)[kUnroll], uint32_t &c, const Codec &cd,
+                                 __amdgpu_buffer_rsrc_t rx, uint32_t kx, uint32_t xq,
+                                 uint32_t oob, float (&acc)[NA]) {
+  uint32_t cq[kUnroll];
+  float v[kUnroll];
+#pragma unroll
+  for (int q = 0; q < kUnroll; ++q) {
+    const Unpacked u = unpack(p[q], cd);
+    c += u.delta;
+    cq[q] = c;
+    v[q] = decode_value<FMT>(u.vbits);
+  }
+  if constexpr (L == 1) {
+    float xv[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) xv[q] = buffer_load_f32(rx, (p[q] & 1u) ? cq[q] << 2 : oob);
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) acc[0] = fmaf(v[q], xv[q], acc[0]);
+  } else {
+    f32x4 xv[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q)
+      xv[q] = buffer_load_f32x4(rx, (p[q] & 1u) ? cq[q] * kx + xq : oob);
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      acc[0] = fmaf(v[q], xv[q].x, acc[0]);
+      acc[1] = fmaf(v[q], xv[q].y, acc[1]);
+      acc[2] = fmaf(v[q], xv[q].z, acc[2]);
+      acc[3] = fmaf(v[q], xv[q].w, acc[3]);
+    }
+  }
+}
+
+template <int FMT, int L>
+__global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ items,
+                                                    const uint32_t *__restrict__ unit_start,
+                                                    uint32_t count, uint32_t total, int k) {
+  constexpr int NA = L == 1 ? 1 : 4;
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(b * (kB / kWave) + threadIdx.x / kWave);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t stride = gridDim.x * (kB / kWave);
+  uint32_t u = wave;
+  if (u >= total) return;
+  const uint32_t k4 = (uint32_t)k >> 2, kx = (uint32_t)k * 4u;
+  Unit cur = unit_at<L>(items, unit_start, find_item(unit_start, count, u), u, lane, k4);
+  constexpr bool NT = L == 1;
+  uint32_t p[kUnroll];
+  load_words<NT>(items[cur.item].pack + cur.s + cur.l, cur.w, 0, p);
+  for (;;) {
+    const bool more = u + stride < total;
+    Unit nx;
+    uint32_t pn[kUnroll];
+    if (more) {  // the next unit's bounds and first words, before this unit's gathers
+      uint32_t itn = cur.item;
+      while (u + stride >= unit_start[itn + 1]) ++itn;
+      nx = unit_at<L>(items, unit_start, itn, u + stride, lane, k4);
+      load_words<NT>(items[itn].pack + nx.s + nx.l, nx.w, 0, pn);
+    }
+    const Item &I = items[cur.item];
+    const uint32_t t = cur.ks * kWave + cur.l;
+    const __amdgpu_buffer_rsrc_t rx = make_rsrc(I.in, I.m * kx);
+    const uint32_t xq = 16u * cur.q;
+    uint32_t c = left_offset32(t, I.geo);
+    float acc[NA];
+#pragma unroll
+    for (int r = 0; r < NA; ++r) acc[r] = 0.0f;
+    const uint32_t oob = I.m * kx;
+    fma_words<FMT, L, NA>(p, c, I.cd, rx, kx, xq, oob, acc);
+    for (uint32_t j = kUnroll; j < cur.w; j += kUnroll) {  // slices wider than one group
+      uint32_t pr[kUnroll];
+      load_words<NT>(I.pack + cur.s + cur.l, cur.w, j, pr);
+      fma_words<FMT, L, NA>(pr, c, I.cd, rx, kx, xq, oob, acc);
+    }
+    if (t < I.n && cur.live) {
+      if constexpr (FMT == PKSELL_FIX) {
+        const int sh = (int)I.row_exp[t] - (I.cd.D + 1);
+#pragma unroll
+        for (int r = 0; r < NA; ++r) acc[r] = ldexpf(acc[r], sh);
+      }
+      const uint32_t row = out_row(I.perm, I.perm_bytes, t, I.geo);
+      if constexpr (L == 1) {
+        I.out[row] = acc[0];
+      } else {
+        *reinterpret_cast<f32x4 *>(I.out + (int64_t)row * k + 4 * cur.q) =
+            f32x4{acc[0], acc[1], acc[2], acc[3]};
+      }
+    }
+    if (!more) break;
+    cur = nx;
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) p[q] = pn[q];
+    u += stride;
+  }
+}
+
+typedef void (*PipeKernel)(const Item *, const uint32_t *, uint32_t, uint32_t, int);
+
+template <int FMT>
+PipeKernel k_batched_pipe_for(int L) {
+  switch (L) {
+    case 1: return k_batched_pipe<FMT, 1>;
+    case 2: return k_batched_pipe<FMT, 2>;
+    case 4: return k_batched_pipe<FMT, 4>;
+    case 8: return k_batched_pipe<FMT, 8>;
+    default: return k_batched_pipe<FMT, 16>;
+  }
+}
+
+// Forward products with k = 1 or with lane groups run the pipelined loop;
+// transposed products and other k run k_batched in passes.
+bool uses_pipe(const pksell_batch &p) { return !p.transpose && (p.k == 1 || p.group > 1); }
+
+// Workgroups of the batched kernel that fit on one CU at once.
+int resident_blocks(const pksell_batch &p) {
+  const void *fn = nullptr;
+  if (uses_pipe(p)) {
+    fn = p.fmt == PKSELL_FP16   ? (const void *)k_batched_pipe_for<PKSELL_FP16>(p.group)
+         : p.fmt == PKSELL_E8MY ? (const void *)k_batched_pipe_for<PKSELL_E8MY>(p.group)
+                                : (const void *)k_batched_pipe_for<PKSELL_FIX>(p.group);
+  } else {
+    fn = (const void *)k_batched<PKSELL_E8MY, 8, false, false>;  // the largest pass kernel
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kB, 0) != hipSuccess || nb < 1)
+    nb = 1;
+  return nb;
 }
 
 template <typename T>
@@ -160,6 +347,13 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
   std::vector<Item> host((size_t)count);
   std::vector<uint32_t> start((size_t)count + 1, 0);
   int fmt = -1;
+  // 16-byte gathers and stores need k % 4 == 0 and 16-byte aligned blocks;
+  // forward products with k >= 8 then use lane groups of L lanes per row
+  bool aligned = k % 4 == 0;
+  for (int32_t i = 0; i < count; ++i)
+    aligned &= ((reinterpret_cast<uintptr_t>(items[i].in) |
+                 reinterpret_cast<uintptr_t>(items[i].out)) & 15) == 0;
+  const int L = (aligned && !transpose && k >= 8) ? group_size(k) : 1;  // lanes per row
   for (int32_t i = 0; i < count; ++i) {
     const pksell_matrix *A = items[i].A;
     PKS_CHECK(A, PKSELL_EINVAL, "item %d: null matrix", i);
@@ -185,8 +379,9 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
     h.perm_bytes = (uint32_t)A->perm_bytes;
     h.geo = make_geo(A->sigma, A->k_left, A->C);
     h.cd = make_codec(A->D);
-    start[(size_t)i + 1] = start[(size_t)i] + (uint32_t)A->n_slices;
-    PKS_CHECK(start[(size_t)i + 1] >= start[(size_t)i], PKSELL_ERANGE, "too many slices");
+    const int64_t next = (int64_t)start[(size_t)i] + A->n_slices * L;
+    PKS_CHECK(next < (int64_t(1) << 32), PKSELL_ERANGE, "too many work units");
+    start[(size_t)i + 1] = (uint32_t)next;
   }
   Carver cv(ws);
   Item *dev_items = cv.take<Item>((size_t)count);
@@ -205,18 +400,15 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
   plan->fmt = fmt;
   plan->k = (int32_t)k;
   plan->transpose = transpose ? 1 : 0;
-  // 16-byte gathers and stores need k % 4 == 0 and 16-byte aligned blocks
-  bool aligned = k % 4 == 0;
-  for (int32_t i = 0; i < count; ++i)
-    aligned &= ((reinterpret_cast<uintptr_t>(items[i].in) |
-                 reinterpret_cast<uintptr_t>(items[i].out)) & 15) == 0;
   plan->vec4 = aligned ? 1 : 0;
+  plan->group = L;
   plan->total_units = start[(size_t)count];
-  // a chip-filling grid: 8 waves per SIMD, 4 SIMDs per CU
-  const int64_t max_waves = (int64_t)cus * 32;
+  // a chip-filling grid: as many workgroups as fit on every CU at once
+  const int64_t max_waves = (int64_t)cus * resident_blocks(*plan) * (kB / kWave);
   const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(plan->total_units, max_waves));
   plan->units_per_wave = (int32_t)cdiv(std::max<int64_t>(1, plan->total_units), waves);
-  plan->waves = (int32_t)cdiv(std::max<int64_t>(1, plan->total_units), plan->units_per_wave);
+  plan->waves = (int32_t)waves;
+  PKS_CHECK(plan->total_units + 4 * waves < (int64_t(1) << 32), PKSELL_ERANGE, "too many work units");
   plan->items = dev_items;
   plan->unit_start = dev_start;
   return PKSELL_OK;
@@ -234,15 +426,25 @@ int pksell_spmv_batched(const pksell_batch *plan, void *stream) {
   }
   if (plan->total_units == 0) return PKSELL_OK;
   const int64_t grid = cdiv(plan->waves, kB / kWave);
-  const uint32_t cnt = (uint32_t)plan->count, tot = (uint32_t)plan->total_units,
-                 pw = (uint32_t)plan->units_per_wave;
+  const uint32_t cnt = (uint32_t)plan->count, tot = (uint32_t)plan->total_units;
   // 16-byte gathers and stores when every x / y row group is aligned
   const bool v4 = plan->vec4 && !plan->transpose;
+  if (uses_pipe(*plan)) {
+    PKS_CHECK(plan->group == 1 || (v4 && k >= 8 && plan->group == group_size(k)), PKSELL_EINVAL,
+              "bad plan");
+    switch (plan->fmt) {
+      case PKSELL_FP16: k_batched_pipe_for<PKSELL_FP16>(plan->group)<<<grid, kB, 0, st>>>(items, start, cnt, tot, k); break;
+      case PKSELL_E8MY: k_batched_pipe_for<PKSELL_E8MY>(plan->group)<<<grid, kB, 0, st>>>(items, start, cnt, tot, k); break;
+      default: k_batched_pipe_for<PKSELL_FIX>(plan->group)<<<grid, kB, 0, st>>>(items, start, cnt, tot, k); break;
+    }
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
   for (int r0 = 0; r0 < k;) {
     const int left = k - r0;
     const int kb = left >= 32 ? 32 : left >= 8 ? 8 : 1;
 #define PKS_B(F, KB, T, V) \
-  k_batched<F, KB, T, V><<<grid, kB, 0, st>>>(items, start, cnt, tot, pw, k, r0)
+  k_batched<F, KB, T, V><<<grid, kB, 0, st>>>(items, start, cnt, tot, k, r0)
 #define PKS_BK(F, T)                                  \
   do {                                                \
     if (kb == 32) {                                   \

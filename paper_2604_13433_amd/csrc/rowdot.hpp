@@ -44,14 +44,25 @@ __device__ inline bool lane_slice(const int64_t *offset, uint32_t n_slices, cons
   return true;
 }
 
+// Word load: nontemporal when each word is read once (the stream should
+// not evict x from the caches), plain when several waves share the words.
+template <bool NT>
+__device__ inline uint32_t load_word(const uint32_t *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 // The PackSELL row loop (sec. 4.4) for one lane: walks the w words of its
 // slice lane in groups of kUnroll -- all loads of a group in flight
 // together, columns as running sums of deltas from c, then all gathers
 // together, then the products accumulated in word order.  The last partial
 // group re-reads the lane's last word (clamped, in bounds) and turns the
-// extra words into padding (delta 0, value 0).  ``gather(c, r)`` returns the
-// operand for column c and right-hand side r.
-template <int FMT, int KB, typename Gather>
+// extra words into padding (delta 0, value 0).  ``gather(c, r, live)``
+// returns the operand for column c and right-hand side r; live is false for
+// flag-0 words (dummies and padding, value 0), whose gather the callers
+// point past the end of their buffer resource so that it returns 0 without
+// a memory request.
+template <int FMT, int KB, bool NT = true, typename Gather>
 __device__ inline void packsell_row(const uint32_t *P, uint32_t stride, uint32_t w, uint32_t c,
                                     const Codec &cd, Gather gather, float (&acc)[KB]) {
   auto group = [&](uint32_t j, bool full) {
@@ -59,7 +70,7 @@ __device__ inline void packsell_row(const uint32_t *P, uint32_t stride, uint32_t
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
       const uint32_t jj = full ? j + q : min(j + q, w - 1);
-      p[q] = __builtin_nontemporal_load(P + jj * stride);
+      p[q] = load_word<NT>(P + jj * stride);
       if (!full && j + q >= w) p[q] = 0u;
     }
     uint32_t cq[kUnroll];
@@ -75,7 +86,7 @@ __device__ inline void packsell_row(const uint32_t *P, uint32_t stride, uint32_t
     for (int r = 0; r < KB; ++r) {
       float xv[kUnroll];
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) xv[q] = gather(cq[q], r);
+      for (int q = 0; q < kUnroll; ++q) xv[q] = gather(cq[q], r, (p[q] & 1u) != 0u);
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) acc[r] = fmaf(v[q], xv[q], acc[r]);
     }
@@ -94,9 +105,9 @@ __device__ inline f32x4 buffer_load_f32x4(__amdgpu_buffer_rsrc_t r, uint32_t byt
 }
 
 // packsell_row for KB right-hand sides (KB a multiple of 4) gathered four at
-// a time: ``gather4(c, g)`` returns columns 4g .. 4g+3 of x row c.  Each
-// accumulator still adds its products in word order.
-template <int FMT, int KB, typename Gather4>
+// a time: ``gather4(c, g, live)`` returns columns 4g .. 4g+3 of x row c.
+// Each accumulator still adds its products in word order.
+template <int FMT, int KB, bool NT = true, typename Gather4>
 __device__ inline void packsell_row_v4(const uint32_t *P, uint32_t stride, uint32_t w, uint32_t c,
                                        const Codec &cd, Gather4 gather4, float (&acc)[KB]) {
   static_assert(KB % 4 == 0, "KB must be a multiple of 4");
@@ -105,7 +116,7 @@ __device__ inline void packsell_row_v4(const uint32_t *P, uint32_t stride, uint3
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
       const uint32_t jj = full ? j + q : min(j + q, w - 1);
-      p[q] = __builtin_nontemporal_load(P + jj * stride);
+      p[q] = load_word<NT>(P + jj * stride);
       if (!full && j + q >= w) p[q] = 0u;
     }
     uint32_t cq[kUnroll];
@@ -121,7 +132,7 @@ __device__ inline void packsell_row_v4(const uint32_t *P, uint32_t stride, uint3
     for (int g = 0; g < KB / 4; ++g) {
       f32x4 xv[kUnroll];
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) xv[q] = gather4(cq[q], g);
+      for (int q = 0; q < kUnroll; ++q) xv[q] = gather4(cq[q], g, (p[q] & 1u) != 0u);
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
         acc[4 * g + 0] = fmaf(v[q], xv[q].x, acc[4 * g + 0]);
@@ -134,6 +145,36 @@ __device__ inline void packsell_row_v4(const uint32_t *P, uint32_t stride, uint3
   uint32_t j = 0;
   for (; j + kUnroll <= w; j += kUnroll) group(j, true);
   if (j < w) group(j, false);
+}
+
+// Lane groups for k right-hand sides (k a multiple of 4): L lanes (a power
+// of two, 4L >= k) share one row and lane q of the group owns columns
+// 4q .. 4q+3, so a group gathers one contiguous 16L-byte piece of x row c
+// per word (one cache line at k = 32) instead of L separate pieces, and
+// any k <= 64 is one pass over the words.  A wave holds 64 / L rows; lanes
+// with 4q >= k repeat the last live lane's loads (same addresses) and store
+// nothing.  h selects which 64 / L rows of the slice the wave takes.
+struct GroupLane {
+  uint32_t l;  // row within the slice
+  uint32_t q;  // column group (clamped to k / 4 - 1)
+  bool live;   // owns columns 4q .. 4q+3
+};
+
+template <int L>
+__device__ inline GroupLane group_lane(uint32_t h, uint32_t lane, uint32_t k4) {
+  static_assert(L >= 2 && L <= 16 && (L & (L - 1)) == 0, "L must be 2, 4, 8 or 16");
+  GroupLane g;
+  g.l = h * (kWave / L) + lane / L;
+  const uint32_t q = lane % L;
+  g.live = q < k4;
+  g.q = g.live ? q : k4 - 1;
+  return g;
+}
+
+// Smallest lane-group size L (2..16) with 4L >= k, for 8 <= k <= 64.
+inline int group_size(int64_t k) {
+  const int64_t k4 = (k + 3) / 4;
+  return k4 <= 2 ? 2 : k4 <= 4 ? 4 : k4 <= 8 ? 8 : 16;
 }
 
 }  // namespace pksell

@@ -174,9 +174,9 @@ __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restr
     float acc[1] = {0.0f};
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)A.C;
     packsell_row<FMT, 1>(A.pack + ln.s + ln.l, stride, ln.w, left_offset32(ln.t, A.geo), A.cd,
-                         [&](uint32_t c, int) {
-                           return fmaf(beta, buffer_load_f32(rp, c << 2),
-                                       buffer_load_f32(rr_r, c << 2));
+                         [&](uint32_t c, int, bool live) {
+                           const uint32_t o = live ? c << 2 : A.n * 4u;  // flag 0: no request
+                           return fmaf(beta, buffer_load_f32(rp, o), buffer_load_f32(rr_r, o));
                          },
                          acc);
     if (ln.t < A.n) {

@@ -41,21 +41,22 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
   const uint32_t t = ln.t;
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, (uint32_t)a.m * (uint32_t)a.k * 4u);
   const uint32_t kx = (uint32_t)a.k * 4u, x0 = (uint32_t)a.r0 * 4u;
+  const uint32_t oob = (uint32_t)a.m * kx;  // past the resource: returns 0, no request
   float acc[KB];
 #pragma unroll
   for (int r = 0; r < KB; ++r) acc[r] = 0.0f;
   const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)a.C;
   if constexpr (V4) {
     packsell_row_v4<FMT, KB>(a.pack + ln.s + ln.l, stride, ln.w, left_offset32(t, a.geo), a.cd,
-                             [&](uint32_t c, int g) {
-                               return buffer_load_f32x4(rx, c * kx + x0 + 16u * g);
+                             [&](uint32_t c, int g, bool live) {
+                               return buffer_load_f32x4(rx, live ? c * kx + x0 + 16u * g : oob);
                              },
                              acc);
   } else {
     packsell_row<FMT, KB>(a.pack + ln.s + ln.l, stride, ln.w, left_offset32(t, a.geo), a.cd,
-                          [&](uint32_t c, int r) {
+                          [&](uint32_t c, int r, bool live) {
                             const uint32_t xo = K1 ? (c << 2) : (c * kx + x0 + 4u * r);
-                            return buffer_load_f32(rx, xo);
+                            return buffer_load_f32(rx, live ? xo : oob);
                           },
                           acc);
   }
@@ -75,6 +76,38 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
 #pragma unroll
     for (int r = 0; r < KB; ++r) a.y[o + r] = acc[r];
   }
+}
+
+// C = 64, k a multiple of 4 and >= 8, 16-byte aligned x and y: lane groups
+// of L lanes per row (group_lane), one wave per (slice, h) with h < L.
+template <int FMT, int L>
+__global__ __launch_bounds__(kBlock) void k_spmv_group(SpmvArgs a) {
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(b * (kBlock / kWave) + threadIdx.x / kWave);
+  const uint32_t ks = wv / L, h = wv % L;
+  if (ks >= a.n_slices) return;
+  const GroupLane g = group_lane<L>(h, threadIdx.x & (kWave - 1), (uint32_t)a.k >> 2);
+  const uint32_t t = ks * kWave + g.l;
+  const int64_t s = a.offset[ks];
+  const uint32_t w = (uint32_t)((a.offset[ks + 1] - s) >> 6);
+  const uint32_t kx = (uint32_t)a.k * 4u, xq = 16u * g.q;
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * kx);
+  const uint32_t oob = a.m * kx;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  // the L waves of a slice share its words: plain (not nontemporal) loads
+  packsell_row_v4<FMT, 4, false>(a.pack + s + g.l, kWave, w, left_offset32(t, a.geo), a.cd,
+                                 [&](uint32_t c, int, bool live) {
+                                   return buffer_load_f32x4(rx, live ? c * kx + xq : oob);
+                                 },
+                                 acc);
+  if (t >= a.n || !g.live) return;
+  if constexpr (FMT == PKSELL_FIX) {
+    const int sh = (int)a.row_exp[t] - (a.cd.D + 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = ldexpf(acc[r], sh);
+  }
+  const int64_t o = (int64_t)out_row(a.perm, a.perm_bytes, t, a.geo) * a.k + 4 * g.q;
+  *reinterpret_cast<f32x4 *>(a.y + o) = f32x4{acc[0], acc[1], acc[2], acc[3]};
 }
 
 // C = 64, k = 1: each wave walks two consecutive slices together, so the
@@ -130,7 +163,8 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) xv[i][q] = buffer_load_f32(rx, cq[i][q] << 2);
+      for (int q = 0; q < kUnroll; ++q)
+        xv[i][q] = buffer_load_f32(rx, (p[i][q] & 1u) ? cq[i][q] << 2 : a.m * 4u);
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
@@ -178,7 +212,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_units(SpmvArgs a, UnitArgs u) {
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 4u);
   float acc[1] = {0.0f};
   packsell_row<FMT, 1>(a.pack + s + (int64_t)j0 * kWave + lane, kWave, wl, c0, a.cd,
-                       [&](uint32_t col, int) { return buffer_load_f32(rx, col << 2); }, acc);
+                       [&](uint32_t col, int, bool live) {
+                         return buffer_load_f32(rx, live ? col << 2 : a.m * 4u);
+                       },
+                       acc);
   if (chunks > 1) {
     u.partial[(base + c) * kWave + lane] = acc[0];
     return;
@@ -313,6 +350,20 @@ int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, hipStream_t st)
   }
   int64_t r0 = 0;
   const bool aligned = ((reinterpret_cast<uintptr_t>(base.x) | reinterpret_cast<uintptr_t>(base.y)) & 15) == 0;
+  if constexpr (CW) {
+    if (k % 4 == 0 && k >= 8 && aligned) {  // lane groups: one pass for every k
+      const int L = group_size(k);
+      const int64_t g = cdiv((int64_t)base.n_slices * L, kBlock / kWave);
+      switch (L) {
+        case 2: k_spmv_group<FMT, 2><<<g, kBlock, 0, st>>>(base); break;
+        case 4: k_spmv_group<FMT, 4><<<g, kBlock, 0, st>>>(base); break;
+        case 8: k_spmv_group<FMT, 8><<<g, kBlock, 0, st>>>(base); break;
+        default: k_spmv_group<FMT, 16><<<g, kBlock, 0, st>>>(base); break;
+      }
+      PKS_LAUNCHED();
+      return PKSELL_OK;
+    }
+  }
   if (k % 4 == 0 && aligned) {  // 16-byte gathers and stores
     while (r0 < k) {
       SpmvArgs a = base;

@@ -27,7 +27,7 @@ def encode_all(mats, D_of=lambda i: 9, fmt="e8my"):
             for i, a in enumerate(mats)]
 
 
-@pytest.mark.parametrize("k", [1, 3, 8, 32, 13])
+@pytest.mark.parametrize("k", [1, 3, 8, 12, 32, 13, 64])
 def test_batched_matches_single_and_oracle(k):
     mats = small_batch()
     enc = encode_all(mats, D_of=lambda i: [9, 12, 3][i % 3])

@@ -110,7 +110,7 @@ def test_random_parity(fmt, D, C, sigma):
         assert np.array_equal(dv, ref_v)
 
 
-@pytest.mark.parametrize("k", [2, 3, 8, 13])
+@pytest.mark.parametrize("k", [2, 3, 4, 8, 12, 13, 16, 20, 32, 36, 64])
 def test_multiple_rhs(k):
     a = random_csr(5, 700, 650, density=0.02)
     X = W.uniform_vector(a.m, 9, k=k)
@@ -119,6 +119,19 @@ def test_multiple_rhs(k):
         Y = B.spmv(A, torch.from_numpy(X).to(DEV)).cpu().numpy()
         ref, q = oracle_product(a, FMTS[fmt], D, X)
         assert normalised_error(Y, ref, a, q, X) <= SPMV_TOL
+
+
+@pytest.mark.parametrize("k", [8, 12, 20, 32, 64])
+def test_lane_groups_equal_single_vector_products(k):
+    """k a multiple of 4 (lane groups of 2..16 lanes per row): every column
+    of the block product equals the one-vector product of that column bit
+    for bit -- the same words, decoded values and FMA order."""
+    a = random_csr(6, 1500, 1400, density=0.01)
+    A, _ = both(a, "e8my", 9, 64, 256)
+    X = torch.from_numpy(W.uniform_vector(a.m, 10, k=k)).to(DEV)
+    Y = B.spmv(A, X)
+    for r in range(k):
+        assert torch.equal(Y[:, r], B.spmv(A, X[:, r].contiguous())), r
 
 
 def test_m1_poisson_fp16():
