@@ -75,7 +75,8 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=400)
-    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=2000,
+                   help="untimed launches first (about 30 ms of the headline product, so clocks settle)")
     p.add_argument("--grid", type=int, default=128, help="grid points per axis")
     p.add_argument("--replica-bytes", type=float, default=1.2e9)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
