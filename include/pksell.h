@@ -201,6 +201,26 @@ int pksell_grad_values(const pksell_matrix *A, const int64_t *rowptr,
                        const float *g, const float *x, float *grad, int64_t k,
                        void *stream);
 
+/* The transpose of a CSR matrix on the device, for a PackSELL copy of A^T
+ * (not in the paper).  With the element-wise quantisers (FP16, E8MY) the
+ * encoded copy holds exactly (A_q)^T, so grad_x = A_q^T g becomes a forward
+ * pksell_spmv on it, with no atomics; FIX quantises per row, so its A^T
+ * copy would hold different values and its adjoint stays pksell_spmv_t.
+ *
+ * Input: rowptr int64[n+1], col int32[nnz] (in [0, m), strictly increasing
+ * per row), val (float32 or float64 per val_dtype) [nnz].  Output (caller
+ * allocated): t_rowptr int64[m+1], t_col int32[nnz] (rows of A, ascending
+ * per column), t_val [nnz] in the input's value type.  A stable radix sort
+ * by column: deterministic.  Needs nnz < 2^31 - 1.  Validates rowptr and the
+ * column range first (EINVAL on malformed input, no writes), which
+ * SYNCHRONISES once; the rest is asynchronous on ``stream``. */
+int pksell_csr_transpose_query(int64_t n, int64_t m, int64_t nnz, size_t *ws_bytes);
+int pksell_csr_transpose(const int64_t *rowptr, const int32_t *col,
+                         const void *val, int32_t val_dtype, int64_t n,
+                         int64_t m, int64_t nnz, int64_t *t_rowptr,
+                         int32_t *t_col, void *t_val, void *ws,
+                         size_t ws_bytes, void *stream);
+
 /* Decodes every word position: cols[p] = column reconstructed at word p
  * (running sum of deltas from the left offset), vals[p] = decoded value
  * (0 for flag-0 words; FIX: q * 2^e).  Positions of phantom rows past n are

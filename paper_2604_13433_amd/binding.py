@@ -85,6 +85,9 @@ _PROTOS = {
 }
 
 _PROTOS.update({
+    "pksell_csr_transpose_query": ([i64, i64, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pksell_csr_transpose": ([vp, vp, vp, i32, i64, i64, i64, vp, vp, vp, vp, ctypes.c_size_t, vp],
+                             ctypes.c_int),
     "pksell_batch_plan_bytes": ([i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_batch_plan": ([ctypes.POINTER(CBatchItem), i32, i64, i32, ctypes.POINTER(CBatch), vp,
                            ctypes.c_size_t, vp], ctypes.c_int),
@@ -278,6 +281,43 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
     _check(L.pksell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
                            _ptr(ws), ws_bytes.value, st))
     return A
+
+
+def csr_transpose(rowptr, col, val, n: int, m: int, device="cuda"):
+    """CSR of A^T on the device: (t_rowptr int64[m+1], t_col int32[nnz],
+    t_val[nnz]) with t_val in val's float type."""
+    device = torch.device(device)
+    rp = _dev(rowptr, torch.int64, device)
+    cl = _dev(col, torch.int32, device)
+    f64 = (isinstance(val, np.ndarray) and val.dtype == np.float64) or \
+        (isinstance(val, torch.Tensor) and val.dtype == torch.float64)
+    vl = _dev(val, torch.float64 if f64 else torch.float32, device)
+    nnz = int(cl.numel())
+    ws_bytes = ctypes.c_size_t()
+    _check(lib().pksell_csr_transpose_query(n, m, nnz, ctypes.byref(ws_bytes)))
+    ws = torch.empty(max(1, ws_bytes.value), dtype=torch.uint8, device=device)
+    t_rowptr = torch.empty(m + 1, dtype=torch.int64, device=device)
+    t_col = torch.empty(max(1, nnz), dtype=torch.int32, device=device)
+    t_val = torch.empty(max(1, nnz), dtype=vl.dtype, device=device)
+    _check(lib().pksell_csr_transpose(_ptr(rp), _ptr(cl), _ptr(vl), F64 if f64 else F32, n, m, nnz,
+                                      _ptr(t_rowptr), _ptr(t_col), _ptr(t_val), _ptr(ws),
+                                      ws_bytes.value, _stream(device)))
+    return t_rowptr, t_col[:nnz], t_val[:nnz]
+
+
+def encode_transpose(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 64,
+                     sigma: int = 256, perm_mode: int = IMPLICIT, device="cuda",
+                     split_words: int = 0) -> PackSELLMatrix:
+    """PackSELL of A^T (m x n) from the CSR of A, transposed on the device.
+    For FP16 and E8MY it holds exactly (A_q)^T, so ``spmv`` on it is the
+    adjoint product A_q^T g."""
+    if isinstance(fmt, str):
+        fmt = FMT_BY_NAME[fmt]
+    if fmt == FIX:
+        raise ValueError("FIX quantises per row: a transposed copy would not hold (A_q)^T")
+    t_rowptr, t_col, t_val = csr_transpose(rowptr, col, val, n, m, device)
+    return encode(t_rowptr, t_col, t_val, m, n, fmt, D, C, sigma, perm_mode, device,
+                  split_words=split_words)
 
 
 def spmv(A: PackSELLMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:

@@ -28,12 +28,14 @@ def grid_values(a, D, seed):
     return F.e8my_value_bits(v, D).view(np.float32)
 
 
+@pytest.mark.parametrize("adjoint", ["atomic", "transpose"])
 @pytest.mark.parametrize("k", [1, 4])
-def test_gradients_against_fp64_reference(k):
+def test_gradients_against_fp64_reference(k, adjoint):
     a = random_csr(11, 900, 700, per_row=12)
     D = 9
     vals = torch.tensor(grid_values(a, D, 1), device=DEV, requires_grad=True)
-    lin = AG.PackSELLLinear(a.rowptr, a.col, vals, a.n, a.m, "e8my", D)
+    lin = AG.PackSELLLinear(a.rowptr, a.col, vals, a.n, a.m, "e8my", D, adjoint=adjoint)
+    assert (lin.transposed() is not None) == (adjoint == "transpose")
     X = W.uniform_vector(a.m, 2, k=k)
     G = W.uniform_vector(a.n, 3, k=k)
     x = torch.tensor(X, device=DEV, requires_grad=True)
@@ -89,6 +91,13 @@ def test_finite_differences():
             continue
         fd = (f(fp, x) - f(fm, x)) / (2 * h)
         assert abs(fd - float(vals.grad[e_i])) <= 1e-4 * (1 + abs(fd))
+
+
+def test_transpose_adjoint_rejects_fix():
+    a = random_csr(14, 50, 50, per_row=3)
+    vals = torch.tensor(a.val.astype(np.float32), device=DEV)
+    with pytest.raises(ValueError):
+        AG.PackSELLLinear(a.rowptr, a.col, vals, a.n, a.m, "fix", 15, adjoint="transpose")
 
 
 def test_reencodes_after_update():
