@@ -221,6 +221,16 @@ int pksell_csr_transpose(const int64_t *rowptr, const int32_t *col,
                          int32_t *t_col, void *t_val, void *ws,
                          size_t ws_bytes, void *stream);
 
+/* Measurement helper (not in the paper): one streaming read of ``bytes``
+ * (a positive multiple of 16; src 16-byte aligned) in a single launch, to
+ * measure the practical HBM read ceiling for a transfer of that size.  Each
+ * wave reads ``chunks`` (1..4096) consecutive pieces of 64 lanes x ``width``
+ * (4 or 16) bytes with nontemporal loads, eight in flight per lane.
+ * ``out`` (device, >= 1 float) is only there so the loads are kept; its
+ * contents carry no meaning. */
+int pksell_stream_read(const void *src, size_t bytes, int32_t width,
+                       int32_t chunks, float *out, void *stream);
+
 /* Decodes every word position: cols[p] = column reconstructed at word p
  * (running sum of deltas from the left offset), vals[p] = decoded value
  * (0 for flag-0 words; FIX: q * 2^e).  Positions of phantom rows past n are

@@ -1,12 +1,16 @@
 """Autotuner for PackSELL parameters: delta width D (the delta/value bit
-split), slice height C and window sigma.
+split), slice height C, window sigma and, for single-vector products with
+C = 64, the wide-slice split width J (the work-unit shape).
 
 Model first, measurement second.  The encoder's analyse phase alone gives
 the exact stored-word count (nonzeros + dummies + padding) of every
 candidate, so the algorithmic bytes of one product are known without
 building any words.  The product is bandwidth-bound, so the cheapest few
 candidates by bytes are then encoded and timed on the GPU (HIP events over
-graph replays), and the fastest wins.  Precision is a constraint, not a
+graph replays), and the fastest wins.  The split width does not change the
+bytes, only how the work is cut into waves, so each timed C = 64 candidate
+is also timed with every J of ``split_list`` that splits at least one of its
+slices.  Precision is a constraint, not a
 goal: E8MY candidates keep at least ``min_mantissa`` mantissa bits
 (Y = 22 - D), FIX at least ``min_mantissa`` value bits.
 
@@ -26,6 +30,7 @@ from . import binding as B
 
 DEFAULT_C = (32, 64)
 DEFAULT_SIGMA = (64, 256, 1024, 8192, 65536)
+DEFAULT_SPLIT = (128, 256)
 
 
 def signature(rowptr, col, n: int, m: int, fmt: str, min_mantissa: int, k: int) -> str:
@@ -68,9 +73,11 @@ def _time_spmv(A, x, y, reps=50):
 
 def tune(rowptr, col, val, n: int, m: int, fmt: str = "e8my", min_mantissa: int = 13,
          perm_mode: int = B.IMPLICIT, k: int = 1, C_list=DEFAULT_C, sigma_list=DEFAULT_SIGMA,
-         time_top: int = 3, cache_path: str | None = None, device="cuda") -> dict:
-    """Returns {"fmt", "D", "C", "sigma", "bytes", "us", "candidates": [...]}."""
-    key = signature(rowptr, col, n, m, fmt, min_mantissa, k)
+         split_list=DEFAULT_SPLIT, time_top: int = 3, cache_path: str | None = None,
+         device="cuda") -> dict:
+    """Returns {"fmt", "D", "C", "sigma", "split_words", "bytes", "us",
+    "candidates": [...]}."""
+    key = signature(rowptr, col, n, m, fmt, min_mantissa, k) + f":{tuple(split_list)}"
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -96,12 +103,27 @@ def tune(rowptr, col, val, n: int, m: int, fmt: str = "e8my", min_mantissa: int 
     y = torch.empty((n,) if k == 1 else (n, k), device=device)
     for c in cands[:time_top]:
         A = B.encode(rp, cl, vl, n, m, fmt, c["D"], c["C"], c["sigma"], perm_mode, device)
+        c["split_words"] = 0
         c["us"] = round(_time_spmv(A, x, y) * 1e3, 3)
         del A
+        if k != 1 or c["C"] != 64:
+            continue
+        c["split_us"] = {}
+        for J in split_list:
+            A = B.encode(rp, cl, vl, n, m, fmt, c["D"], c["C"], c["sigma"], perm_mode, device,
+                         split_words=J)
+            if A.n_split_units > 0:
+                c["split_us"][str(J)] = round(_time_spmv(A, x, y) * 1e3, 3)
+            del A
+        if c["split_us"]:
+            J, us = min(c["split_us"].items(), key=lambda kv: kv[1])
+            if us < c["us"]:
+                c["split_words"], c["us"] = int(J), us
     timed = [c for c in cands if "us" in c]
     best = min(timed, key=lambda c: c["us"])
-    out = dict(fmt=fmt, D=best["D"], C=best["C"], sigma=best["sigma"], bytes=best["bytes"],
-               us=best["us"], min_mantissa=min_mantissa, k=k, candidates=cands[: max(10, time_top)])
+    out = dict(fmt=fmt, D=best["D"], C=best["C"], sigma=best["sigma"],
+               split_words=best["split_words"], bytes=best["bytes"], us=best["us"],
+               min_mantissa=min_mantissa, k=k, candidates=cands[: max(10, time_top)])
     if cache_path:
         cache[key] = out
         tmp = cache_path + ".tmp"

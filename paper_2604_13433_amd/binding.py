@@ -88,6 +88,7 @@ _PROTOS.update({
     "pksell_csr_transpose_query": ([i64, i64, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_csr_transpose": ([vp, vp, vp, i32, i64, i64, i64, vp, vp, vp, vp, ctypes.c_size_t, vp],
                              ctypes.c_int),
+    "pksell_stream_read": ([vp, ctypes.c_size_t, i32, i32, vp, vp], ctypes.c_int),
     "pksell_batch_plan_bytes": ([i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_batch_plan": ([ctypes.POINTER(CBatchItem), i32, i64, i32, ctypes.POINTER(CBatch), vp,
                            ctypes.c_size_t, vp], ctypes.c_int),
@@ -281,6 +282,24 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
     _check(L.pksell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
                            _ptr(ws), ws_bytes.value, st))
     return A
+
+
+class StreamRead:
+    """One streaming read of ``buf`` (a device tensor whose byte size is a
+    multiple of 16) per call: the HBM read ceiling for that transfer size.
+    ``width`` (4 or 16) bytes per lane and load, ``chunks`` wave-wide pieces
+    per wave."""
+
+    def __init__(self, buf: torch.Tensor, width: int = 4, chunks: int = 7):
+        assert buf.is_contiguous() and buf.data_ptr() % 16 == 0
+        self.buf = buf
+        self.bytes = buf.numel() * buf.element_size()
+        self.width, self.chunks = width, chunks
+        self.out = torch.empty(1, dtype=torch.float32, device=buf.device)
+
+    def __call__(self):
+        _check(lib().pksell_stream_read(_ptr(self.buf), self.bytes, self.width, self.chunks,
+                                        _ptr(self.out), _stream(self.buf.device)))
 
 
 def csr_transpose(rowptr, col, val, n: int, m: int, device="cuda"):

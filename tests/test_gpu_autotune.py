@@ -35,3 +35,30 @@ def test_tune_fp16_single_D():
     a = W.m1_poisson2d()
     r = T.tune(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 10, sigma_list=(64, 256), device=DEV)
     assert r["D"] == 15
+
+
+def test_tune_splits_wide_slices(tmp_path):
+    """Power-law rows (n = 60,000, rows up to 5000 entries) in one sigma
+    window: the split widths are timed, and the chosen configuration builds
+    and multiplies correctly."""
+    import numpy as np
+
+    from helpers import FMTS, SPMV_TOL, normalised_error, oracle_product
+
+    a = W.powerlaw(60_000, seed=9)
+    cache = os.path.join(tmp_path, "tune.json")
+    r = T.tune(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 10, C_list=(64,), sigma_list=(65536,),
+               split_list=(128, 256), time_top=1, cache_path=cache, device=DEV)
+    top = r["candidates"][0]
+    assert set(top["split_us"]) == {"128", "256"}  # both split some slice
+    assert r["split_words"] in (0, 128, 256)
+    assert r["us"] == min([top["us"]] + list(top["split_us"].values()))
+    A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "fp16", r["D"], r["C"], r["sigma"],
+                 B.IMPLICIT, DEV, split_words=r["split_words"])
+    x = W.uniform_vector(a.m, 3)
+    y = B.spmv(A, torch.from_numpy(x).to(DEV)).cpu().numpy()
+    ref, q = oracle_product(a, FMTS["fp16"], 15, x)
+    assert normalised_error(y, ref, a, q, x) <= SPMV_TOL
+    assert T.tune(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 10, C_list=(64,),
+                  sigma_list=(65536,), split_list=(128, 256), time_top=1,
+                  cache_path=cache, device=DEV) == r
