@@ -495,7 +495,7 @@ def pcg_leg(args, torch, B, W):
     res["fp64_cg"] = run(None, 0)
     log(f"[bench] fp64 CG: {res['fp64_cg']}")
     best = None
-    for D in (9, 12):
+    for D in (9, 12, 14):
         lo = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e8my", D, 64, 256, B.IMPLICIT, dev)
         for m_in in (20, 50):
             r = run(lo, m_in)

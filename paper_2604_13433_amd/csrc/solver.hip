@@ -52,9 +52,9 @@ struct Parts {
 
 // ---- reductions -----------------------------------------------------------------
 
-template <int NV>
+template <int NV, int BS = kB>
 __device__ inline void block_sum(double (&v)[NV]) {
-  __shared__ double sh[NV][kB / kWave];
+  __shared__ double sh[NV][BS / kWave];
 #pragma unroll
   for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -65,31 +65,48 @@ __device__ inline void block_sum(double (&v)[NV]) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     double s = 0.0;
-    for (int i = 0; i < kB / kWave; ++i) s += sh[q][i];
+    for (int i = 0; i < BS / kWave; ++i) s += sh[q][i];
     v[q] = s;  // every thread holds the total
   }
   __syncthreads();
 }
 
-// Writes this workgroup's partial sums.
-template <int NV>
+// Writes this workgroup's partial sums (BS threads per workgroup).
+template <int NV, int BS = kB>
 __device__ inline void put_partials(double (&v)[NV], Parts out) {
-  block_sum(v);
+  block_sum<NV, BS>(v);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int q = 0; q < NV; ++q) out.p[q * out.count + blockIdx.x] = v[q];
 }
 
+// Elements of one thread in flight at once in the grid-stride loops: each
+// loop loads kVecUnroll elements (stride apart) before computing on any of
+// them, then computes them in index order, so every sum is accumulated in
+// the same order as a plain one-element-at-a-time loop.
+constexpr int kVecUnroll = 8;
+
 // Sums a previous kernel's partials; every thread of every workgroup gets the
 // same totals (same order of additions everywhere).
-template <int NV>
+template <int NV, int BS = kB>
 __device__ inline void get_totals(Parts in, double (&tot)[NV]) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) tot[q] = 0.0;
-  for (uint32_t i = threadIdx.x; i < in.count; i += kB)
+  for (uint32_t i0 = threadIdx.x; i0 < in.count; i0 += kVecUnroll * BS) {
+    double v[NV][kVecUnroll];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) tot[q] += in.p[q * in.count + i];
-  block_sum(tot);
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const uint32_t i = i0 + u * BS;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q][u] = i < in.count ? in.p[q * in.count + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u)
+      if (i0 + u * BS < in.count)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) tot[q] += v[q][u];
+  }
+  block_sum<NV, BS>(tot);
 }
 
 __device__ inline bool outer_stopped(const State *st) {
@@ -193,6 +210,114 @@ __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restr
   put_partials(v, pq_out);
 }
 
+// (A) for C = 64: the same step with two slices per wave and 128-thread
+// workgroups (four slices per workgroup, as in k_inner_a), so the grid runs
+// in about one round of waves; the first eight words of both slices are
+// requested before the previous partials are summed, so their latency
+// overlaps the beta prologue.  Same arithmetic per row as k_inner_a.
+constexpr int kPairB = 128;
+
+template <int FMT>
+__global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__restrict__ r,
+                                                    const float *__restrict__ p_old,
+                                                    float *__restrict__ p_new,
+                                                    float *__restrict__ q, State *st,
+                                                    Parts rr_in, Parts pq_out) {
+  constexpr int S = 2;
+  const bool stop = outer_stopped(st) || st->inner_stop;
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(b * (kPairB / kWave) + threadIdx.x / kWave);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t k0 = wave * S;
+  int64_t off[S + 1];
+  uint32_t w[S], p[S][kUnroll];
+#pragma unroll
+  for (int i = 0; i <= S; ++i) off[i] = A.offset[min(k0 + i, A.n_slices)];
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    w[i] = stop ? 0u : (uint32_t)((off[i + 1] - off[i]) >> 6);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      uint32_t v = 0u;
+      if (u < (int)w[i]) v = __builtin_nontemporal_load(A.pack + off[i] + lane + u * kWave);
+      p[i][u] = v;
+    }
+  }
+  const bool first = st->in_first;
+  double rr[1] = {0.0};
+  if (!stop) get_totals<1, kPairB>(rr_in, rr);
+  const double beta_d = first ? 0.0 : rr[0] / st->in_rr_used;
+  const bool quit = !stop && !(rr[0] > 0.0 && isfinite(beta_d));  // inner residual vanished
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->in_step_ok = !(stop || quit);
+    if (quit) st->inner_stop = 1;
+    st->in_rr_cur = rr[0];
+    st->in_beta = beta_d;
+  }
+  if (stop || quit) return;
+  const float beta = (float)beta_d;
+  const __amdgpu_buffer_rsrc_t rr_r = make_rsrc(r, A.n * 4u);
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(p_old, A.n * 4u);
+  const uint32_t oob = A.n * 4u;  // flag-0 words: past the resources, no request
+  uint32_t c[S];
+  float acc[S];
+  uint32_t wm = 0;
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    c[i] = left_offset32((k0 + i) * kWave + lane, A.geo);
+    acc[i] = 0.0f;
+    wm = max(wm, w[i]);
+  }
+  for (uint32_t j = 0; j < wm; j += kUnroll) {
+    if (j > 0) {
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          uint32_t v = 0u;
+          if (j + u < w[i]) v = __builtin_nontemporal_load(A.pack + off[i] + lane + (j + u) * kWave);
+          p[i][u] = v;
+        }
+    }
+    uint32_t o[S][kUnroll];
+    float v[S][kUnroll];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const Unpacked d = unpack(p[i][u], A.cd);
+        c[i] += d.delta;
+        o[i][u] = (p[i][u] & 1u) ? c[i] << 2 : oob;
+        v[i][u] = decode_value<FMT>(d.vbits);
+      }
+    float xv[S][kUnroll];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        xv[i][u] = fmaf(beta, buffer_load_f32(rp, o[i][u]), buffer_load_f32(rr_r, o[i][u]));
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) acc[i] = fmaf(v[i][u], xv[i][u], acc[i]);
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    const uint32_t t = (k0 + i) * kWave + lane;
+    if (k0 + i >= A.n_slices || t >= A.n) continue;
+    float qi = acc[i];
+    if constexpr (FMT == PKSELL_FIX) qi = ldexpf(qi, (int)A.row_exp[t] - (A.cd.D + 1));
+    const uint32_t row = out_row(A.perm, A.perm_bytes, t, A.geo);
+    const float pn = fmaf(beta, p_old[row], r[row]);
+    p_new[row] = pn;
+    q[row] = qi;
+    part += (double)pn * (double)qi;
+  }
+  double vv[1] = {part};
+  put_partials<1, kPairB>(vv, pq_out);
+}
+
 // (B) float32 inner update: alpha = rr / pq; z += alpha p, r -= alpha q;
 // partials of the new r.r.
 __global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ z,
@@ -210,11 +335,28 @@ __global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ 
   const double alpha_d = rr / pq[0];
   const float alpha = (float)alpha_d;
   double part = 0.0;
-  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
-    z[i] = fmaf(alpha, p[i], z[i]);
-    const float ri = fmaf(-alpha, q[i], r[i]);
-    r[i] = ri;
-    part += (double)ri * (double)ri;
+  const uint32_t S = gridDim.x * kB;
+  for (uint32_t i0 = blockIdx.x * kB + threadIdx.x; i0 < n; i0 += kVecUnroll * S) {
+    float zz[kVecUnroll], pp[kVecUnroll], qq[kVecUnroll], rv[kVecUnroll];
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const uint32_t i = i0 + u * S;
+      const bool in = i < n;
+      zz[u] = in ? z[i] : 0.0f;
+      pp[u] = in ? p[i] : 0.0f;
+      qq[u] = in ? q[i] : 0.0f;
+      rv[u] = in ? r[i] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const uint32_t i = i0 + u * S;
+      if (i < n) {
+        z[i] = fmaf(alpha, pp[u], zz[u]);
+        const float ri = fmaf(-alpha, qq[u], rv[u]);
+        r[i] = ri;
+        part += (double)ri * (double)ri;
+      }
+    }
   }
   double v[1] = {part};
   put_partials(v, rr_out);
@@ -223,6 +365,36 @@ __global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ 
     st->in_alpha = alpha_d;
     st->inner_iters += 1;
     st->in_first = 0;
+  }
+}
+
+// x += alpha p; r -= alpha q; part += r.r over this thread's elements (in
+// index order), with kVecUnroll elements in flight.
+__device__ inline void axpy_pair(uint32_t n, double alpha, double *__restrict__ x,
+                                 double *__restrict__ r, const double *__restrict__ p,
+                                 const double *__restrict__ q, double &part) {
+  const uint32_t S = gridDim.x * kB;
+  for (uint32_t i0 = blockIdx.x * kB + threadIdx.x; i0 < n; i0 += kVecUnroll * S) {
+    double xx[kVecUnroll], pp[kVecUnroll], qq[kVecUnroll], rv[kVecUnroll];
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const uint32_t i = i0 + u * S;
+      const bool in = i < n;
+      xx[u] = in ? x[i] : 0.0;
+      pp[u] = in ? p[i] : 0.0;
+      qq[u] = in ? q[i] : 0.0;
+      rv[u] = in ? r[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const uint32_t i = i0 + u * S;
+      if (i < n) {
+        x[i] = fma(alpha, pp[u], xx[u]);
+        const double ri = fma(-alpha, qq[u], rv[u]);
+        r[i] = ri;
+        part += ri * ri;
+      }
+    }
   }
 }
 
@@ -288,12 +460,7 @@ __global__ __launch_bounds__(kB) void k_cg_b(uint32_t n, double *__restrict__ x,
   const double rr = st->rr_cur;
   const double alpha = rr / pq[0];
   double part = 0.0;
-  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
-    x[i] = fma(alpha, p[i], x[i]);
-    const double ri = fma(-alpha, q[i], r[i]);
-    r[i] = ri;
-    part += ri * ri;
-  }
+  axpy_pair(n, alpha, x, r, p, q, part);
   double v[1] = {part};
   put_partials(v, rr_out);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -317,12 +484,22 @@ __global__ __launch_bounds__(kB) void k_inner_init(uint32_t n, const double *__r
   const bool stop = !(nr > 0.0 && isfinite(nr));
   const double inv = stop ? 0.0 : 1.0 / nr;
   double part = 0.0;
-  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
-    const float v = (float)(r[i] * inv);
-    rin[i] = v;
-    zin[i] = 0.0f;
-    p0[i] = 0.0f;
-    part += (double)v * (double)v;
+  const uint32_t S = gridDim.x * kB;
+  for (uint32_t i0 = blockIdx.x * kB + threadIdx.x; i0 < n; i0 += kVecUnroll * S) {
+    double rv[kVecUnroll];
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) rv[u] = i0 + u * S < n ? r[i0 + u * S] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const uint32_t i = i0 + u * S;
+      if (i < n) {
+        const float v = (float)(rv[u] * inv);
+        rin[i] = v;
+        zin[i] = 0.0f;
+        p0[i] = 0.0f;
+        part += (double)v * (double)v;
+      }
+    }
   }
   double v[1] = {part};
   put_partials(v, rr_out);
@@ -403,12 +580,7 @@ __global__ __launch_bounds__(kB) void k_outer_update(uint32_t n, double *__restr
   }
   const double alpha = t[1] / t[0];
   double part = 0.0;
-  for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
-    x[i] = fma(alpha, p[i], x[i]);
-    const double ri = fma(-alpha, q[i], r[i]);
-    r[i] = ri;
-    part += ri * ri;
-  }
+  axpy_pair(n, alpha, x, r, p, q, part);
   double v[1] = {part};
   put_partials(v, rr_out);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -585,7 +757,12 @@ struct Solve {
 
   template <int FMT, bool CW>
   void inner_a(const PackView &A, const float *po, float *pn, Parts rr_in, Parts pq_out) {
-    k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
+    // gp workgroups either way: 4 slices each (256 threads x 1 slice per
+    // wave, or 128 threads x 2 slices per wave), so the partial count agrees
+    if constexpr (CW)
+      k_inner_a2<FMT><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
+    else
+      k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
   }
 
   // Enqueues one flexible-CG outer iteration with m_in inner iterations.
