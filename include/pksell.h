@@ -213,7 +213,9 @@ int pksell_grad_values(const pksell_matrix *A, const int64_t *rowptr,
  * per column), t_val [nnz] in the input's value type.  A stable radix sort
  * by column: deterministic.  Needs nnz < 2^31 - 1.  Validates rowptr and the
  * column range first (EINVAL on malformed input, no writes), which
- * SYNCHRONISES once; the rest is asynchronous on ``stream``. */
+ * SYNCHRONISES once; the rest is asynchronous on ``stream``.
+ * pksell_csr_transpose_query sizes the workspace; it asks the current
+ * device for the sort's scratch size, so it needs a GPU. */
 int pksell_csr_transpose_query(int64_t n, int64_t m, int64_t nnz, size_t *ws_bytes);
 int pksell_csr_transpose(const int64_t *rowptr, const int32_t *col,
                          const void *val, int32_t val_dtype, int64_t n,

@@ -234,8 +234,17 @@ __global__ __launch_bounds__(kBlock) void k_combine_chunks(SpmvArgs a, UnitArgs 
   const uint32_t k = u.splits[4 * sp], base = u.splits[4 * sp + 1], chunks = u.splits[4 * sp + 2];
   const uint32_t t = k * kWave + lane;
   if (t >= a.n) return;
+  // eight chunk sums in flight at a time, added in chunk order
   float r = 0.0f;
-  for (uint32_t c = 0; c < chunks; ++c) r += u.partial[(base + c) * kWave + lane];
+  for (uint32_t c0 = 0; c0 < chunks; c0 += 8) {
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      v[i] = c0 + i < chunks ? u.partial[(base + c0 + i) * kWave + lane] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (c0 + i < chunks) r += v[i];
+  }
   if constexpr (FMT == PKSELL_FIX) r = ldexpf(r, (int)a.row_exp[t] - (a.cd.D + 1));
   a.y[out_row(a.perm, a.perm_bytes, t, a.geo)] = r;
 }

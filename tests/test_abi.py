@@ -96,3 +96,18 @@ def test_encode_rejects_bad_split_words(C, J):
     rc = B.lib().pksell_encode(p, p, p, B.F32, ctypes.byref(desc), p, max(ws, 4096), None)
     assert rc == B.EINVAL
     assert b"split_words" in B.lib().pksell_last_error()
+
+
+@pytest.mark.parametrize("n,m,nnz,code", [(-1, 5, 5, B.EINVAL), (5, 5, -2, B.EINVAL),
+                                          (1 << 30, 5, 5, B.ERANGE), (5, 5, 1 << 31, B.ERANGE)])
+def test_csr_transpose_query_rejects(n, m, nnz, code):
+    ws = ctypes.c_size_t()
+    assert B.lib().pksell_csr_transpose_query(n, m, nnz, ctypes.byref(ws)) == code
+    assert B.lib().pksell_last_error()
+
+
+def test_stream_read_rejects_on_host():
+    buf = (ctypes.c_uint8 * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    for nbytes, width, chunks in [(20, 4, 7), (0, 4, 7), (64, 8, 7), (64, 4, 0), (64, 4, 5000)]:
+        assert B.lib().pksell_stream_read(p, nbytes, width, chunks, p, None) == B.EINVAL

@@ -6,6 +6,8 @@ oracle's encoding of that transpose, and the forward product on it must
 equal the oracle's A_q^T g within 1e-6 (normalised by the largest absolute
 column sum of A_q times ||g||_inf).
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -115,3 +117,12 @@ def test_powerlaw_adjoint_full_size():
     ref = L.spmv_t(a.rowptr, a.col, q, g, a.m)
     colsum = np.bincount(a.col, weights=np.abs(q), minlength=a.m).max()
     assert np.max(np.abs(yt - ref)) / (colsum * np.abs(g).max()) <= SPMV_TOL
+
+
+def test_csr_transpose_query_sizes():
+    """The workspace holds the sorted keys, two index arrays, the row map and
+    the sort's own scratch (the sort sizes its scratch from the device)."""
+    ws = ctypes.c_size_t()
+    assert B.lib().pksell_csr_transpose_query(1000, 800, 12345, ctypes.byref(ws)) == B.OK
+    assert ws.value >= 4 * 4 * 12345
+    assert B.lib().pksell_csr_transpose_query(0, 0, 0, ctypes.byref(ws)) == B.OK
