@@ -166,11 +166,15 @@ __device__ inline Unit unit_at(const Item *items, const uint32_t *unit_start, ui
   return x;
 }
 
-// Words j .. j+7 of a slice lane (w is wave-uniform; words past w are
-// padding).  Nontemporal when one wave reads each word (L = 1).
+// Words j .. j+7 of lane l of the slice starting at word s (w is
+// wave-uniform; words past w are padding).  Nontemporal when one wave reads
+// each word (L = 1), plain when lane groups share them.  (Streamed buffer
+// loads, faster in the single-matrix kernels, made this pipelined loop 20 %
+// slower.)
 template <bool NT>
-__device__ inline void load_words(const uint32_t *P, uint32_t w, uint32_t j,
+__device__ inline void load_words(const Item &it, int64_t s, uint32_t l, uint32_t w, uint32_t j,
                                   uint32_t (&p)[kUnroll]) {
+  const uint32_t *P = it.pack + s + l;
 #pragma unroll
   for (int q = 0; q < kUnroll; ++q) {
     uint32_t v = 0u;
@@ -230,7 +234,7 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
   Unit cur = unit_at<L>(items, unit_start, find_item(unit_start, count, u), u, lane, k4);
   constexpr bool NT = L == 1;
   uint32_t p[kUnroll];
-  load_words<NT>(items[cur.item].pack + cur.s + cur.l, cur.w, 0, p);
+  load_words<NT>(items[cur.item], cur.s, cur.l, cur.w, 0, p);
   for (;;) {
     const bool more = u + stride < total;
     Unit nx;
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
       uint32_t itn = cur.item;
       while (u + stride >= unit_start[itn + 1]) ++itn;
       nx = unit_at<L>(items, unit_start, itn, u + stride, lane, k4);
-      load_words<NT>(items[itn].pack + nx.s + nx.l, nx.w, 0, pn);
+      load_words<NT>(items[itn], nx.s, nx.l, nx.w, 0, pn);
     }
     const Item &I = items[cur.item];
     const uint32_t t = cur.ks * kWave + cur.l;
@@ -253,7 +257,7 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
     fma_words<FMT, L, NA>(p, c, I.cd, rx, kx, xq, oob, acc);
     for (uint32_t j = kUnroll; j < cur.w; j += kUnroll) {  // slices wider than one group
       uint32_t pr[kUnroll];
-      load_words<NT>(I.pack + cur.s + cur.l, cur.w, j, pr);
+      load_words<NT>(I, cur.s, cur.l, cur.w, j, pr);
       fma_words<FMT, L, NA>(pr, c, I.cd, rx, kx, xq, oob, acc);
     }
     if (t < I.n && cur.live) {

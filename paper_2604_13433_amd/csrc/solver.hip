@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restr
 // overlaps the beta prologue.  Same arithmetic per row as k_inner_a.
 constexpr int kPairB = 128;
 
-template <int FMT>
+template <int FMT, bool BUF>
 __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__restrict__ r,
                                                     const float *__restrict__ p_old,
                                                     float *__restrict__ p_new,
@@ -231,15 +231,21 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
   const uint32_t k0 = wave * S;
   int64_t off[S + 1];
   uint32_t w[S], p[S][kUnroll];
+  __amdgpu_buffer_rsrc_t rs[S];
 #pragma unroll
   for (int i = 0; i <= S; ++i) off[i] = A.offset[min(k0 + i, A.n_slices)];
+  auto word = [&](int i, uint32_t j) {
+    return BUF ? stream_word(rs[i], lane, j)
+               : __builtin_nontemporal_load(A.pack + off[i] + lane + j * kWave);
+  };
 #pragma unroll
   for (int i = 0; i < S; ++i) {
     w[i] = stop ? 0u : (uint32_t)((off[i + 1] - off[i]) >> 6);
+    rs[i] = slice_words(A.pack + off[i], w[i]);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       uint32_t v = 0u;
-      if (u < (int)w[i]) v = __builtin_nontemporal_load(A.pack + off[i] + lane + u * kWave);
+      if (u < (int)w[i]) v = word(i, u);
       p[i][u] = v;
     }
   }
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           uint32_t v = 0u;
-          if (j + u < w[i]) v = __builtin_nontemporal_load(A.pack + off[i] + lane + (j + u) * kWave);
+          if (j + u < w[i]) v = word(i, j + u);
           p[i][u] = v;
         }
     }
@@ -716,6 +722,7 @@ struct Solve {
   hipStream_t s;
   uint32_t n, vb;
   uint32_t gs, gp;  // grids of the SELL and PackSELL product kernels
+  bool stream_ok;   // the inner words are addressable by 32-bit byte offsets
 
   Parts pa_for(uint32_t grid) const { return {w.pa.p, grid}; }
   Parts vec(const Parts &p) const { return {p.p, vb}; }
@@ -759,9 +766,12 @@ struct Solve {
   void inner_a(const PackView &A, const float *po, float *pn, Parts rr_in, Parts pq_out) {
     // gp workgroups either way: 4 slices each (256 threads x 1 slice per
     // wave, or 128 threads x 2 slices per wave), so the partial count agrees
-    if constexpr (CW)
-      k_inner_a2<FMT><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
-    else
+    if constexpr (CW) {
+      if (stream_ok)
+        k_inner_a2<FMT, true><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
+      else
+        k_inner_a2<FMT, false><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
+    } else
       k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
   }
 
@@ -960,6 +970,7 @@ int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi, const double 
   sv.vb = (uint32_t)std::min<int64_t>(kVecBlocks, cdiv(A_hi->n, kB));
   sv.gs = (uint32_t)cdiv(A_hi->n_slices * A_hi->C, kB);
   sv.gp = A_lo ? (uint32_t)cdiv(A_lo->n_slices * A_lo->C, kB) : 0u;
+  sv.stream_ok = A_lo && A_lo->n_words < (int64_t(1) << 30);
   sv.w = carve_work(ws, A_hi->n, max_blocks_of(A_hi, A_lo));
   PKS_CHECK(ws && ws_bytes >= sv.w.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes",
             sv.w.bytes);

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_group(SpmvArgs a) {
 // gives.  Same arithmetic, in the same word order per row, as k_spmv.
 constexpr int kPairBlock = 128;
 
-template <int FMT>
+template <int FMT, bool BUF>
 __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
   constexpr int S = 2;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -138,6 +138,9 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
     c[i] = left_offset32((k0 + i) * kWave + lane, a.geo);
     acc[i] = 0.0f;
   }
+  __amdgpu_buffer_rsrc_t rs[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) rs[i] = slice_words(a.pack + off[i], w[i]);
   for (uint32_t j = 0; j < wm; j += kUnroll) {
     uint32_t p[S][kUnroll];
 #pragma unroll
@@ -145,7 +148,9 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
         uint32_t v = 0u;  // past the slice's width: a padding word
-        if (j + q < w[i]) v = __builtin_nontemporal_load(a.pack + off[i] + lane + (j + q) * kWave);
+        if (j + q < w[i])
+          v = BUF ? stream_word(rs[i], lane, j + q)
+                  : __builtin_nontemporal_load(a.pack + off[i] + lane + (j + q) * kWave);
         p[i][q] = v;
       }
     uint32_t cq[S][kUnroll];
@@ -195,7 +200,7 @@ struct UnitArgs {
   uint32_t n_units, n_split_slices, J;
 };
 
-template <int FMT>
+template <int FMT, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_spmv_units(SpmvArgs a, UnitArgs u) {
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t unit = __builtin_amdgcn_readfirstlane(b * (kBlock / kWave) + threadIdx.x / kWave);
@@ -211,11 +216,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_units(SpmvArgs a, UnitArgs u) {
   const uint32_t c0 = chunks == 1 ? left_offset32(t, a.geo) : u.ckpt[(base + c) * kWave + lane];
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 4u);
   float acc[1] = {0.0f};
-  packsell_row<FMT, 1>(a.pack + s + (int64_t)j0 * kWave + lane, kWave, wl, c0, a.cd,
-                       [&](uint32_t col, int, bool live) {
-                         return buffer_load_f32(rx, live ? col << 2 : a.m * 4u);
-                       },
-                       acc);
+  const uint32_t *first = a.pack + s + (int64_t)j0 * kWave;
+  const __amdgpu_buffer_rsrc_t rs = slice_words(first, wl);
+  packsell_row_f<FMT, 1>(
+      [&](uint32_t j) {
+        return BUF ? stream_word(rs, lane, j) : __builtin_nontemporal_load(first + lane + j * kWave);
+      },
+      wl, c0, a.cd,
+      [&](uint32_t col, int, bool live) { return buffer_load_f32(rx, live ? col << 2 : a.m * 4u); },
+      acc);
   if (chunks > 1) {
     u.partial[(base + c) * kWave + lane] = acc[0];
     return;
@@ -334,6 +343,9 @@ SpmvArgs make_args(const pksell_matrix *A, const float *x, float *y, int64_t k) 
   return a;
 }
 
+// The streamed word loads address a slice through 32-bit byte offsets.
+bool stream_words_ok(const pksell_matrix *A) { return A->n_words < (int64_t(1) << 30); }
+
 int check_matrix(const pksell_matrix *A) {
   PKS_CHECK(A, PKSELL_EINVAL, "null matrix");
   PKS_CHECK(A->n == 0 || (A->offset && (A->n_words == 0 || A->pack)), PKSELL_EINVAL,
@@ -346,11 +358,14 @@ int check_matrix(const pksell_matrix *A) {
 }
 
 template <int FMT, bool CW>
-int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, hipStream_t st) {
+int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, bool buf, hipStream_t st) {
   if (k == 1) {
     if constexpr (CW) {
       const int64_t waves = cdiv(base.n_slices, 2);
-      k_spmv_pair<FMT><<<cdiv(waves, kPairBlock / kWave), kPairBlock, 0, st>>>(base);
+      if (buf)
+        k_spmv_pair<FMT, true><<<cdiv(waves, kPairBlock / kWave), kPairBlock, 0, st>>>(base);
+      else
+        k_spmv_pair<FMT, false><<<cdiv(waves, kPairBlock / kWave), kPairBlock, 0, st>>>(base);
     } else {
       k_spmv<FMT, CW, 1, true><<<grid, kBlock, 0, st>>>(base);
     }
@@ -411,15 +426,18 @@ int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, hipStream_t st)
 }
 
 template <int FMT>
-int launch_fmt(const SpmvArgs &a, int64_t grid, int64_t k, int32_t C, hipStream_t st) {
-  return C == kWave ? launch_fmt_cw<FMT, true>(a, grid, k, st)
-                    : launch_fmt_cw<FMT, false>(a, grid, k, st);
+int launch_fmt(const SpmvArgs &a, int64_t grid, int64_t k, int32_t C, bool buf, hipStream_t st) {
+  return C == kWave ? launch_fmt_cw<FMT, true>(a, grid, k, buf, st)
+                    : launch_fmt_cw<FMT, false>(a, grid, k, buf, st);
 }
 
 template <int FMT>
-int launch_units(const SpmvArgs &a, const UnitArgs &u, hipStream_t st) {
+int launch_units(const SpmvArgs &a, const UnitArgs &u, bool buf, hipStream_t st) {
   constexpr int wpb = kBlock / kWave;
-  k_spmv_units<FMT><<<cdiv(u.n_units, wpb), kBlock, 0, st>>>(a, u);
+  if (buf)
+    k_spmv_units<FMT, true><<<cdiv(u.n_units, wpb), kBlock, 0, st>>>(a, u);
+  else
+    k_spmv_units<FMT, false><<<cdiv(u.n_units, wpb), kBlock, 0, st>>>(a, u);
   PKS_LAUNCHED();
   k_combine_chunks<FMT><<<cdiv(u.n_split_slices, wpb), kBlock, 0, st>>>(a, u);
   PKS_LAUNCHED();
@@ -462,17 +480,19 @@ int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, voi
               PKSELL_ERANGE, "too many work units");
     UnitArgs u{A->units, A->splits, A->ckpt, A->partial, (uint32_t)A->n_units,
                (uint32_t)A->n_split_slices, (uint32_t)A->split_words};
+    const bool buf = stream_words_ok(A);
     switch (A->fmt) {
-      case PKSELL_FP16: return launch_units<PKSELL_FP16>(a, u, st);
-      case PKSELL_E8MY: return launch_units<PKSELL_E8MY>(a, u, st);
-      default: return launch_units<PKSELL_FIX>(a, u, st);
+      case PKSELL_FP16: return launch_units<PKSELL_FP16>(a, u, buf, st);
+      case PKSELL_E8MY: return launch_units<PKSELL_E8MY>(a, u, buf, st);
+      default: return launch_units<PKSELL_FIX>(a, u, buf, st);
     }
   }
   const int64_t grid = cdiv(A->n_slices * A->C, kBlock);
+  const bool buf = stream_words_ok(A);
   switch (A->fmt) {
-    case PKSELL_FP16: return launch_fmt<PKSELL_FP16>(a, grid, k, A->C, st);
-    case PKSELL_E8MY: return launch_fmt<PKSELL_E8MY>(a, grid, k, A->C, st);
-    default: return launch_fmt<PKSELL_FIX>(a, grid, k, A->C, st);
+    case PKSELL_FP16: return launch_fmt<PKSELL_FP16>(a, grid, k, A->C, buf, st);
+    case PKSELL_E8MY: return launch_fmt<PKSELL_E8MY>(a, grid, k, A->C, buf, st);
+    default: return launch_fmt<PKSELL_FIX>(a, grid, k, A->C, buf, st);
   }
 }
 
