@@ -67,6 +67,17 @@ __device__ inline uint32_t stream_word(__amdgpu_buffer_rsrc_t rs, uint32_t lane,
   return __builtin_amdgcn_raw_buffer_load_b32(rs, (lane + j * kWave) * 4u, 0, kStreamPolicy);
 }
 
+// Element j of lane ``lane`` of a C = 64 slice of 4- or 8-byte elements
+// (the SELL comparators' columns and values), streamed the same way.
+template <typename T>
+__device__ inline T stream_elem(__amdgpu_buffer_rsrc_t rs, uint32_t lane, uint32_t j) {
+  const uint32_t off = (lane + j * kWave) * (uint32_t)sizeof(T);
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, kStreamPolicy));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kStreamPolicy));
+}
+
 // The PackSELL row loop (sec. 4.4) for one lane: walks the w words of its
 // slice lane in groups of kUnroll -- all loads of a group in flight
 // together, columns as running sums of deltas from c, then all gathers

@@ -134,14 +134,20 @@ struct SellView {
   uint32_t n, n_slices;
   int32_t C, perm_bytes;
   RowGeo geo;
+  uint32_t stream;  // C = 64 and arrays below 4 GiB: stream slots through buffer resources
 };
 
 // Row dot product of a SELL lane: sum over its w slots of val * gather(col).
-template <typename Gather>
+template <bool CWAVE, typename Gather>
 __device__ inline double sell_row(const SellView &S, const Lane &ln, uint32_t stride,
                                   Gather gather) {
   const int32_t *pc = S.col + ln.s + ln.l;
   const double *pv = S.val + ln.s + ln.l;
+  // streamed slots need a wave-uniform slice start (C = 64)
+  const bool buf = CWAVE && S.stream;
+  const __amdgpu_buffer_rsrc_t rc = make_rsrc(CWAVE ? S.col + ln.s : S.col, buf ? ln.w * 256u : 0u);
+  const __amdgpu_buffer_rsrc_t rv =
+      make_rsrc(CWAVE ? S.val + ln.s : S.val, buf ? ln.w * 512u : 0u);
   double acc = 0.0;
   for (uint32_t j = 0; j < ln.w; j += kUnroll) {
     int32_t cc[kUnroll];
@@ -149,8 +155,13 @@ __device__ inline double sell_row(const SellView &S, const Lane &ln, uint32_t st
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
       const uint32_t jj = min(j + q, ln.w - 1);
-      cc[q] = __builtin_nontemporal_load(pc + jj * stride);
-      vv[q] = j + q < ln.w ? __builtin_nontemporal_load(pv + jj * stride) : 0.0;
+      if (buf) {
+        cc[q] = stream_elem<int32_t>(rc, ln.l, jj);
+        vv[q] = j + q < ln.w ? stream_elem<double>(rv, ln.l, jj) : 0.0;
+      } else {
+        cc[q] = __builtin_nontemporal_load(pc + jj * stride);
+        vv[q] = j + q < ln.w ? __builtin_nontemporal_load(pv + jj * stride) : 0.0;
+      }
     }
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) acc = fma(vv[q], gather(cc[q]), acc);
@@ -434,7 +445,8 @@ __global__ __launch_bounds__(kB) void k_cg_a(SellView S, const double *__restric
   double part = 0.0;
   if (live) {
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
-    const double qi = sell_row(S, ln, stride, [&](int32_t c) { return fma(beta, p_old[c], r[c]); });
+    const double qi =
+        sell_row<CWAVE>(S, ln, stride, [&](int32_t c) { return fma(beta, p_old[c], r[c]); });
     if (ln.t < S.n) {
       const uint32_t i = out_row(S.perm, S.perm_bytes, ln.t, S.geo);
       const double pn = fma(beta, p_old[i], r[i]);
@@ -556,7 +568,7 @@ __global__ __launch_bounds__(kB) void k_outer_aq(SellView S, const double *__res
   double pq = 0.0, pr = 0.0;
   if (live) {
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
-    const double qi = sell_row(S, ln, stride, [&](int32_t c) { return p[c]; });
+    const double qi = sell_row<CWAVE>(S, ln, stride, [&](int32_t c) { return p[c]; });
     if (ln.t < S.n) {
       const uint32_t i = out_row(S.perm, S.perm_bytes, ln.t, S.geo);
       q[i] = qi;
@@ -618,7 +630,7 @@ __global__ __launch_bounds__(kB) void k_residual(SellView S, const double *__res
   double rr = 0.0, bb = 0.0;
   if (live) {
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
-    const double ax = sell_row(S, ln, stride, [&](int32_t c) { return x[c]; });
+    const double ax = sell_row<CWAVE>(S, ln, stride, [&](int32_t c) { return x[c]; });
     if (ln.t < S.n) {
       const uint32_t i = out_row(S.perm, S.perm_bytes, ln.t, S.geo);
       const double ri = b[i] - ax;
@@ -695,6 +707,7 @@ SellView sell_view(const pksell_sell *S) {
   v.C = S->C;
   v.perm_bytes = S->perm_bytes;
   v.geo = make_geo(S->sigma, 0, S->C);
+  v.stream = S->C == kWave && S->n_slots < (int64_t(1) << 29) ? 1u : 0u;
   return v;
 }
 

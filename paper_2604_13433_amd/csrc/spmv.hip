@@ -292,7 +292,9 @@ __global__ void k_fill_zero(T *p, int64_t len) {
 
 // Plain SELL-C-sigma SpMV (sec. 3): the float32 / float64 comparator, with
 // the same lane mapping and batched loads as the PackSELL kernel.
-template <typename T, bool CWAVE>
+// BUF (C = 64 and arrays below 4 GiB): columns and values are streamed
+// through per-slice buffer resources, as the PackSELL words are.
+template <typename T, bool CWAVE, bool BUF = false>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict__ offset,
                                                       const int32_t *__restrict__ scol,
                                                       const T *__restrict__ sval, const void *perm,
@@ -306,14 +308,23 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
   T acc = 0;
   const int32_t *pc = scol + ln.s + ln.l;
   const T *pv = sval + ln.s + ln.l;
+  // (BUF implies C = 64, where ln.s is wave-uniform)
+  const __amdgpu_buffer_rsrc_t rc = BUF ? make_rsrc(scol + ln.s, w * 256u) : make_rsrc(scol, 0u);
+  const __amdgpu_buffer_rsrc_t rv =
+      BUF ? make_rsrc(sval + ln.s, w * kWave * (uint32_t)sizeof(T)) : make_rsrc(sval, 0u);
   for (uint32_t j = 0; j < w; j += kUnroll) {
     int32_t cc[kUnroll];
     T vv[kUnroll];
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
       const bool in = j + q < w;
-      cc[q] = in ? __builtin_nontemporal_load(pc + (j + q) * stride) : 0;
-      vv[q] = in ? __builtin_nontemporal_load(pv + (j + q) * stride) : T(0);
+      if constexpr (BUF) {
+        cc[q] = in ? stream_elem<int32_t>(rc, ln.l, j + q) : 0;
+        vv[q] = in ? stream_elem<T>(rv, ln.l, j + q) : T(0);
+      } else {
+        cc[q] = in ? __builtin_nontemporal_load(pc + (j + q) * stride) : 0;
+        vv[q] = in ? __builtin_nontemporal_load(pv + (j + q) * stride) : T(0);
+      }
     }
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q)
@@ -530,16 +541,21 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
   }
   PKS_CHECK(x, PKSELL_EINVAL, "null x");
   const int64_t grid = cdiv(S->n_slices * S->C, kBlock);
-#define PKS_SELL(T, CW)                                                                       \
-  k_sell_spmv<T, CW><<<grid, kBlock, 0, st>>>(S->offset, S->col, static_cast<const T *>(S->val), \
+#define PKS_SELL(T, CW, BF)                                                                   \
+  k_sell_spmv<T, CW, BF><<<grid, kBlock, 0, st>>>(S->offset, S->col, static_cast<const T *>(S->val), \
                                              perm, S->perm_bytes, static_cast<const T *>(x),     \
                                              static_cast<T *>(y), (uint32_t)S->n,                \
                                              (uint32_t)S->n_slices, S->C,                        \
                                              make_geo(S->sigma, 0, S->C))
+  const bool buf = S->C == kWave && S->n_slots < (int64_t(1) << 29);
   if (S->dtype == PKSELL_F32) {
-    if (S->C == kWave) PKS_SELL(float, true); else PKS_SELL(float, false);
+    if (buf) PKS_SELL(float, true, true);
+    else if (S->C == kWave) PKS_SELL(float, true, false);
+    else PKS_SELL(float, false, false);
   } else {
-    if (S->C == kWave) PKS_SELL(double, true); else PKS_SELL(double, false);
+    if (buf) PKS_SELL(double, true, true);
+    else if (S->C == kWave) PKS_SELL(double, true, false);
+    else PKS_SELL(double, false, false);
   }
 #undef PKS_SELL
   PKS_LAUNCHED();
