@@ -34,7 +34,7 @@ struct SpmvArgs {
 // KB right-hand sides (columns r0 .. r0+KB-1 of the row-major x / y blocks;
 // K1: k == 1, so the x offset is a shift; V4: k and r0 are multiples of 4,
 // so x is gathered and y stored four columns at a time).
-template <int FMT, bool CWAVE, int KB, bool K1, bool V4 = false>
+template <int FMT, bool CWAVE, int KB, bool K1, bool V4 = false, bool BUF = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
   Lane ln;
   if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
@@ -52,6 +52,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
                                return buffer_load_f32x4(rx, live ? c * kx + x0 + 16u * g : oob);
                              },
                              acc);
+  } else if constexpr (BUF) {  // C = 64: streamed words (slice start is wave-uniform)
+    static_assert(CWAVE, "streamed words need C = 64");
+    const __amdgpu_buffer_rsrc_t rs = slice_words(a.pack + ln.s, ln.w);
+    packsell_row_f<FMT, KB>([&](uint32_t j) { return stream_word(rs, ln.l, j); }, ln.w,
+                            left_offset32(t, a.geo), a.cd,
+                            [&](uint32_t c, int r, bool live) {
+                              const uint32_t xo = K1 ? (c << 2) : (c * kx + x0 + 4u * r);
+                              return buffer_load_f32(rx, live ? xo : oob);
+                            },
+                            acc);
   } else {
     packsell_row<FMT, KB>(a.pack + ln.s + ln.l, stride, ln.w, left_offset32(t, a.geo), a.cd,
                           [&](uint32_t c, int r, bool live) {
@@ -334,6 +344,67 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
   y[out_row(perm, perm_bytes, t, g)] = acc;
 }
 
+// SELL with C = 64 and streamed slots, two slices per wave in 128-thread
+// workgroups: the comparator gets the same structure as k_spmv_pair.
+template <typename T>
+__global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restrict__ offset,
+                                                         const int32_t *__restrict__ scol,
+                                                         const T *__restrict__ sval,
+                                                         const void *perm, int32_t perm_bytes,
+                                                         const T *__restrict__ x,
+                                                         T *__restrict__ y, uint32_t n,
+                                                         uint32_t n_slices, RowGeo g) {
+  constexpr int S = 2;
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t wave =
+      __builtin_amdgcn_readfirstlane(b * (kPairBlock / kWave) + threadIdx.x / kWave);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t k0 = wave * S;
+  if (k0 >= n_slices) return;
+  int64_t off[S + 1];
+#pragma unroll
+  for (int i = 0; i <= S; ++i) off[i] = offset[min(k0 + i, n_slices)];
+  uint32_t w[S], wm = 0;
+  __amdgpu_buffer_rsrc_t rc[S], rv[S];
+  T acc[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    w[i] = (uint32_t)((off[i + 1] - off[i]) >> 6);
+    wm = max(wm, w[i]);
+    rc[i] = make_rsrc(scol + off[i], w[i] * 256u);
+    rv[i] = make_rsrc(sval + off[i], w[i] * kWave * (uint32_t)sizeof(T));
+    acc[i] = T(0);
+  }
+  for (uint32_t j = 0; j < wm; j += kUnroll) {
+    int32_t cc[S][kUnroll];
+    T vv[S][kUnroll];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const bool in = j + q < w[i];
+        cc[i][q] = in ? stream_elem<int32_t>(rc[i], lane, j + q) : 0;
+        vv[i][q] = in ? stream_elem<T>(rv[i], lane, j + q) : T(0);
+      }
+    T xv[S][kUnroll];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) xv[i][q] = j + q < w[i] ? x[cc[i][q]] : T(0);
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q)
+        if (j + q < w[i]) acc[i] += vv[i][q] * xv[i][q];
+  }
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    const uint32_t t = (k0 + i) * kWave + lane;
+    if (k0 + i >= n_slices || t >= n) continue;
+    y[out_row(perm, perm_bytes, t, g)] = acc[i];
+  }
+}
+
 SpmvArgs make_args(const pksell_matrix *A, const float *x, float *y, int64_t k) {
   SpmvArgs a;
   a.pack = A->pack;
@@ -368,10 +439,27 @@ int check_matrix(const pksell_matrix *A) {
   return PKSELL_OK;
 }
 
+// Two slices per wave pay off for narrow slices (the stencils: 7 words per
+// lane on the 128^3 and 256^3 Laplacians); for wide ones (81 on the block
+// stencil, thousands on power-law rows) one slice per wave ran faster, for
+// PackSELL and SELL alike.
+inline bool pair_slices(int64_t words, int64_t n_slices) {
+  return n_slices > 0 && words <= 16 * (int64_t)kWave * n_slices;
+}
+
 template <int FMT, bool CW>
-int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, bool buf, hipStream_t st) {
+int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, bool buf, bool pair,
+                  hipStream_t st) {
   if (k == 1) {
     if constexpr (CW) {
+      if (!pair) {
+        if (buf)
+          k_spmv<FMT, CW, 1, true, false, true><<<grid, kBlock, 0, st>>>(base);
+        else
+          k_spmv<FMT, CW, 1, true><<<grid, kBlock, 0, st>>>(base);
+        PKS_LAUNCHED();
+        return PKSELL_OK;
+      }
       const int64_t waves = cdiv(base.n_slices, 2);
       if (buf)
         k_spmv_pair<FMT, true><<<cdiv(waves, kPairBlock / kWave), kPairBlock, 0, st>>>(base);
@@ -437,9 +525,10 @@ int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, bool buf, hipSt
 }
 
 template <int FMT>
-int launch_fmt(const SpmvArgs &a, int64_t grid, int64_t k, int32_t C, bool buf, hipStream_t st) {
-  return C == kWave ? launch_fmt_cw<FMT, true>(a, grid, k, buf, st)
-                    : launch_fmt_cw<FMT, false>(a, grid, k, buf, st);
+int launch_fmt(const SpmvArgs &a, int64_t grid, int64_t k, int32_t C, bool buf, bool pair,
+               hipStream_t st) {
+  return C == kWave ? launch_fmt_cw<FMT, true>(a, grid, k, buf, pair, st)
+                    : launch_fmt_cw<FMT, false>(a, grid, k, buf, pair, st);
 }
 
 template <int FMT>
@@ -500,10 +589,11 @@ int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, voi
   }
   const int64_t grid = cdiv(A->n_slices * A->C, kBlock);
   const bool buf = stream_words_ok(A);
+  const bool pair = pair_slices(A->n_words, A->n_slices);
   switch (A->fmt) {
-    case PKSELL_FP16: return launch_fmt<PKSELL_FP16>(a, grid, k, A->C, buf, st);
-    case PKSELL_E8MY: return launch_fmt<PKSELL_E8MY>(a, grid, k, A->C, buf, st);
-    default: return launch_fmt<PKSELL_FIX>(a, grid, k, A->C, buf, st);
+    case PKSELL_FP16: return launch_fmt<PKSELL_FP16>(a, grid, k, A->C, buf, pair, st);
+    case PKSELL_E8MY: return launch_fmt<PKSELL_E8MY>(a, grid, k, A->C, buf, pair, st);
+    default: return launch_fmt<PKSELL_FIX>(a, grid, k, A->C, buf, pair, st);
   }
 }
 
@@ -548,7 +638,18 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
                                              (uint32_t)S->n_slices, S->C,                        \
                                              make_geo(S->sigma, 0, S->C))
   const bool buf = S->C == kWave && S->n_slots < (int64_t(1) << 29);
-  if (S->dtype == PKSELL_F32) {
+  // two slices per wave for narrow float32 slices (float64 ran slower paired)
+  if (buf && S->dtype == PKSELL_F32 && pair_slices(S->n_slots, S->n_slices)) {
+    const int64_t pg = cdiv(cdiv(S->n_slices, 2), kPairBlock / kWave);
+#define PKS_SELL2(T)                                                                      \
+  k_sell_pair<T><<<pg, kPairBlock, 0, st>>>(S->offset, S->col, static_cast<const T *>(S->val), \
+                                            perm, S->perm_bytes, static_cast<const T *>(x),    \
+                                            static_cast<T *>(y), (uint32_t)S->n,               \
+                                            (uint32_t)S->n_slices, make_geo(S->sigma, 0, S->C))
+    if (S->dtype == PKSELL_F32) PKS_SELL2(float);
+    else PKS_SELL2(double);
+#undef PKS_SELL2
+  } else if (S->dtype == PKSELL_F32) {
     if (buf) PKS_SELL(float, true, true);
     else if (S->C == kWave) PKS_SELL(float, true, false);
     else PKS_SELL(float, false, false);
