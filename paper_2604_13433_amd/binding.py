@@ -142,6 +142,12 @@ def _dev(t, dtype, device):
     return t.to(device=device, dtype=dtype).contiguous()
 
 
+# Integer fields of the descriptor (everything but the device pointers).
+_DESC_INTS = ("n", "m", "nnz", "C", "sigma", "D", "fmt", "perm_mode", "perm_bytes", "n_slices",
+              "n_words", "n_dummies", "k_left", "split_words", "n_units", "n_split_units",
+              "n_split_slices")
+
+
 class PackSELLMatrix:
     """A PackSELL matrix on the GPU (device arrays held as torch tensors)."""
 
@@ -213,6 +219,28 @@ class PackSELLMatrix:
         for name in ("units", "splits", "ckpt", "partial"):
             v = self.t.get(name)
             setattr(d, name, v.data_ptr() if v is not None else None)
+
+    def save(self, path: str):
+        """Writes the descriptor and every device array to an .npz file (no
+        pickles: plain arrays and integers)."""
+        d = self.desc
+        meta = {f: int(getattr(d, f)) for f in _DESC_INTS}
+        arrays = {k: v.cpu().numpy() for k, v in self.t.items()}
+        np.savez(path, **{f"meta_{k}": np.int64(v) for k, v in meta.items()},
+                 **{f"arr_{k}": v for k, v in arrays.items()})
+
+    @classmethod
+    def load(cls, path: str, device="cuda") -> "PackSELLMatrix":
+        """Reads a matrix written by ``save`` onto ``device``."""
+        device = torch.device(device)
+        with np.load(path, allow_pickle=False) as z:
+            desc = CMatrix()
+            for f in _DESC_INTS:
+                setattr(desc, f, int(z[f"meta_{f}"]))
+            t = {k[4:]: torch.from_numpy(z[k]).to(device) for k in z.files if k.startswith("arr_")}
+        m = cls(desc, t, device)
+        m._bind()
+        return m
 
     @property
     def split_words(self) -> int:

@@ -111,3 +111,15 @@ def test_stream_read_rejects_on_host():
     p = ctypes.cast(buf, ctypes.c_void_p)
     for nbytes, width, chunks in [(20, 4, 7), (0, 4, 7), (64, 8, 7), (64, 4, 0), (64, 4, 5000)]:
         assert B.lib().pksell_stream_read(p, nbytes, width, chunks, p, None) == B.EINVAL
+
+
+def test_encode_rejects_small_workspace():
+    rc, desc, ws = _query(n=100)
+    assert rc == 0 and ws > 0
+    buf = (ctypes.c_uint8 * max(ws, 4096))()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    desc.offset = p
+    desc.perm = p
+    rc = B.lib().pksell_encode(p, p, p, B.F32, ctypes.byref(desc), p, ws - 1, None)
+    assert rc == B.EWORKSPACE
+    assert b"workspace" in B.lib().pksell_last_error()

@@ -4,6 +4,7 @@ Encoded words, offsets, perm and decoded columns must match the oracle bit
 for bit; products must agree with the oracle's float64 product on the same
 quantised values within 1e-6, normalised by ||A_q||_inf ||x||_inf.
 """
+import ctypes
 import json
 import os
 
@@ -259,3 +260,55 @@ def test_m3_powerlaw_full_size():
     A, E = both(a, "fp16", 15, 64, 65536)
     assert_same_encoding(A, E)
     check_spmv(A, a, "fp16", 15, x, B.IMPLICIT, E)
+
+
+def test_every_word_slot_written():
+    """The fill phase writes every slot of every slice: driven through the C
+    ABI with ``pack`` pre-filled by a sentinel (0xDEADBEEF) that none of the
+    oracle's words equals for these inputs, the words end equal to the
+    oracle's."""
+    a = random_csr(31, 2000, 1700, per_row=9)
+    L_ = B.lib()
+    for fmt, D in [("fp16", 15), ("e8my", 3), ("fix", 12)]:
+        desc = B.CMatrix()
+        ws_bytes = ctypes.c_size_t()
+        B._check(L_.pksell_encode_query(a.n, a.m, a.nnz, 64, 256, D, B.FMT_BY_NAME[fmt],
+                                        B.IMPLICIT, ctypes.byref(desc), ctypes.byref(ws_bytes)))
+        t = {"offset": torch.empty(desc.n_slices + 1, dtype=torch.int64, device=DEV),
+             "perm": torch.empty(a.n * desc.perm_bytes, dtype=torch.uint8, device=DEV)}
+        ws = torch.empty(ws_bytes.value, dtype=torch.uint8, device=DEV)
+        rp = torch.from_numpy(a.rowptr).to(DEV)
+        cl = torch.from_numpy(a.col.astype(np.int32)).to(DEV)
+        vl = torch.from_numpy(a.val.astype(np.float32)).to(DEV)
+        M = B.PackSELLMatrix(desc, t, DEV)
+        M._bind()
+        st = B._stream(DEV)
+        args = (B._ptr(rp), B._ptr(cl), B._ptr(vl), B.F32, ctypes.byref(desc), B._ptr(ws),
+                ws_bytes.value, st)
+        B._check(L_.pksell_encode(*args))  # analyse
+        t["pack"] = torch.full((desc.n_words,), -0x21524111, dtype=torch.int32, device=DEV)
+        if fmt == "fix":
+            t["row_exp"] = torch.full((a.n,), 0x7777, dtype=torch.int16, device=DEV)
+        M._bind()
+        B._check(L_.pksell_encode(*args))  # fill
+        torch.cuda.synchronize()
+        E = P.encode(a.rowptr, a.col, a.val, a.n, a.m, FMTS[fmt], D, 64, 256)
+        assert not np.any(E.pack == 0xDEADBEEF)  # the sentinel is not a real word here
+        got = words(M)
+        assert np.array_equal(got, E.pack)
+        if fmt == "fix":
+            assert np.array_equal(M.row_exp.cpu().numpy().astype(np.int64), E.row_exp)
+
+
+def test_save_and_load_roundtrip(tmp_path):
+    a = random_csr(32, 900, 800, per_row=7)
+    x = torch.from_numpy(W.uniform_vector(a.m, 2)).to(DEV)
+    for fmt, D, split in [("e8my", 9, 0), ("fix", 15, 0), ("fp16", 15, 8)]:
+        A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 256, B.IMPLICIT, DEV,
+                     split_words=split)
+        path = str(tmp_path / f"m_{fmt}.npz")
+        A.save(path)
+        A2 = B.PackSELLMatrix.load(path, DEV)
+        assert A2.n_words == A.n_words and A2.k_left == A.k_left and A2.D == A.D
+        assert torch.equal(A2.pack, A.pack)
+        assert torch.equal(B.spmv(A2, x), B.spmv(A, x))
