@@ -269,6 +269,8 @@ def main():
         out["powerlaw"] = powerlaw_leg(args, torch, B, W)
         out["block3_27pt"] = block_leg(args, torch, B, W)
         out["laplace3d_256"] = large_leg(args, torch, B, W)
+    if not args.no_extra:
+        out["fp64_words"] = fp64_leg(args, a, torch, B, W)
     if not args.no_batched:
         out["batched"] = batched_leg(args, torch, B, W)
     if not args.no_pcg:
@@ -392,6 +394,49 @@ def powerlaw_leg(args, torch, B, W):
     log(f"[bench] powerlaw sell_fp32: {res['sell_fp32']}")
     for name, *_ in variants:
         res[name]["speedup_vs_sell_fp32"] = round(res["sell_fp32"]["us"] / res[name]["us"], 3)
+    return res
+
+
+def fp64_leg(args, a, torch, B, W):
+    """64-bit-word PackSELL (E11MY, 8 bytes per stored word) against FP64
+    SELL (12 bytes per slot), float64 x and y, on the 7-point 128^3
+    Laplacian (D = 15: E11M36, no dummies) and on the scaled 27-point 100^3
+    system of the solver leg (D = 14: E11M37), with the largest relative
+    change of the product against the unquantised float64 matrix."""
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, mat, D, mode in [("laplace3d_128", a, 15, B.EXPLICIT),
+                               ("stencil27_100", W.symmetric_diag_scale(W.m4_stencil27()), 14,
+                                B.IMPLICIT)]:
+        A = B.encode(mat.rowptr, mat.col, mat.val, mat.n, mat.m, "e11my", D, 64, 256, mode, dev)
+        S = B.sell_encode(mat.rowptr, mat.col, mat.val, mat.n, mat.m, torch.float64, 64, 256, mode,
+                          dev)
+        per_p, per_s = A.bytes_per_spmv(), S.bytes_per_spmv()
+        out = {}
+        for label, M, per, fn in [("packsell64", A, per_p, B.spmv_f64), ("sell_fp64", S, per_s,
+                                                                         B.sell_spmv)]:
+            R = max(2, int(math.ceil(args.replica_bytes / per)))
+            reps = [M] + [M.replicate() for _ in range(R - 1)]
+            xs = [torch.rand(mat.m, dtype=torch.float64, device=dev) * 2 - 1 for _ in range(R)]
+            ys = [torch.empty(mat.n, dtype=torch.float64, device=dev) for _ in range(R)]
+            ms = Timed(torch, lambda i: fn(reps[i], xs[i], ys[i]), R, min(args.steps, 200),
+                       min(args.warmup, 400)).run()
+            out[label] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
+                          "bytes": per}
+            if label == "packsell64":
+                yp = ys[0].clone()
+                x0 = xs[0]
+            else:
+                ys_ref = fn(M, x0)  # same x, unquantised FP64 values
+            del reps, xs, ys
+        diff = float((yp - ys_ref).abs().max() / ys_ref.abs().max().clamp_min(1e-300))
+        out["speedup_vs_sell_fp64"] = round(out["sell_fp64"]["us"] / out["packsell64"]["us"], 3)
+        out["D"] = D
+        out["words"] = A.n_words
+        out["max_rel_change_vs_fp64_values"] = diff
+        res[name] = out
+        log(f"[bench] 64-bit words {name}: {out}")
+        del A, S
     return res
 
 

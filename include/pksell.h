@@ -49,6 +49,10 @@ extern "C" {
 #define PKSELL_E8MY 1 /* FP32-compatible float, Y = 22 - D mantissa bits; 1 <= D <= 22 */
 #define PKSELL_FIX 2  /* (31-D)-bit two's-complement integer times a per-row
                          power of two; 1 <= D <= 29 */
+#define PKSELL_E11MY 3 /* 64-bit words (sec. 4.2.1 with W = 64): an
+                          FP64-compatible float with Y = 51 - D mantissa bits,
+                          the E8MY construction applied to FP64; 1 <= D <= 51.
+                          Products in float64 through pksell_spmv_f64 only. */
 
 /* ---- row permutation modes (sec. 3) ------------------------------------ */
 #define PKSELL_EXPLICIT 0 /* results are produced in stored (sorted) row order */
@@ -64,6 +68,8 @@ extern "C" {
  *
  *   pack     uint32[n_words]     slice k occupies [offset[k], offset[k+1]),
  *                                word j of lane l at offset[k] + j*C + l
+ *                                (E11MY: uint64[n_words], 64-bit words, the
+ *                                same layout; the pointer is cast)
  *   offset   int64[n_slices + 1] slice starts in words (sec. 3)
  *   perm     uint8 (sigma <= 256) or uint16 [n]  original row minus its
  *                                window start, per stored row (implicit mode
@@ -232,6 +238,14 @@ int pksell_csr_transpose(const int64_t *rowptr, const int32_t *col,
  * contents carry no meaning. */
 int pksell_stream_read(const void *src, size_t bytes, int32_t width,
                        int32_t chunks, float *out, void *stream);
+
+/* y = A_q x in float64 for 64-bit-word matrices (fmt E11MY): x float64[m],
+ * y float64[n] (original order in implicit mode, stored order in explicit
+ * mode), accumulated in float64 in word order.  One right-hand side.  Not
+ * in the paper as such: its W = 64 word with the E8MY value construction
+ * applied to FP64, for FP64 operators at 8 bytes per stored word.  Other
+ * product, adjoint, batched and solver entry points reject E11MY. */
+int pksell_spmv_f64(const pksell_matrix *A, const double *x, double *y, void *stream);
 
 /* Decodes every word position: cols[p] = column reconstructed at word p
  * (running sum of deltas from the left offset), vals[p] = decoded value

@@ -17,10 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpksell.so")
 
 OK, EINVAL, ERANGE, EWORKSPACE, EHIP, ENOTCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
-FP16, E8MY, FIX = 0, 1, 2
+FP16, E8MY, FIX, E11MY = 0, 1, 2, 3
 EXPLICIT, IMPLICIT = 0, 1
 F32, F64 = 4, 8
-FMT_BY_NAME = {"fp16": FP16, "e8my": E8MY, "fix": FIX}
+FMT_BY_NAME = {"fp16": FP16, "e8my": E8MY, "fix": FIX, "e11my": E11MY}
 
 i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
 
@@ -75,6 +75,7 @@ _PROTOS = {
                              ctypes.POINTER(CMatrix), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_encode": ([vp, vp, vp, i32, ctypes.POINTER(CMatrix), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "pksell_spmv": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
+    "pksell_spmv_f64": ([ctypes.POINTER(CMatrix), vp, vp, vp], ctypes.c_int),
     "pksell_spmv_t": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
     "pksell_grad_values": ([ctypes.POINTER(CMatrix), vp, vp, vp, vp, i64, vp], ctypes.c_int),
     "pksell_decode": ([ctypes.POINTER(CMatrix), vp, vp, vp], ctypes.c_int),
@@ -195,6 +196,11 @@ class PackSELLMatrix:
         dummies included), the offsets, perm (implicit), row exponents
         (FIX), x once and y once."""
         d = self.desc
+        if d.fmt == E11MY:  # 8-byte words, float64 x and y
+            b = 8 * d.n_words + 8 * (d.n_slices + 1) + 8 * d.m * k + 8 * d.n * k
+            if d.perm_mode == IMPLICIT:
+                b += d.perm_bytes * d.n
+            return int(b)
         b = 4 * d.n_words + 8 * (d.n_slices + 1) + 4 * d.m * k + 4 * d.n * k
         if d.perm_mode == IMPLICIT:
             b += d.perm_bytes * d.n
@@ -298,7 +304,8 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
                            _ptr(ws), ws_bytes.value, st))
     if analyse_only:
         return A
-    t["pack"] = torch.empty(max(1, desc.n_words), dtype=torch.int32, device=device)
+    wdt = torch.int64 if fmt == E11MY else torch.int32  # 64-bit words for E11MY
+    t["pack"] = torch.empty(max(1, desc.n_words), dtype=wdt, device=device)
     if fmt == FIX:
         t["row_exp"] = torch.empty(max(1, n), dtype=torch.int16, device=device)
     if desc.n_split_units > 0:
@@ -375,6 +382,16 @@ def spmv(A: PackSELLMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> t
     assert x.dtype == torch.float32 and x.is_contiguous() and x.shape[0] == A.m
     assert y.dtype == torch.float32 and y.is_contiguous() and y.shape[0] == A.n
     _check(lib().pksell_spmv(ctypes.byref(A.desc), _ptr(x), _ptr(y), k, _stream(x.device)))
+    return y
+
+
+def spmv_f64(A: PackSELLMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    """y = A_q x in float64 for a 64-bit-word (E11MY) matrix (x: m float64)."""
+    if y is None:
+        y = torch.empty(A.n, dtype=torch.float64, device=x.device)
+    assert x.dtype == torch.float64 and x.is_contiguous() and x.shape[0] == A.m
+    assert y.dtype == torch.float64 and y.is_contiguous() and y.shape[0] == A.n
+    _check(lib().pksell_spmv_f64(ctypes.byref(A.desc), _ptr(x), _ptr(y), _stream(x.device)))
     return y
 
 

@@ -362,6 +362,8 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
     const pksell_matrix *A = items[i].A;
     PKS_CHECK(A, PKSELL_EINVAL, "item %d: null matrix", i);
     PKS_CHECK(A->C == kWave, PKSELL_EINVAL, "item %d: batched products need C = 64", i);
+    PKS_CHECK(A->fmt >= PKSELL_FP16 && A->fmt <= PKSELL_FIX, PKSELL_EINVAL,
+              "item %d: batched products take FP16, E8MY or FIX words", i);
     PKS_CHECK(fmt < 0 || A->fmt == fmt, PKSELL_EINVAL, "item %d: all matrices need one format", i);
     fmt = A->fmt;
     PKS_CHECK(A->perm_mode != PKSELL_IMPLICIT || A->perm, PKSELL_EINVAL, "item %d: no perm", i);

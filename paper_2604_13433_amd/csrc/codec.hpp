@@ -78,6 +78,20 @@ __device__ inline uint32_t quant_e8my(float v, int D) {
   return sign | r;
 }
 
+// E11MY (64-bit words): the same integer rule on the FP64 pattern -- round
+// the magnitude bits to a multiple of 2^(D+1), ties away from zero, past the
+// largest finite value to infinity; NaN becomes 0x7FF8000000000000.
+__device__ inline uint64_t quant_e11my(double v, int D) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint64_t sign = b & 0x8000000000000000ull;
+  const uint64_t mag = b & 0x7FFFFFFFFFFFFFFFull;
+  if (mag > 0x7FF0000000000000ull) return 0x7FF8000000000000ull;
+  if (mag == 0x7FF0000000000000ull) return b;
+  uint64_t r = (mag + (1ull << D)) & ~((2ull << D) - 1ull);
+  if (r > 0x7FF0000000000000ull) r = 0x7FF0000000000000ull;
+  return sign | r;
+}
+
 // FIX: row exponent e = e(M) - (V - 1) with M = max |a| = f * 2^e(M),
 // 1/2 <= f < 1 (0 for M == 0); q = clamp(round_half_away(v * 2^-e),
 // +-(2^(V-1) - 1)) in the upper V bits.

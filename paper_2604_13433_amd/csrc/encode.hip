@@ -346,6 +346,42 @@ __global__ void k_fill_packsell(const int64_t *__restrict__ rowptr, const int32_
   while (j < w) put(0u, run);
 }
 
+// 64-bit words (E11MY): one thread per stored row position, as
+// k_fill_packsell; values are taken in float64.
+template <typename VT>
+__global__ void k_fill_packsell64(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                  const VT *__restrict__ val, int64_t n, int32_t C, int32_t sigma,
+                                  int64_t k_left, int32_t D, int64_t n_slices,
+                                  const int32_t *__restrict__ stored_rows,
+                                  const int64_t *__restrict__ offset, uint64_t *__restrict__ pack) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slices * C) return;
+  int64_t k = i / C, l = i - k * C;
+  int64_t s = offset[k];
+  int64_t w = (offset[k + 1] - s) / C;
+  uint64_t *out = pack + s + l;
+  int64_t j = 0;
+  if (i < n) {
+    int64_t r = stored_rows[i];
+    uint32_t prev = left_offset(r, sigma, k_left);
+    const uint32_t lim = D >= 31 ? 0xFFFFFFFFu : (1u << D);  // columns < 2^30
+    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      const uint32_t c = (uint32_t)col[e];
+      uint32_t d = c - prev;
+      prev = c;
+      const uint64_t vb = quant_e11my((double)val[e], D);
+      if (d >= lim) {
+        out[j * C] = (uint64_t)d << 1;  // dummy at the same column
+        ++j;
+        d = 0;
+      }
+      out[j * C] = vb | ((uint64_t)d << 1) | 1ull;
+      ++j;
+    }
+  }
+  for (; j < w; ++j) out[j * C] = 0ull;
+}
+
 template <typename VT, typename OT>
 __global__ void k_fill_sell(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                             const VT *__restrict__ val, int64_t n, int32_t C, int64_t n_slices,
@@ -524,6 +560,7 @@ int pksell_encode_query(int64_t n, int64_t m, int64_t nnz, int32_t C, int32_t si
     case PKSELL_FP16: PKS_CHECK(D == 15, PKSELL_EINVAL, "FP16 needs D = 15"); break;
     case PKSELL_E8MY: PKS_CHECK(D >= 1 && D <= 22, PKSELL_EINVAL, "E8MY needs 1 <= D <= 22"); break;
     case PKSELL_FIX: PKS_CHECK(D >= 1 && D <= 29, PKSELL_EINVAL, "FIX needs 1 <= D <= 29"); break;
+    case PKSELL_E11MY: PKS_CHECK(D >= 1 && D <= 51, PKSELL_EINVAL, "E11MY needs 1 <= D <= 51"); break;
     default: PKS_CHECK(false, PKSELL_EINVAL, "unknown format %d", fmt);
   }
   std::memset(A, 0, sizeof(*A));
@@ -550,6 +587,8 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val, in
             "implicit mode needs perm");
   Plan p = carve(ws, A->n, A->n_slices);
   PKS_CHECK(ws && ws_bytes >= p.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes", p.bytes);
+  PKS_CHECK(A->split_words == 0 || A->fmt != PKSELL_E11MY, PKSELL_EINVAL,
+            "split_words: not for 64-bit words (E11MY)");
   PKS_CHECK(A->split_words == 0 || (A->C == kWave && A->split_words % 8 == 0 &&
                                     A->split_words >= 8 && A->split_words <= (1 << 24)),
             PKSELL_EINVAL, "split_words must be 0 or a multiple of 8 in [8, 2^24], with C = 64");
@@ -581,6 +620,19 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val, in
     PKS_LAUNCHED();
   }
   const int64_t g = cdiv(rows, kBlock);
+  if (A->fmt == PKSELL_E11MY) {
+    uint64_t *pk = reinterpret_cast<uint64_t *>(A->pack);
+    if (val_dtype == PKSELL_F32)
+      k_fill_packsell64<float><<<g, kBlock, 0, st>>>(rowptr, col, static_cast<const float *>(val),
+                                                     A->n, A->C, A->sigma, A->k_left, A->D,
+                                                     A->n_slices, p.stored_rows, A->offset, pk);
+    else
+      k_fill_packsell64<double><<<g, kBlock, 0, st>>>(rowptr, col, static_cast<const double *>(val),
+                                                      A->n, A->C, A->sigma, A->k_left, A->D,
+                                                      A->n_slices, p.stored_rows, A->offset, pk);
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
 #define PKS_FILL(F, VT)                                                                      \
   k_fill_packsell<F, VT><<<g, kBlock, 0, st>>>(rowptr, col, static_cast<const VT *>(val),   \
                                                A->n, A->C, A->sigma, A->k_left, A->D,       \

@@ -970,6 +970,8 @@ int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi, const double 
     PKS_CHECK(A_lo->n == A_hi->n && A_lo->m == A_hi->m, PKSELL_EINVAL, "shape mismatch");
     PKS_CHECK(A_lo->perm_mode == PKSELL_IMPLICIT && A_lo->perm && A_lo->pack && A_lo->offset,
               PKSELL_EINVAL, "inner PackSELL matrix must be implicit with arrays set");
+    PKS_CHECK(A_lo->fmt >= PKSELL_FP16 && A_lo->fmt <= PKSELL_FIX, PKSELL_EINVAL,
+              "the inner matrix takes FP16, E8MY or FIX words");
     PKS_CHECK(A_lo->fmt != PKSELL_FIX || A_lo->row_exp, PKSELL_EINVAL, "FIX needs row_exp");
     PKS_CHECK(m_in >= 1 && m_in <= 10000, PKSELL_EINVAL, "m_in must be in [1, 10000]");
   }

@@ -405,6 +405,72 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
   }
 }
 
+// ---- 64-bit words (E11MY) in float64 -------------------------------------------
+
+struct Spmv64Args {
+  const uint64_t *pack;
+  const int64_t *offset;
+  const void *perm;
+  const double *x;
+  double *y;
+  uint32_t n, m, n_slices;
+  int32_t C, perm_bytes;
+  RowGeo geo;
+  uint32_t dmask;  // the flag-1 delta after >> 1 (columns < 2^30, so at most 31 bits)
+  uint64_t vmask;  // ~(2^(D+1) - 1): the value field
+};
+
+// The sec. 4.4 loop for 64-bit words: groups of eight words in flight, the
+// delta from the low half (every delta is below 2^30), the value field as a
+// float64, gathers of x in float64 (flag-0 words past the resource), float64
+// FMA in word order.  BUF (C = 64, words below 4 GiB): words streamed
+// through a buffer resource on the slice, as in the 32-bit kernels.
+template <bool CWAVE, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_spmv64(Spmv64Args a) {
+  Lane ln;
+  if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
+  const uint32_t t = ln.t, w = ln.w;
+  const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)a.C;
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 8u);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(BUF ? a.pack + ln.s : a.pack, BUF ? w * 512u : 0u);
+  const uint64_t *P = a.pack + ln.s + ln.l;
+  uint32_t c = left_offset32(t, a.geo);
+  double acc = 0.0;
+  for (uint32_t j = 0; j < w; j += kUnroll) {
+    uint64_t p[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      uint64_t v = 0ull;
+      if (j + q < w) {
+        if constexpr (BUF)
+          v = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(
+                                               rs, (ln.l + (j + q) * kWave) * 8u, 0, kStreamPolicy));
+        else
+          v = __builtin_nontemporal_load(P + (j + q) * stride);
+      }
+      p[q] = v;
+    }
+    uint32_t off[kUnroll];
+    double val[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const uint32_t lo = (uint32_t)p[q];
+      const bool flag = lo & 1u;
+      c += flag ? ((lo >> 1) & a.dmask) : (uint32_t)(p[q] >> 1);
+      off[q] = flag ? c * 8u : a.m * 8u;
+      val[q] = flag ? __builtin_bit_cast(double, p[q] & a.vmask) : 0.0;
+    }
+    double xv[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q)
+      xv[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, off[q], 0, 0));
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) acc = fma(val[q], xv[q], acc);
+  }
+  if (t >= a.n) return;
+  a.y[out_row(a.perm, a.perm_bytes, t, a.geo)] = acc;
+}
+
 SpmvArgs make_args(const pksell_matrix *A, const float *x, float *y, int64_t k) {
   SpmvArgs a;
   a.pack = A->pack;
@@ -430,6 +496,8 @@ bool stream_words_ok(const pksell_matrix *A) { return A->n_words < (int64_t(1) <
 
 int check_matrix(const pksell_matrix *A) {
   PKS_CHECK(A, PKSELL_EINVAL, "null matrix");
+  PKS_CHECK(A->fmt != PKSELL_E11MY, PKSELL_EINVAL,
+            "64-bit words (E11MY): use pksell_spmv_f64, the only entry point for them");
   PKS_CHECK(A->n == 0 || (A->offset && (A->n_words == 0 || A->pack)), PKSELL_EINVAL,
             "matrix arrays not set");
   PKS_CHECK(A->perm_mode != PKSELL_IMPLICIT || A->n == 0 || A->perm, PKSELL_EINVAL,
@@ -595,6 +663,46 @@ int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, voi
     case PKSELL_E8MY: return launch_fmt<PKSELL_E8MY>(a, grid, k, A->C, buf, pair, st);
     default: return launch_fmt<PKSELL_FIX>(a, grid, k, A->C, buf, pair, st);
   }
+}
+
+int pksell_spmv_f64(const pksell_matrix *A, const double *x, double *y, void *stream) {
+  PKS_CHECK(A, PKSELL_EINVAL, "null matrix");
+  PKS_CHECK(A->fmt == PKSELL_E11MY, PKSELL_EINVAL, "pksell_spmv_f64 needs fmt E11MY");
+  PKS_CHECK(A->n == 0 || (A->offset && (A->n_words == 0 || A->pack)), PKSELL_EINVAL,
+            "matrix arrays not set");
+  PKS_CHECK(A->perm_mode != PKSELL_IMPLICIT || A->n == 0 || A->perm, PKSELL_EINVAL,
+            "implicit mode needs perm");
+  PKS_CHECK(A->m < (int64_t(1) << 29), PKSELL_ERANGE, "m must be below 2^29 (8-byte x)");
+  PKS_CHECK(A->n == 0 || y, PKSELL_EINVAL, "null y");
+  hipStream_t st = as_stream(stream);
+  if (A->n == 0) return PKSELL_OK;
+  if (A->m == 0) {
+    k_fill_zero<double><<<cdiv(A->n, kBlock), kBlock, 0, st>>>(y, A->n);
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
+  PKS_CHECK(x, PKSELL_EINVAL, "null x");
+  Spmv64Args a;
+  a.pack = reinterpret_cast<const uint64_t *>(A->pack);
+  a.offset = A->offset;
+  a.perm = A->perm_mode == PKSELL_IMPLICIT ? A->perm : nullptr;
+  a.x = x;
+  a.y = y;
+  a.n = (uint32_t)A->n;
+  a.m = (uint32_t)A->m;
+  a.n_slices = (uint32_t)A->n_slices;
+  a.C = A->C;
+  a.perm_bytes = A->perm_bytes;
+  a.geo = make_geo(A->sigma, A->k_left, A->C);
+  a.dmask = A->D >= 31 ? 0x7FFFFFFFu : (1u << A->D) - 1u;
+  a.vmask = ~((2ull << A->D) - 1ull);
+  const int64_t grid = cdiv(A->n_slices * A->C, kBlock);
+  const bool buf = A->C == kWave && A->n_words < (int64_t(1) << 29);
+  if (buf) k_spmv64<true, true><<<grid, kBlock, 0, st>>>(a);
+  else if (A->C == kWave) k_spmv64<true, false><<<grid, kBlock, 0, st>>>(a);
+  else k_spmv64<false, false><<<grid, kBlock, 0, st>>>(a);
+  PKS_LAUNCHED();
+  return PKSELL_OK;
 }
 
 int pksell_decode(const pksell_matrix *A, int32_t *cols, float *vals, void *stream) {

@@ -65,6 +65,7 @@ def test_encode_query_sizes():
     (dict(sigma=0), B.EINVAL), (dict(sigma=65537), B.EINVAL),
     (dict(fmt=B.FP16, D=14), B.EINVAL), (dict(fmt=B.E8MY, D=0), B.EINVAL),
     (dict(fmt=B.E8MY, D=23), B.EINVAL), (dict(fmt=B.FIX, D=30), B.EINVAL),
+    (dict(fmt=B.E11MY, D=52), B.EINVAL), (dict(fmt=B.E11MY, D=0), B.EINVAL),
     (dict(fmt=7), B.EINVAL), (dict(mode=3), B.EINVAL), (dict(n=-1), B.EINVAL),
     (dict(n=1 << 30), B.ERANGE), (dict(m=1 << 30), B.ERANGE),
 ])
@@ -123,3 +124,9 @@ def test_encode_rejects_small_workspace():
     rc = B.lib().pksell_encode(p, p, p, B.F32, ctypes.byref(desc), p, ws - 1, None)
     assert rc == B.EWORKSPACE
     assert b"workspace" in B.lib().pksell_last_error()
+
+
+def test_encode_query_accepts_e11my_range():
+    for D in (1, 15, 51):
+        rc, d, ws = _query(fmt=B.E11MY, D=D)
+        assert rc == B.OK and d.fmt == B.E11MY and d.D == D
