@@ -580,7 +580,30 @@ def pcg_leg(args, torch, B, W):
                 best = (f"iocg_e8m{22 - D}_min{m_in}", r)
     res["best"] = best[0]
     res["best_speedup_vs_fp64_cg"] = best[1]["speedup_vs_fp64_cg"]
+    # the float64 operator as 64-bit-word PackSELL (E11M37, D = 14): it holds
+    # A rounded to 38 significant bits, so these solve that system; the
+    # FP64 SELL CG above stays the baseline of every speedup
+    hi64 = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e11my", 14, 64, 256, B.IMPLICIT, dev)
+    res["fp64_cg_words64"] = run_with(hi64, None, 0, run_fn=B.pcg, b=b)
+    log(f"[bench] FP64 CG, 64-bit-word operator: {res['fp64_cg_words64']}")
+    lo = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e8my", 14, 64, 256, B.IMPLICIT, dev)
+    r = run_with(hi64, lo, 20, run_fn=B.pcg, b=b)
+    r["speedup_vs_fp64_cg"] = round(res["fp64_cg"]["ms"] / r["ms"], 3)
+    res["iocg_e8m8_min20_words64_outer"] = r
+    log(f"[bench] IO-CG E8M8 m_in=20, 64-bit-word outer: {r}")
     return res
+
+
+def run_with(hi, lo, m_in, run_fn, b, reps=3):
+    """Median time of ``reps`` solves to 1e-10 (x0 = 0)."""
+    times, info, x = [], None, None
+    for _ in range(reps):
+        x, info = run_fn(lo, hi, b, tol=1e-10, m_in=max(m_in, 1), max_outer=20000)
+        times.append(info["seconds"])
+    return dict(ms=round(1e3 * sorted(times)[len(times) // 2], 2),
+                iterations=info["outer_iterations"], inner=info["inner_iterations"],
+                rel_residual=info["rel_residual"],
+                max_abs_err_vs_ones=float((x - 1.0).abs().max()))
 
 
 def cpu_leg(args, a, x_np, results, H, torch):

@@ -353,6 +353,22 @@ int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi,
                int32_t max_outer, pksell_pcg_info *info, void *ws,
                size_t ws_bytes, void *stream);
 
+/* The same solvers with the float64 operator A_hi given as a 64-bit-word
+ * PackSELL matrix (fmt E11MY, implicit row order, no split units) instead
+ * of float64 SELL: 8 bytes per stored word for the outer products and the
+ * true residual, instead of 12 per SELL slot.  Everything else (A_lo,
+ * arguments, synchronisation, status codes) is as in pksell_pcg; the system
+ * solved is the one whose matrix A_hi holds, i.e. A with its values rounded
+ * to 52 - D significant bits.  Both calls return PKSELL_EINVAL, before any
+ * device work, when A_hi is not an E11MY matrix; pksell_pcg64 also when it
+ * is not square or not in implicit row order. */
+int pksell_pcg64_workspace(const pksell_matrix *A_lo, const pksell_matrix *A_hi,
+                           size_t *ws_bytes);
+int pksell_pcg64(const pksell_matrix *A_lo, const pksell_matrix *A_hi,
+                 const double *b, double *x, double tol, int32_t m_in,
+                 int32_t max_outer, pksell_pcg_info *info, void *ws,
+                 size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,6 +98,10 @@ _PROTOS.update({
                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_pcg": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CSell), vp, vp, ctypes.c_double,
                     i32, i32, ctypes.POINTER(CPcgInfo), vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "pksell_pcg64_workspace": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CMatrix),
+                                ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pksell_pcg64": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CMatrix), vp, vp, ctypes.c_double,
+                      i32, i32, ctypes.POINTER(CPcgInfo), vp, ctypes.c_size_t, vp], ctypes.c_int),
 })
 
 OPTIONAL: dict = {}
@@ -509,21 +513,26 @@ class SolveInfo(dict):
     """Iteration counts, final true relative residual, wall seconds, status."""
 
 
-def pcg(A_lo: PackSELLMatrix | None, A_hi: SellMatrix, b: torch.Tensor,
+def pcg(A_lo: PackSELLMatrix | None, A_hi, b: torch.Tensor,
         x0: torch.Tensor | None = None, tol: float = 1e-10, m_in: int = 50,
         max_outer: int = 10000, check: bool = True):
     """Solve A x = b: inner-outer CG with a PackSELL inner operator, or plain
-    float64 CG when ``A_lo`` is None.  Returns (x, info)."""
+    float64 CG when ``A_lo`` is None.  ``A_hi`` (the float64 operator) is a
+    float64 SellMatrix or a 64-bit-word (E11MY) PackSELLMatrix.
+    Returns (x, info)."""
     assert b.dtype == torch.float64 and b.numel() == A_hi.n
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     ws_bytes = ctypes.c_size_t()
     lo = ctypes.byref(A_lo.desc) if A_lo is not None else None
     L = lib()
-    _check(L.pksell_pcg_workspace(lo, ctypes.byref(A_hi.desc), ctypes.byref(ws_bytes)))
+    words64 = isinstance(A_hi, PackSELLMatrix)
+    query = L.pksell_pcg64_workspace if words64 else L.pksell_pcg_workspace
+    run = L.pksell_pcg64 if words64 else L.pksell_pcg
+    _check(query(lo, ctypes.byref(A_hi.desc), ctypes.byref(ws_bytes)))
     ws = torch.empty(max(1, ws_bytes.value), dtype=torch.uint8, device=b.device)
     info = CPcgInfo()
-    st = L.pksell_pcg(lo, ctypes.byref(A_hi.desc), _ptr(b), _ptr(x), tol, m_in, max_outer,
-                      ctypes.byref(info), _ptr(ws), ws_bytes.value, _stream(b.device))
+    st = run(lo, ctypes.byref(A_hi.desc), _ptr(b), _ptr(x), tol, m_in, max_outer,
+             ctypes.byref(info), _ptr(ws), ws_bytes.value, _stream(b.device))
     out = SolveInfo(outer_iterations=info.outer_iterations,
                     inner_iterations=info.inner_iterations,
                     rel_residual=info.rel_residual, seconds=info.seconds, status=st)

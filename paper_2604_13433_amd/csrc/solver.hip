@@ -126,6 +126,8 @@ struct PackView {
   Codec cd;
 };
 
+// The float64 operator of the outer iteration and of FP64 CG: SELL slots
+// (kind 0: col + val) or 64-bit-word PackSELL (kind 1: E11MY words).
 struct SellView {
   const int64_t *offset;
   const int32_t *col;
@@ -134,13 +136,60 @@ struct SellView {
   uint32_t n, n_slices;
   int32_t C, perm_bytes;
   RowGeo geo;
-  uint32_t stream;  // C = 64 and arrays below 4 GiB: stream slots through buffer resources
+  uint32_t stream;  // C = 64 and arrays below 4 GiB: stream through buffer resources
+  uint32_t kind;    // 0: SELL, 1: 64-bit PackSELL words
+  const uint64_t *words;
+  uint32_t dmask;   // 64-bit words: the flag-1 delta after >> 1 (columns < 2^30)
+  uint64_t vmask;   // 64-bit words: the value field
 };
 
-// Row dot product of a SELL lane: sum over its w slots of val * gather(col).
+// Row dot product of a 64-bit-word PackSELL lane (sec. 4.4 with W = 64):
+// columns from the eq. 4 offset plus the deltas, value * gather(column) for
+// flag-1 words; flag-0 words add 0 * gather(column) (a valid column of the
+// square operator), which keeps the loop branch-free.
+template <bool CWAVE, typename Gather>
+__device__ inline double words64_row(const SellView &S, const Lane &ln, uint32_t stride,
+                                     Gather gather) {
+  const uint64_t *P = S.words + ln.s + ln.l;
+  const bool buf = CWAVE && S.stream;
+  const __amdgpu_buffer_rsrc_t rs =
+      make_rsrc(CWAVE ? S.words + ln.s : S.words, buf ? ln.w * 512u : 0u);
+  uint32_t c = left_offset32(ln.t, S.geo);
+  double acc = 0.0;
+  for (uint32_t j = 0; j < ln.w; j += kUnroll) {
+    uint64_t p[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      uint64_t v = 0ull;
+      if (j + q < ln.w)
+        v = buf ? __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(
+                                                   rs, (ln.l + (j + q) * kWave) * 8u, 0,
+                                                   kStreamPolicy))
+                : __builtin_nontemporal_load(P + (j + q) * stride);
+      p[q] = v;
+    }
+    uint32_t cq[kUnroll];
+    double vv[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const uint32_t lo = (uint32_t)p[q];
+      const bool flag = lo & 1u;
+      c += flag ? ((lo >> 1) & S.dmask) : (uint32_t)(p[q] >> 1);
+      cq[q] = c;
+      vv[q] = flag ? __builtin_bit_cast(double, p[q] & S.vmask) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) acc = fma(vv[q], gather((int32_t)cq[q]), acc);
+  }
+  return acc;
+}
+
+// Row dot product of a lane of the float64 operator: sum over its w slots
+// of val * gather(col).
 template <bool CWAVE, typename Gather>
 __device__ inline double sell_row(const SellView &S, const Lane &ln, uint32_t stride,
                                   Gather gather) {
+  if (S.kind == 1) return words64_row<CWAVE>(S, ln, stride, gather);
   const int32_t *pc = S.col + ln.s + ln.l;
   const double *pv = S.val + ln.s + ln.l;
   // streamed slots need a wave-uniform slice start (C = 64)
@@ -690,8 +739,8 @@ Work carve_work(void *ws, int64_t n, int64_t max_blocks) {
   return w;
 }
 
-int64_t max_blocks_of(const pksell_sell *S, const pksell_matrix *A) {
-  int64_t mb = cdiv(S->n_slices * S->C, kB);
+int64_t max_blocks_of(const SellView &S, const pksell_matrix *A) {
+  int64_t mb = cdiv((int64_t)S.n_slices * S.C, kB);
   if (A) mb = std::max<int64_t>(mb, cdiv(A->n_slices * A->C, kB));
   return std::max<int64_t>(mb, 1);
 }
@@ -708,6 +757,30 @@ SellView sell_view(const pksell_sell *S) {
   v.perm_bytes = S->perm_bytes;
   v.geo = make_geo(S->sigma, 0, S->C);
   v.stream = S->C == kWave && S->n_slots < (int64_t(1) << 29) ? 1u : 0u;
+  v.kind = 0;
+  v.words = nullptr;
+  v.dmask = 0;
+  v.vmask = 0;
+  return v;
+}
+
+// The float64 operator from a 64-bit-word (E11MY) PackSELL matrix.
+SellView words64_view(const pksell_matrix *A) {
+  SellView v;
+  v.offset = A->offset;
+  v.col = nullptr;
+  v.val = nullptr;
+  v.perm = A->perm;
+  v.n = (uint32_t)A->n;
+  v.n_slices = (uint32_t)A->n_slices;
+  v.C = A->C;
+  v.perm_bytes = A->perm_bytes;
+  v.geo = make_geo(A->sigma, A->k_left, A->C);
+  v.stream = A->C == kWave && A->n_words < (int64_t(1) << 29) ? 1u : 0u;
+  v.kind = 1;
+  v.words = reinterpret_cast<const uint64_t *>(A->pack);
+  v.dmask = A->D >= 31 ? 0x7FFFFFFFu : (1u << A->D) - 1u;
+  v.vmask = ~((2ull << A->D) - 1ull);
   return v;
 }
 
@@ -728,7 +801,7 @@ PackView pack_view(const pksell_matrix *A) {
 
 struct Solve {
   const pksell_matrix *lo;
-  const pksell_sell *hi;
+  SellView hv;  // the float64 operator
   const double *b;
   double *x;
   Work w;
@@ -742,9 +815,9 @@ struct Solve {
 
   // r = b - A x, then rr and bnorm2 into the state (two launches).
   int residual() {
-    const SellView S = sell_view(hi);
+    const SellView &S = hv;
     const Parts out = pa_for(gs);
-    if (hi->C == kWave)
+    if (hv.C == kWave)
       k_residual<true><<<gs, kB, 0, s>>>(S, b, x, w.r, out);
     else
       k_residual<false><<<gs, kB, 0, s>>>(S, b, x, w.r, out);
@@ -757,14 +830,14 @@ struct Solve {
   // Enqueues ``count`` float64 CG iterations (count even: the p buffers and
   // the r.r partial sets alternate, so a replay starts where the last ended).
   int cg_iterations(int count) {
-    const SellView S = sell_view(hi);
+    const SellView &S = hv;
     for (int it = 0; it < count; ++it) {
       double *po = (it & 1) ? w.p1 : w.p0;
       double *pn = (it & 1) ? w.p0 : w.p1;
       const Parts rr_in = vec((it & 1) ? w.pb0 : w.pb1);
       const Parts rr_out = vec((it & 1) ? w.pb1 : w.pb0);
       const Parts pq = pa_for(gs);
-      if (hi->C == kWave)
+      if (hv.C == kWave)
         k_cg_a<true><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, rr_in, pq);
       else
         k_cg_a<false><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, rr_in, pq);
@@ -790,7 +863,7 @@ struct Solve {
 
   // Enqueues one flexible-CG outer iteration with m_in inner iterations.
   int outer_iteration(int m_in) {
-    const SellView S = sell_view(hi);
+    const SellView &S = hv;
     const PackView A = pack_view(lo);
     const Parts ppq = pa_for(gp);
     k_inner_init<<<vb, kB, 0, s>>>(n, w.r, w.rin, w.zin, w.f0, w.st, vec(w.pb0));
@@ -815,7 +888,7 @@ struct Solve {
     k_outer_p<<<vb, kB, 0, s>>>(n, w.zin, w.p0, w.st, vec(w.pb0));
     PKS_LAUNCHED();
     const Parts paq = pa_for(gs);
-    if (hi->C == kWave)
+    if (hv.C == kWave)
       k_outer_aq<true><<<gs, kB, 0, s>>>(S, w.p0, w.r, w.q, w.st, paq);
     else
       k_outer_aq<false><<<gs, kB, 0, s>>>(S, w.p0, w.r, w.q, w.st, paq);
@@ -941,33 +1014,14 @@ int solve(Solve &sv, double tol, int32_t m_in, int32_t max_outer, pksell_pcg_inf
   return status;
 }
 
-}  // namespace
-}  // namespace pksell
-
-using namespace pksell;
-
-extern "C" {
-
-int pksell_pcg_workspace(const pksell_matrix *A_lo, const pksell_sell *A_hi, size_t *ws_bytes) {
-  PKS_CHECK(A_hi && ws_bytes, PKSELL_EINVAL, "null argument");
-  *ws_bytes = carve_work(nullptr, A_hi->n, max_blocks_of(A_hi, A_lo)).bytes;
-  return PKSELL_OK;
-}
-
-int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi, const double *b, double *x,
-               double tol, int32_t m_in, int32_t max_outer, pksell_pcg_info *info, void *ws,
-               size_t ws_bytes, void *stream) {
+// The shared body of pksell_pcg and pksell_pcg64 once the outer operator's
+// own checks passed: inner-matrix checks, the workspace, a private stream.
+int run_pcg(const pksell_matrix *A_lo, const SellView &hv, int64_t n, const double *b, double *x,
+            double tol, int32_t m_in, int32_t max_outer, pksell_pcg_info *info, void *ws,
+            size_t ws_bytes, void *stream) {
   const auto t0 = std::chrono::steady_clock::now();
-  PKS_CHECK(A_hi && b && x && info, PKSELL_EINVAL, "null argument");
-  std::memset(info, 0, sizeof(*info));
-  PKS_CHECK(A_hi->n == A_hi->m, PKSELL_EINVAL, "the matrix must be square");
-  PKS_CHECK(A_hi->dtype == PKSELL_F64, PKSELL_EINVAL, "the outer matrix must be float64 SELL");
-  PKS_CHECK(A_hi->perm_mode == PKSELL_IMPLICIT, PKSELL_EINVAL,
-            "the solver needs implicit row order (original ordering)");
-  PKS_CHECK(A_hi->n > 0 && A_hi->offset && A_hi->col && A_hi->val && A_hi->perm, PKSELL_EINVAL,
-            "outer matrix arrays not set");
   if (A_lo) {
-    PKS_CHECK(A_lo->n == A_hi->n && A_lo->m == A_hi->m, PKSELL_EINVAL, "shape mismatch");
+    PKS_CHECK(A_lo->n == n && A_lo->m == n, PKSELL_EINVAL, "shape mismatch");
     PKS_CHECK(A_lo->perm_mode == PKSELL_IMPLICIT && A_lo->perm && A_lo->pack && A_lo->offset,
               PKSELL_EINVAL, "inner PackSELL matrix must be implicit with arrays set");
     PKS_CHECK(A_lo->fmt >= PKSELL_FP16 && A_lo->fmt <= PKSELL_FIX, PKSELL_EINVAL,
@@ -978,15 +1032,15 @@ int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi, const double 
   PKS_CHECK(tol > 0.0 && max_outer >= 1, PKSELL_EINVAL, "tol must be > 0, max_outer >= 1");
   Solve sv;
   sv.lo = A_lo;
-  sv.hi = A_hi;
+  sv.hv = hv;
   sv.b = b;
   sv.x = x;
-  sv.n = (uint32_t)A_hi->n;
-  sv.vb = (uint32_t)std::min<int64_t>(kVecBlocks, cdiv(A_hi->n, kB));
-  sv.gs = (uint32_t)cdiv(A_hi->n_slices * A_hi->C, kB);
+  sv.n = (uint32_t)n;
+  sv.vb = (uint32_t)std::min<int64_t>(kVecBlocks, cdiv(n, kB));
+  sv.gs = (uint32_t)cdiv((int64_t)hv.n_slices * hv.C, kB);
   sv.gp = A_lo ? (uint32_t)cdiv(A_lo->n_slices * A_lo->C, kB) : 0u;
   sv.stream_ok = A_lo && A_lo->n_words < (int64_t(1) << 30);
-  sv.w = carve_work(ws, A_hi->n, max_blocks_of(A_hi, A_lo));
+  sv.w = carve_work(ws, n, max_blocks_of(hv, A_lo));
   PKS_CHECK(ws && ws_bytes >= sv.w.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes",
             sv.w.bytes);
   // The solve runs on a private stream (graph capture needs a non-default
@@ -1003,6 +1057,57 @@ int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi, const double 
   info->seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return rc;
+}
+
+}  // namespace
+}  // namespace pksell
+
+using namespace pksell;
+
+extern "C" {
+
+int pksell_pcg_workspace(const pksell_matrix *A_lo, const pksell_sell *A_hi, size_t *ws_bytes) {
+  PKS_CHECK(A_hi && ws_bytes, PKSELL_EINVAL, "null argument");
+  *ws_bytes = carve_work(nullptr, A_hi->n, max_blocks_of(sell_view(A_hi), A_lo)).bytes;
+  return PKSELL_OK;
+}
+
+int pksell_pcg64_workspace(const pksell_matrix *A_lo, const pksell_matrix *A_hi,
+                           size_t *ws_bytes) {
+  PKS_CHECK(A_hi && ws_bytes, PKSELL_EINVAL, "null argument");
+  PKS_CHECK(A_hi->fmt == PKSELL_E11MY, PKSELL_EINVAL, "the outer matrix must have 64-bit words");
+  *ws_bytes = carve_work(nullptr, A_hi->n, max_blocks_of(words64_view(A_hi), A_lo)).bytes;
+  return PKSELL_OK;
+}
+
+int pksell_pcg(const pksell_matrix *A_lo, const pksell_sell *A_hi, const double *b, double *x,
+               double tol, int32_t m_in, int32_t max_outer, pksell_pcg_info *info, void *ws,
+               size_t ws_bytes, void *stream) {
+  PKS_CHECK(A_hi && b && x && info, PKSELL_EINVAL, "null argument");
+  std::memset(info, 0, sizeof(*info));
+  PKS_CHECK(A_hi->n == A_hi->m, PKSELL_EINVAL, "the matrix must be square");
+  PKS_CHECK(A_hi->dtype == PKSELL_F64, PKSELL_EINVAL, "the outer matrix must be float64 SELL");
+  PKS_CHECK(A_hi->perm_mode == PKSELL_IMPLICIT, PKSELL_EINVAL,
+            "the solver needs implicit row order (original ordering)");
+  PKS_CHECK(A_hi->n > 0 && A_hi->offset && A_hi->col && A_hi->val && A_hi->perm, PKSELL_EINVAL,
+            "outer matrix arrays not set");
+  return run_pcg(A_lo, sell_view(A_hi), A_hi->n, b, x, tol, m_in, max_outer, info, ws, ws_bytes,
+                 stream);
+}
+
+int pksell_pcg64(const pksell_matrix *A_lo, const pksell_matrix *A_hi, const double *b, double *x,
+                 double tol, int32_t m_in, int32_t max_outer, pksell_pcg_info *info, void *ws,
+                 size_t ws_bytes, void *stream) {
+  PKS_CHECK(A_hi && b && x && info, PKSELL_EINVAL, "null argument");
+  std::memset(info, 0, sizeof(*info));
+  PKS_CHECK(A_hi->fmt == PKSELL_E11MY, PKSELL_EINVAL, "the outer matrix must have 64-bit words");
+  PKS_CHECK(A_hi->n == A_hi->m, PKSELL_EINVAL, "the matrix must be square");
+  PKS_CHECK(A_hi->perm_mode == PKSELL_IMPLICIT, PKSELL_EINVAL,
+            "the solver needs implicit row order (original ordering)");
+  PKS_CHECK(A_hi->n > 0 && A_hi->offset && A_hi->pack && A_hi->perm, PKSELL_EINVAL,
+            "outer matrix arrays not set");
+  return run_pcg(A_lo, words64_view(A_hi), A_hi->n, b, x, tol, m_in, max_outer, info, ws,
+                 ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -130,3 +130,26 @@ def test_encode_query_accepts_e11my_range():
     for D in (1, 15, 51):
         rc, d, ws = _query(fmt=B.E11MY, D=D)
         assert rc == B.OK and d.fmt == B.E11MY and d.D == D
+
+
+def test_pcg64_rejects_on_host():
+    """The 64-bit-word solver checks its outer matrix before any device work:
+    a 32-bit-word matrix, a non-square one and explicit row order are
+    rejected; dummy host buffers stand in for the device arrays."""
+    buf = (ctypes.c_double * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    info = B.CPcgInfo()
+    ws = ctypes.c_size_t()
+    L = B.lib()
+    cases = [dict(fmt=B.E8MY, D=9), dict(fmt=B.E11MY, D=14, m=90),
+             dict(fmt=B.E11MY, D=14, mode=B.EXPLICIT)]
+    for kw in cases:
+        rc, desc, _ = _query(**kw)
+        assert rc == B.OK
+        desc.offset = desc.perm = desc.pack = p
+        rc = L.pksell_pcg64(None, ctypes.byref(desc), p, p, 1e-8, 5, 5, ctypes.byref(info), p,
+                            512, None)
+        assert rc == B.EINVAL, kw
+        assert L.pksell_last_error()
+    rc, desc, _ = _query(fmt=B.E8MY, D=9)
+    assert L.pksell_pcg64_workspace(None, ctypes.byref(desc), ctypes.byref(ws)) == B.EINVAL

@@ -4,8 +4,9 @@ Words and offsets must equal the 64-bit oracle's bit for bit; products must
 equal the oracle's float64 product on the same quantised values within
 1e-13, normalised by ||A_q||_inf ||x||_inf (float64 accumulation, so the
 bar is set by float64 rounding, not by the 1e-6 of the float32 products).
-Every other product, adjoint, batched and solver entry point must reject
-64-bit-word matrices.
+Every other product, adjoint and batched entry point, and the solvers'
+inner (float32) operator, must reject 64-bit-word matrices; the solvers
+take them only as the float64 operator (tests/test_gpu_pcg.py).
 """
 import numpy as np
 import pytest

@@ -104,3 +104,44 @@ def test_rejects_explicit_order():
     with pytest.raises(B.PackSELLError) as e:
         B.pcg(None, hi, torch.from_numpy(b).to(DEV))
     assert e.value.status == B.EINVAL
+
+
+def test_fp64_cg_on_64_bit_words():
+    """Plain float64 CG with the operator given as 64-bit-word PackSELL
+    (E11M37): it solves the system of the values it holds, so it is checked
+    against the oracle's CG on those quantised values."""
+    from oracle import packsell64 as P64
+
+    a, b = system()
+    D = 14
+    hi = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e11my", D, 64, 256, B.IMPLICIT, DEV)
+    x, info = B.pcg(None, hi, torch.from_numpy(b).to(DEV), tol=1e-10, max_outer=5000)
+    x = x.cpu().numpy()
+    q = P64.quantized(a.val, D)
+    true = np.linalg.norm(b - L.spmv(a.rowptr, a.col, q, x)) / np.linalg.norm(b)
+    assert info["rel_residual"] < 1e-10 and true < 1e-10
+    ref = L.cg(a.rowptr, a.col, q, b, tol=1e-10)
+    assert np.max(np.abs(x - ref.x)) < 1e-7
+    assert abs(info["outer_iterations"] - ref.iterations) <= max(3, ref.iterations // 50)
+    assert np.max(np.abs(x - 1.0)) < 1e-6  # the quantised system is within 2^-38 of A
+
+
+@pytest.mark.parametrize("inner", [("e8my", 9), ("fp16", 15)])
+def test_iocg_with_64_bit_outer_operator(inner):
+    from oracle import packsell64 as P64
+
+    a, b = system(20, 4)
+    D = 14
+    lo = B.encode(a.rowptr, a.col, a.val, a.n, a.m, inner[0], inner[1], 64, 256, B.IMPLICIT, DEV)
+    hi = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e11my", D, 64, 256, B.IMPLICIT, DEV)
+    x, info = B.pcg(lo, hi, torch.from_numpy(b).to(DEV), tol=1e-10, m_in=20, max_outer=500)
+    x = x.cpu().numpy()
+    q_hi = P64.quantized(a.val, D)
+    true = np.linalg.norm(b - L.spmv(a.rowptr, a.col, q_hi, x)) / np.linalg.norm(b)
+    assert info["rel_residual"] < 1e-10 and true < 1e-10
+    q_lo = P.quantized_values(a.rowptr, a.col, a.val, a.n,
+                              {"e8my": F.FMT_E8MY, "fp16": F.FMT_FP16}[inner[0]], inner[1])
+    ref = L.iocg(a.rowptr, a.col, q_hi, q_lo, b, m_in=20, tol=1e-10)
+    assert ref.converged
+    assert np.max(np.abs(x - ref.x)) < 1e-7
+    assert abs(info["outer_iterations"] - ref.iterations) <= max(2, ref.iterations // 3)
