@@ -17,6 +17,52 @@ __device__ inline uint32_t out_row(const void *perm, int32_t perm_bytes, uint32_
                                               : (uint32_t) static_cast<const uint16_t *>(perm)[t]);
 }
 
+// The destination of stored row t: block_start(t) + perm[t] in implicit
+// order, t itself in explicit order; and, for FIX, the row's scale exponent.
+// row_out issues the perm and row_exp loads at the start of the row's work,
+// through buffer resources (lanes with t >= n read 0 and store nothing, so
+// no divergent branch), and keeps the raw loaded values: they are combined
+// only where the result is stored.  Using a loaded value right away would
+// make the wave wait for that load before it issues its word loads.
+struct RowOut {
+  uint32_t base, p;
+  uint32_t e;  // FIX: the raw int16 row exponent
+  // The empty asm pins the use of the loaded value here: without it the
+  // compiler may fold the addition back next to the load (into the blocks
+  // that feed a loop-carried RowOut), which reintroduces the early wait.
+  __device__ uint32_t row() const {
+    uint32_t q = p;
+    asm volatile("" : "+v"(q));
+    return base + q;
+  }
+  __device__ int shift(const Codec &cd) const {
+    uint32_t q = e;
+    asm volatile("" : "+v"(q));
+    return (int)(int16_t)q - (cd.D + 1);
+  }
+};
+
+__device__ inline RowOut row_out(const void *perm, int32_t perm_bytes, uint32_t t, uint32_t n,
+                                 const RowGeo &g) {
+  RowOut r{t, 0u, 0u};
+  if (perm != nullptr) {
+    r.base = block_start(t, g);
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(perm, n * (uint32_t)perm_bytes);
+    r.p = perm_bytes == 1 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rp, t, 0, 0)
+                          : (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rp, 2u * t, 0, 0);
+  }
+  return r;
+}
+
+template <int FMT>
+__device__ inline RowOut row_out(const void *perm, int32_t perm_bytes, const int16_t *row_exp,
+                                 uint32_t t, uint32_t n, const RowGeo &g) {
+  RowOut r = row_out(perm, perm_bytes, t, n, g);
+  if constexpr (FMT == PKSELL_FIX)
+    r.e = __builtin_amdgcn_raw_buffer_load_b16(make_rsrc(row_exp, 2u * n), 2u * t, 0, 0);
+  return r;
+}
+
 // Slice coordinates of the calling lane: stored row t, slice k = t / C,
 // lane l, slice start s (words) and width w.  With C = 64 a wave is exactly
 // one slice, so k, s and w are made wave-uniform (scalar loads, scalar loop).

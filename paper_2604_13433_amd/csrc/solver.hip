@@ -244,6 +244,8 @@ __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restr
   const float beta = (float)beta_d;
   Lane ln;
   const bool live = lane_slice<CWAVE>(A.offset, A.n_slices, A.geo, ln);
+  const RowOut ro =
+      row_out<FMT>(A.perm, A.perm_bytes, A.row_exp, live ? ln.t : A.n, A.n, A.geo);
   double part = 0.0;
   if (live) {
     const __amdgpu_buffer_rsrc_t rr_r = make_rsrc(r, A.n * 4u);
@@ -258,8 +260,8 @@ __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restr
                          acc);
     if (ln.t < A.n) {
       float qi = acc[0];
-      if constexpr (FMT == PKSELL_FIX) qi = ldexpf(qi, (int)A.row_exp[ln.t] - (A.cd.D + 1));
-      const uint32_t i = out_row(A.perm, A.perm_bytes, ln.t, A.geo);
+      if constexpr (FMT == PKSELL_FIX) qi = ldexpf(qi, ro.shift(A.cd));
+      const uint32_t i = ro.row();
       const float pn = fmaf(beta, p_old[i], r[i]);
       p_new[i] = pn;
       q[i] = qi;
@@ -294,6 +296,11 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
   __amdgpu_buffer_rsrc_t rs[S];
 #pragma unroll
   for (int i = 0; i <= S; ++i) off[i] = A.offset[min(k0 + i, A.n_slices)];
+  RowOut ro[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+    ro[i] = row_out<FMT>(A.perm, A.perm_bytes, A.row_exp, stop ? A.n : (k0 + i) * kWave + lane,
+                         A.n, A.geo);
   auto word = [&](int i, uint32_t j) {
     return BUF ? stream_word(rs[i], lane, j)
                : __builtin_nontemporal_load(A.pack + off[i] + lane + j * kWave);
@@ -373,8 +380,8 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
     const uint32_t t = (k0 + i) * kWave + lane;
     if (k0 + i >= A.n_slices || t >= A.n) continue;
     float qi = acc[i];
-    if constexpr (FMT == PKSELL_FIX) qi = ldexpf(qi, (int)A.row_exp[t] - (A.cd.D + 1));
-    const uint32_t row = out_row(A.perm, A.perm_bytes, t, A.geo);
+    if constexpr (FMT == PKSELL_FIX) qi = ldexpf(qi, ro[i].shift(A.cd));
+    const uint32_t row = ro[i].row();
     const float pn = fmaf(beta, p_old[row], r[row]);
     p_new[row] = pn;
     q[row] = qi;
@@ -491,14 +498,25 @@ __global__ __launch_bounds__(kB) void k_cg_a(SellView S, const double *__restric
   if (stop || conv) return;
   Lane ln;
   const bool live = lane_slice<CWAVE>(S.offset, S.n_slices, S.geo, ln);
+  const RowOut ri = row_out(S.perm, S.perm_bytes, live ? ln.t : S.n, S.n, S.geo);
   double part = 0.0;
   if (live) {
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
-    const double qi =
-        sell_row<CWAVE>(S, ln, stride, [&](int32_t c) { return fma(beta, p_old[c], r[c]); });
+    // p_new at the row's own index: from the gathers when that column is
+    // among them (the same fma of the same values), else loaded
+    double own = 0.0;
+    bool found = false;
+    const double qi = sell_row<CWAVE>(S, ln, stride, [&](int32_t c) {
+      const double g = fma(beta, p_old[c], r[c]);
+      if ((uint32_t)c - ri.base == ri.p) {  // column c is the row's own index
+        own = g;
+        found = true;
+      }
+      return g;
+    });
     if (ln.t < S.n) {
-      const uint32_t i = out_row(S.perm, S.perm_bytes, ln.t, S.geo);
-      const double pn = fma(beta, p_old[i], r[i]);
+      const uint32_t i = ri.row();
+      const double pn = found ? own : fma(beta, p_old[i], r[i]);
       p_new[i] = pn;
       q[i] = qi;
       part = pn * qi;
@@ -614,15 +632,26 @@ __global__ __launch_bounds__(kB) void k_outer_aq(SellView S, const double *__res
   if (outer_stopped(st)) return;
   Lane ln;
   const bool live = lane_slice<CWAVE>(S.offset, S.n_slices, S.geo, ln);
+  const RowOut ri = row_out(S.perm, S.perm_bytes, live ? ln.t : S.n, S.n, S.geo);
   double pq = 0.0, pr = 0.0;
   if (live) {
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
-    const double qi = sell_row<CWAVE>(S, ln, stride, [&](int32_t c) { return p[c]; });
+    double own = 0.0;  // p at the row's own index, from the gathers when possible
+    bool found = false;
+    const double qi = sell_row<CWAVE>(S, ln, stride, [&](int32_t c) {
+      const double g = p[c];
+      if ((uint32_t)c - ri.base == ri.p) {  // column c is the row's own index
+        own = g;
+        found = true;
+      }
+      return g;
+    });
     if (ln.t < S.n) {
-      const uint32_t i = out_row(S.perm, S.perm_bytes, ln.t, S.geo);
+      const uint32_t i = ri.row();
+      const double pi = found ? own : p[i];
       q[i] = qi;
-      pq = p[i] * qi;
-      pr = p[i] * r[i];
+      pq = pi * qi;
+      pr = pi * r[i];
     }
   }
   double v[2] = {pq, pr};
@@ -676,12 +705,13 @@ __global__ __launch_bounds__(kB) void k_residual(SellView S, const double *__res
                                                 double *__restrict__ r, Parts out) {
   Lane ln;
   const bool live = lane_slice<CWAVE>(S.offset, S.n_slices, S.geo, ln);
+  const RowOut dst = row_out(S.perm, S.perm_bytes, live ? ln.t : S.n, S.n, S.geo);
   double rr = 0.0, bb = 0.0;
   if (live) {
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
     const double ax = sell_row<CWAVE>(S, ln, stride, [&](int32_t c) { return x[c]; });
     if (ln.t < S.n) {
-      const uint32_t i = out_row(S.perm, S.perm_bytes, ln.t, S.geo);
+      const uint32_t i = dst.row();
       const double ri = b[i] - ax;
       r[i] = ri;
       rr = ri * ri;

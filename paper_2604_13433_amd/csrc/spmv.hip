@@ -39,6 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
   Lane ln;
   if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
   const uint32_t t = ln.t;
+  const RowOut ro = row_out<FMT>(a.perm, a.perm_bytes, a.row_exp, t, a.n, a.geo);
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, (uint32_t)a.m * (uint32_t)a.k * 4u);
   const uint32_t kx = (uint32_t)a.k * 4u, x0 = (uint32_t)a.r0 * 4u;
   const uint32_t oob = (uint32_t)a.m * kx;  // past the resource: returns 0, no request
@@ -72,11 +73,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
   }
   if (t >= a.n) return;
   if constexpr (FMT == PKSELL_FIX) {
-    const int sh = (int)a.row_exp[t] - (a.cd.D + 1);
 #pragma unroll
-    for (int r = 0; r < KB; ++r) acc[r] = ldexpf(acc[r], sh);
+    for (int r = 0; r < KB; ++r) acc[r] = ldexpf(acc[r], ro.shift(a.cd));
   }
-  const int64_t o = (int64_t)out_row(a.perm, a.perm_bytes, t, a.geo) * a.k + a.r0;
+  const int64_t o = (int64_t)ro.row() * a.k + a.r0;
   if constexpr (V4) {
     f32x4 *yo = reinterpret_cast<f32x4 *>(a.y + o);
 #pragma unroll
@@ -98,6 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_group(SpmvArgs a) {
   if (ks >= a.n_slices) return;
   const GroupLane g = group_lane<L>(h, threadIdx.x & (kWave - 1), (uint32_t)a.k >> 2);
   const uint32_t t = ks * kWave + g.l;
+  const RowOut ro = row_out<FMT>(a.perm, a.perm_bytes, a.row_exp, g.live ? t : a.n, a.n, a.geo);
   const int64_t s = a.offset[ks];
   const uint32_t w = (uint32_t)((a.offset[ks + 1] - s) >> 6);
   const uint32_t kx = (uint32_t)a.k * 4u, xq = 16u * g.q;
@@ -112,11 +113,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_group(SpmvArgs a) {
                                  acc);
   if (t >= a.n || !g.live) return;
   if constexpr (FMT == PKSELL_FIX) {
-    const int sh = (int)a.row_exp[t] - (a.cd.D + 1);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = ldexpf(acc[r], sh);
+    for (int r = 0; r < 4; ++r) acc[r] = ldexpf(acc[r], ro.shift(a.cd));
   }
-  const int64_t o = (int64_t)out_row(a.perm, a.perm_bytes, t, a.geo) * a.k + 4 * g.q;
+  const int64_t o = (int64_t)ro.row() * a.k + 4 * g.q;
   *reinterpret_cast<f32x4 *>(a.y + o) = f32x4{acc[0], acc[1], acc[2], acc[3]};
 }
 
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_group(SpmvArgs a) {
 // gives.  Same arithmetic, in the same word order per row, as k_spmv.
 constexpr int kPairBlock = 128;
 
-template <int FMT, bool BUF>
+template <int FMT, bool BUF, bool IMPL>
 __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
   constexpr int S = 2;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -136,6 +136,12 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
   const uint32_t k0 = wave * S;
   if (k0 >= a.n_slices) return;
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 4u);
+  RowOut ro[S];  // implicit order: destinations read up front
+  if constexpr (IMPL) {
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+      ro[i] = row_out<FMT>(a.perm, a.perm_bytes, a.row_exp, (k0 + i) * kWave + lane, a.n, a.geo);
+  }
   int64_t off[S + 1];
 #pragma unroll
   for (int i = 0; i <= S; ++i) off[i] = a.offset[min(k0 + i, a.n_slices)];
@@ -190,8 +196,9 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
     const uint32_t t = (k0 + i) * kWave + lane;
     if (k0 + i >= a.n_slices || t >= a.n) continue;
     float r = acc[i];
-    if constexpr (FMT == PKSELL_FIX) r = ldexpf(r, (int)a.row_exp[t] - (a.cd.D + 1));
-    a.y[out_row(a.perm, a.perm_bytes, t, a.geo)] = r;
+    if constexpr (FMT == PKSELL_FIX)
+      r = ldexpf(r, IMPL ? ro[i].shift(a.cd) : (int)a.row_exp[t] - (a.cd.D + 1));
+    a.y[IMPL ? ro[i].row() : t] = r;
   }
 }
 
@@ -223,6 +230,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_units(SpmvArgs a, UnitArgs u) {
   const uint32_t j0 = c * u.J;
   const uint32_t wl = chunks == 1 ? w : min(u.J, w - j0);
   const uint32_t t = k * kWave + lane;
+  const RowOut ro = row_out<FMT>(a.perm, a.perm_bytes, a.row_exp, chunks == 1 ? t : a.n, a.n,
+                                 a.geo);
   const uint32_t c0 = chunks == 1 ? left_offset32(t, a.geo) : u.ckpt[(base + c) * kWave + lane];
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 4u);
   float acc[1] = {0.0f};
@@ -241,8 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_units(SpmvArgs a, UnitArgs u) {
   }
   if (t >= a.n) return;
   float r = acc[0];
-  if constexpr (FMT == PKSELL_FIX) r = ldexpf(r, (int)a.row_exp[t] - (a.cd.D + 1));
-  a.y[out_row(a.perm, a.perm_bytes, t, a.geo)] = r;
+  if constexpr (FMT == PKSELL_FIX) r = ldexpf(r, ro.shift(a.cd));
+  a.y[ro.row()] = r;
 }
 
 template <int FMT>
@@ -253,6 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_combine_chunks(SpmvArgs a, UnitArgs 
   const uint32_t k = u.splits[4 * sp], base = u.splits[4 * sp + 1], chunks = u.splits[4 * sp + 2];
   const uint32_t t = k * kWave + lane;
   if (t >= a.n) return;
+  const RowOut ro = row_out<FMT>(a.perm, a.perm_bytes, a.row_exp, t, a.n, a.geo);
   // eight chunk sums in flight at a time, added in chunk order
   float r = 0.0f;
   for (uint32_t c0 = 0; c0 < chunks; c0 += 8) {
@@ -264,8 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_combine_chunks(SpmvArgs a, UnitArgs 
     for (int i = 0; i < 8; ++i)
       if (c0 + i < chunks) r += v[i];
   }
-  if constexpr (FMT == PKSELL_FIX) r = ldexpf(r, (int)a.row_exp[t] - (a.cd.D + 1));
-  a.y[out_row(a.perm, a.perm_bytes, t, a.geo)] = r;
+  if constexpr (FMT == PKSELL_FIX) r = ldexpf(r, ro.shift(a.cd));
+  a.y[ro.row()] = r;
 }
 
 // Word-by-word decode: the column reached at each word position and the
@@ -314,6 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
   Lane ln;
   if (!lane_slice<CWAVE>(offset, n_slices, g, ln)) return;
   const uint32_t t = ln.t, w = ln.w;
+  const RowOut dst = row_out(perm, perm_bytes, t, n, g);
   const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)C;
   T acc = 0;
   const int32_t *pc = scol + ln.s + ln.l;
@@ -341,12 +352,12 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
       if (j + q < w) acc += vv[q] * x[cc[q]];
   }
   if (t >= n) return;
-  y[out_row(perm, perm_bytes, t, g)] = acc;
+  y[dst.row()] = acc;
 }
 
 // SELL with C = 64 and streamed slots, two slices per wave in 128-thread
 // workgroups: the comparator gets the same structure as k_spmv_pair.
-template <typename T>
+template <typename T, bool IMPL>
 __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restrict__ offset,
                                                          const int32_t *__restrict__ scol,
                                                          const T *__restrict__ sval,
@@ -361,6 +372,11 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t k0 = wave * S;
   if (k0 >= n_slices) return;
+  RowOut dst[S];  // implicit order: destinations read up front
+  if constexpr (IMPL) {
+#pragma unroll
+    for (int i = 0; i < S; ++i) dst[i] = row_out(perm, perm_bytes, (k0 + i) * kWave + lane, n, g);
+  }
   int64_t off[S + 1];
 #pragma unroll
   for (int i = 0; i <= S; ++i) off[i] = offset[min(k0 + i, n_slices)];
@@ -401,7 +417,7 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
   for (int i = 0; i < S; ++i) {
     const uint32_t t = (k0 + i) * kWave + lane;
     if (k0 + i >= n_slices || t >= n) continue;
-    y[out_row(perm, perm_bytes, t, g)] = acc[i];
+    y[IMPL ? dst[i].row() : t] = acc[i];
   }
 }
 
@@ -430,6 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv64(Spmv64Args a) {
   Lane ln;
   if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
   const uint32_t t = ln.t, w = ln.w;
+  const RowOut dst = row_out(a.perm, a.perm_bytes, t, a.n, a.geo);
   const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)a.C;
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 8u);
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(BUF ? a.pack + ln.s : a.pack, BUF ? w * 512u : 0u);
@@ -468,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv64(Spmv64Args a) {
     for (int q = 0; q < kUnroll; ++q) acc = fma(val[q], xv[q], acc);
   }
   if (t >= a.n) return;
-  a.y[out_row(a.perm, a.perm_bytes, t, a.geo)] = acc;
+  a.y[dst.row()] = acc;
 }
 
 SpmvArgs make_args(const pksell_matrix *A, const float *x, float *y, int64_t k) {
@@ -528,11 +545,12 @@ int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, bool buf, bool 
         PKS_LAUNCHED();
         return PKSELL_OK;
       }
-      const int64_t waves = cdiv(base.n_slices, 2);
-      if (buf)
-        k_spmv_pair<FMT, true><<<cdiv(waves, kPairBlock / kWave), kPairBlock, 0, st>>>(base);
-      else
-        k_spmv_pair<FMT, false><<<cdiv(waves, kPairBlock / kWave), kPairBlock, 0, st>>>(base);
+      const int64_t pg = cdiv(cdiv(base.n_slices, 2), kPairBlock / kWave);
+      const bool impl = base.perm != nullptr;
+      if (buf && impl) k_spmv_pair<FMT, true, true><<<pg, kPairBlock, 0, st>>>(base);
+      else if (buf) k_spmv_pair<FMT, true, false><<<pg, kPairBlock, 0, st>>>(base);
+      else if (impl) k_spmv_pair<FMT, false, true><<<pg, kPairBlock, 0, st>>>(base);
+      else k_spmv_pair<FMT, false, false><<<pg, kPairBlock, 0, st>>>(base);
     } else {
       k_spmv<FMT, CW, 1, true><<<grid, kBlock, 0, st>>>(base);
     }
@@ -749,13 +767,13 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
   // two slices per wave for narrow float32 slices (float64 ran slower paired)
   if (buf && S->dtype == PKSELL_F32 && pair_slices(S->n_slots, S->n_slices)) {
     const int64_t pg = cdiv(cdiv(S->n_slices, 2), kPairBlock / kWave);
-#define PKS_SELL2(T)                                                                      \
-  k_sell_pair<T><<<pg, kPairBlock, 0, st>>>(S->offset, S->col, static_cast<const T *>(S->val), \
-                                            perm, S->perm_bytes, static_cast<const T *>(x),    \
-                                            static_cast<T *>(y), (uint32_t)S->n,               \
-                                            (uint32_t)S->n_slices, make_geo(S->sigma, 0, S->C))
-    if (S->dtype == PKSELL_F32) PKS_SELL2(float);
-    else PKS_SELL2(double);
+#define PKS_SELL2(T, IMPL)                                                                     \
+  k_sell_pair<T, IMPL><<<pg, kPairBlock, 0, st>>>(                                             \
+      S->offset, S->col, static_cast<const T *>(S->val), perm, S->perm_bytes,                  \
+      static_cast<const T *>(x), static_cast<T *>(y), (uint32_t)S->n, (uint32_t)S->n_slices,   \
+      make_geo(S->sigma, 0, S->C))
+    if (perm) PKS_SELL2(float, true);
+    else PKS_SELL2(float, false);
 #undef PKS_SELL2
   } else if (S->dtype == PKSELL_F32) {
     if (buf) PKS_SELL(float, true, true);
