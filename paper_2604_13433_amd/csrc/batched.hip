@@ -55,8 +55,9 @@ __device__ inline void do_unit(const Item &it, uint32_t k_slice, uint32_t lane, 
   const uint32_t w = (uint32_t)((it.offset[k_slice + 1] - s) >> 6);
   const uint32_t *P = it.pack + s + lane;
   uint32_t c = left_offset32(t, it.geo);
-  // destination row and FIX scale exponent (2^(e - D - 1), applied with ldexp)
-  const RowOut ro = row_out<FMT>(it.perm, it.perm_bytes, it.row_exp, t, it.n, it.geo);
+  int sh = 0;  // FIX: the row scale 2^(e - D - 1), applied with ldexp
+  if constexpr (FMT == PKSELL_FIX)
+    if (t < it.n) sh = (int)it.row_exp[t] - (it.cd.D + 1);
   if constexpr (!TRANS) {
     const __amdgpu_buffer_rsrc_t rx = make_rsrc(it.in, it.m * (uint32_t)k * 4u);
     const uint32_t kx = (uint32_t)k * 4u, x0 = (uint32_t)r0 * 4u;
@@ -78,10 +79,10 @@ __device__ inline void do_unit(const Item &it, uint32_t k_slice, uint32_t lane, 
                             acc);
     }
     if (t < it.n) {
-      const int64_t o = (int64_t)ro.row() * k + r0;
+      const int64_t o = (int64_t)out_row(it.perm, it.perm_bytes, t, it.geo) * k + r0;
 #pragma unroll
       for (int r = 0; r < KB; ++r)
-        if constexpr (FMT == PKSELL_FIX) acc[r] = ldexpf(acc[r], ro.shift(it.cd));
+        if constexpr (FMT == PKSELL_FIX) acc[r] = ldexpf(acc[r], sh);
       if constexpr (V4) {
         f32x4 *yo = reinterpret_cast<f32x4 *>(it.out + o);
 #pragma unroll
@@ -94,10 +95,10 @@ __device__ inline void do_unit(const Item &it, uint32_t k_slice, uint32_t lane, 
     }
   } else {
     if (t >= it.n) return;
-    const float *g = it.in + (int64_t)ro.row() * k + r0;
+    const float *g = it.in + (int64_t)out_row(it.perm, it.perm_bytes, t, it.geo) * k + r0;
     float gr[KB];
 #pragma unroll
-    for (int r = 0; r < KB; ++r) gr[r] = FMT == PKSELL_FIX ? ldexpf(g[r], ro.shift(it.cd)) : g[r];
+    for (int r = 0; r < KB; ++r) gr[r] = FMT == PKSELL_FIX ? ldexpf(g[r], sh) : g[r];
     for (uint32_t j = 0; j < w; ++j) {
       const uint32_t p = __builtin_nontemporal_load(P + j * kWave);
       const Unpacked u = unpack(p, it.cd);
@@ -232,27 +233,17 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
   const uint32_t k4 = (uint32_t)k >> 2, kx = (uint32_t)k * 4u;
   Unit cur = unit_at<L>(items, unit_start, find_item(unit_start, count, u), u, lane, k4);
   constexpr bool NT = L == 1;
-  // a unit's destination row (and FIX exponent), read right after its first
-  // words
-  auto dest = [&](const Unit &x) {
-    const Item &I = items[x.item];
-    return row_out<FMT>(I.perm, I.perm_bytes, I.row_exp, x.live ? x.ks * kWave + x.l : I.n, I.n,
-                        I.geo);
-  };
   uint32_t p[kUnroll];
   load_words<NT>(items[cur.item], cur.s, cur.l, cur.w, 0, p);
-  RowOut ro = dest(cur);  // after the words: a wait for the offsets must not cover it
   for (;;) {
     const bool more = u + stride < total;
     Unit nx;
-    RowOut ron;
     uint32_t pn[kUnroll];
     if (more) {  // the next unit's bounds and first words, before this unit's gathers
       uint32_t itn = cur.item;
       while (u + stride >= unit_start[itn + 1]) ++itn;
       nx = unit_at<L>(items, unit_start, itn, u + stride, lane, k4);
       load_words<NT>(items[itn], nx.s, nx.l, nx.w, 0, pn);
-      ron = dest(nx);
     }
     const Item &I = items[cur.item];
     const uint32_t t = cur.ks * kWave + cur.l;
@@ -271,10 +262,11 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
     }
     if (t < I.n && cur.live) {
       if constexpr (FMT == PKSELL_FIX) {
+        const int sh = (int)I.row_exp[t] - (I.cd.D + 1);
 #pragma unroll
-        for (int r = 0; r < NA; ++r) acc[r] = ldexpf(acc[r], ro.shift(I.cd));
+        for (int r = 0; r < NA; ++r) acc[r] = ldexpf(acc[r], sh);
       }
-      const uint32_t row = ro.row();
+      const uint32_t row = out_row(I.perm, I.perm_bytes, t, I.geo);
       if constexpr (L == 1) {
         I.out[row] = acc[0];
       } else {
@@ -284,7 +276,6 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
     }
     if (!more) break;
     cur = nx;
-    ro = ron;
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) p[q] = pn[q];
     u += stride;
