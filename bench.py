@@ -182,7 +182,8 @@ def main():
             continue
         built.append(add_packsell(name, fmt, D, mode))
     sells = []
-    for name, dt in [("sell_fp32", torch.float32), ("sell_fp64", torch.float64)]:
+    for name, dt in [("sell_fp32", torch.float32), ("sell_fp16", torch.float16),
+                     ("sell_fp64", torch.float64)]:
         if only and name not in only:
             continue
         S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, dt, 64, 256, B.EXPLICIT, dev)
@@ -215,7 +216,7 @@ def main():
         ms = Timed(torch, lambda i: B.sell_spmv(reps[i], xs[i], ys[i]), R, args.steps,
                    args.warmup).run()
         gbs = per / (ms * 1e-3) / 1e9
-        vb = 8 if S.dtype == torch.float64 else 4
+        vb = S.value_dtype.itemsize
         results[name] = dict(ms=ms, gbs=gbs, bytes=per, replicas=R, slots=S.n_slots,
                              gflops=2 * a.nnz / (ms * 1e-3) / 1e9, y=ys[0], S=S,
                              useful=per - (4 + vb) * (S.n_slots - a.nnz))
@@ -252,6 +253,7 @@ def main():
         "variants": {},
     }
     base32 = results.get("sell_fp32")
+    base16 = results.get("sell_fp16")
     for name, r in results.items():
         v = {"us": round(r["ms"] * 1e3, 2), "GB/s": round(r["gbs"], 1),
              "GFLOP/s": round(r["gflops"], 1), "hbm_frac": round(r["gbs"] / PEAK_HBM_GBS, 4),
@@ -259,6 +261,9 @@ def main():
              "useful_GB/s": round(r["useful"] / (r["ms"] * 1e-3) / 1e9, 1)}
         if base32 is not None:
             v["speedup_vs_sell_fp32"] = round(base32["ms"] / r["ms"], 3)
+        if base16 is not None and name.startswith("packsell_fp16"):
+            # same values (binary16), 4 B per word against 6 B per SELL slot
+            v["speedup_vs_sell_fp16"] = round(base16["ms"] / r["ms"], 3)
         out["variants"][name] = v
 
     if not args.no_adjoint and "packsell_fp16" in results:
@@ -645,7 +650,10 @@ def cpu_leg(args, a, x_np, results, H, torch):
                             "backward_error_eq5": float(np.abs(y - full).max() / den_a)}
         else:
             E = P.encode(a.rowptr, a.col, a.val, a.n, a.m, F.FMT_E8MY, 22, 64, 256, 0)
-            vals = a.val if r["S"].dtype == torch.float64 else a.val.astype(np.float32).astype(np.float64)
+            vdt = r["S"].value_dtype
+            v32 = a.val.astype(np.float32)
+            vals = (a.val if vdt == torch.float64 else
+                    (v32.astype(np.float16) if vdt == torch.float16 else v32).astype(np.float64))
             ref = L.spmv(a.rowptr, a.col, vals, x_np)[E.stored_rows]
             full = L.spmv(a.rowptr, a.col, a.val, x_np)[E.stored_rows]
             den = L.inf_norm(a.rowptr, vals) * np.abs(x_np).max()

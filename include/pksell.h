@@ -61,6 +61,11 @@ extern "C" {
 /* ---- value input types ------------------------------------------------- */
 #define PKSELL_F32 4
 #define PKSELL_F64 8
+/* SELL values only: IEEE binary16 values (rounded from float32 with ties to
+ * even, float64 input rounded to float32 first, as for PackSELL FP16 words),
+ * float32 x and y, float32 accumulation: the plain-SELL counterpart of the
+ * FP16 PackSELL words (int32 column + 2-byte value per slot). */
+#define PKSELL_F16 2
 
 /* A PackSELL matrix.  pksell_encode_query() fills the shape and parameter
  * fields; the analyse phase of pksell_encode() fills n_words, n_dummies and
@@ -116,7 +121,7 @@ typedef struct pksell_matrix {
  */
 typedef struct pksell_sell {
   int64_t n, m, nnz;
-  int32_t C, sigma, perm_mode, perm_bytes, dtype; /* dtype PKSELL_F32/PKSELL_F64 */
+  int32_t C, sigma, perm_mode, perm_bytes, dtype; /* PKSELL_F32/F64/F16 */
   int32_t reserved;
   int64_t n_slices, n_slots;
   int64_t *offset;
@@ -258,7 +263,8 @@ int pksell_decode(const pksell_matrix *A, int32_t *cols, float *vals,
  * Plain SELL-C-sigma (sec. 3), the comparator and the float64 operator.
  * ---------------------------------------------------------------------- */
 
-/* As pksell_encode_query for SELL; dtype is PKSELL_F32 or PKSELL_F64. */
+/* As pksell_encode_query for SELL; dtype is PKSELL_F32, PKSELL_F64 or
+ * PKSELL_F16 (the value type; vectors are float32 for F16). */
 int pksell_sell_query(int64_t n, int64_t m, int64_t nnz, int32_t C,
                       int32_t sigma, int32_t dtype, int32_t perm_mode,
                       pksell_sell *S, size_t *ws_bytes);
@@ -269,7 +275,8 @@ int pksell_sell_encode(const int64_t *rowptr, const int32_t *col,
                        const void *val, int32_t val_dtype, pksell_sell *S,
                        void *ws, size_t ws_bytes, void *stream);
 
-/* y = S x in S->dtype (x: m, y: n, of S->dtype), accumulated in S->dtype. */
+/* y = S x in S->dtype (x: m, y: n, of S->dtype), accumulated in S->dtype;
+ * for PKSELL_F16, x and y are float32 and the sums float32. */
 int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y,
                      void *stream);
 

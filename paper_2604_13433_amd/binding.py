@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpksell.so")
 OK, EINVAL, ERANGE, EWORKSPACE, EHIP, ENOTCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
 FP16, E8MY, FIX, E11MY = 0, 1, 2, 3
 EXPLICIT, IMPLICIT = 0, 1
-F32, F64 = 4, 8
+F32, F64, F16 = 4, 8, 2  # F16: SELL half values (float32 vectors)
 FMT_BY_NAME = {"fp16": FP16, "e8my": E8MY, "fix": FIX, "e11my": E11MY}
 
 i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
@@ -431,7 +431,8 @@ def decode(A: PackSELLMatrix):
 
 
 class SellMatrix:
-    """Plain SELL-C-sigma with float32 or float64 values (the comparator)."""
+    """Plain SELL-C-sigma with float32, float64 or half values (the
+    comparator); half-value matrices take float32 vectors."""
 
     def __init__(self, desc: CSell, tensors: dict, device):
         self.desc = desc
@@ -444,12 +445,18 @@ class SellMatrix:
 
     @property
     def dtype(self):
+        """The vector (x, y) dtype."""
         return torch.float64 if self.desc.dtype == F64 else torch.float32
+
+    @property
+    def value_dtype(self):
+        return {F64: torch.float64, F16: torch.float16}.get(self.desc.dtype, torch.float32)
 
     def bytes_per_spmv(self) -> int:
         d = self.desc
-        vb = 8 if d.dtype == F64 else 4
-        b = (vb + 4) * d.n_slots + 8 * (d.n_slices + 1) + vb * (d.m + d.n)
+        vb = {F64: 8, F16: 2}.get(d.dtype, 4)  # value bytes per slot
+        xb = 8 if d.dtype == F64 else 4        # vector element bytes
+        b = (vb + 4) * d.n_slots + 8 * (d.n_slices + 1) + xb * (d.m + d.n)
         if d.perm_mode == IMPLICIT:
             b += d.perm_bytes * d.n
         return int(b)
@@ -477,7 +484,7 @@ def sell_encode(rowptr, col, val, n: int, m: int, dtype=torch.float32, C: int = 
     vdt = torch.float64 if (isinstance(val, np.ndarray) and val.dtype == np.float64) or \
         (isinstance(val, torch.Tensor) and val.dtype == torch.float64) else torch.float32
     vl = _dev(val, vdt, device)
-    code = F64 if dtype == torch.float64 else F32
+    code = {torch.float64: F64, torch.float16: F16}.get(dtype, F32)
     desc = CSell()
     ws_bytes = ctypes.c_size_t()
     L = lib()

@@ -382,6 +382,15 @@ __global__ void k_fill_packsell64(const int64_t *__restrict__ rowptr, const int3
   for (; j < w; ++j) out[j * C] = 0ull;
 }
 
+// A SELL slot value: half values are rounded from float32 (float64 input
+// first rounded to float32, the intermediate pinned by load_value), as the
+// FP16 PackSELL words are.
+template <typename OT, typename VT>
+__device__ inline OT sell_value(const VT *v, int64_t e) {
+  if constexpr (sizeof(OT) == 2) return (OT)load_value(v, e);
+  else return (OT)v[e];
+}
+
 template <typename VT, typename OT>
 __global__ void k_fill_sell(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                             const VT *__restrict__ val, int64_t n, int32_t C, int64_t n_slices,
@@ -401,7 +410,7 @@ __global__ void k_fill_sell(const int64_t *__restrict__ rowptr, const int32_t *_
     for (int64_t e = rb; e < re; ++e, ++j) {
       last = col[e];
       scol[s + j * C + l] = last;
-      sval[s + j * C + l] = (OT)val[e];
+      sval[s + j * C + l] = sell_value<OT>(val, e);
     }
   }
   for (; j < w; ++j) {
@@ -658,7 +667,8 @@ int pksell_sell_query(int64_t n, int64_t m, int64_t nnz, int32_t C, int32_t sigm
   PKS_CHECK(S && ws_bytes, PKSELL_EINVAL, "null argument");
   int rc = check_common(n, m, nnz, C, sigma, perm_mode);
   if (rc) return rc;
-  PKS_CHECK(dtype == PKSELL_F32 || dtype == PKSELL_F64, PKSELL_EINVAL, "bad dtype");
+  PKS_CHECK(dtype == PKSELL_F32 || dtype == PKSELL_F64 || dtype == PKSELL_F16, PKSELL_EINVAL,
+            "bad dtype");
   std::memset(S, 0, sizeof(*S));
   S->n = n;
   S->m = m;
@@ -702,9 +712,11 @@ int pksell_sell_encode(const int64_t *rowptr, const int32_t *col, const void *va
                                             S->col, static_cast<OT *>(S->val))
   if (val_dtype == PKSELL_F32) {
     if (S->dtype == PKSELL_F32) PKS_SFILL(float, float);
+    else if (S->dtype == PKSELL_F16) PKS_SFILL(float, _Float16);
     else PKS_SFILL(float, double);
   } else {
     if (S->dtype == PKSELL_F32) PKS_SFILL(double, float);
+    else if (S->dtype == PKSELL_F16) PKS_SFILL(double, _Float16);
     else PKS_SFILL(double, double);
   }
 #undef PKS_SFILL

@@ -118,7 +118,9 @@ __device__ inline uint32_t stream_word(__amdgpu_buffer_rsrc_t rs, uint32_t lane,
 template <typename T>
 __device__ inline T stream_elem(__amdgpu_buffer_rsrc_t rs, uint32_t lane, uint32_t j) {
   const uint32_t off = (lane + j * kWave) * (uint32_t)sizeof(T);
-  if constexpr (sizeof(T) == 4)
+  if constexpr (sizeof(T) == 2)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, kStreamPolicy));
+  else if constexpr (sizeof(T) == 4)
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, kStreamPolicy));
   else
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kStreamPolicy));

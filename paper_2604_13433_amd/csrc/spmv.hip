@@ -310,14 +310,15 @@ __global__ void k_fill_zero(T *p, int64_t len) {
   if (i < len) p[i] = T(0);
 }
 
-// Plain SELL-C-sigma SpMV (sec. 3): the float32 / float64 comparator, with
-// the same lane mapping and batched loads as the PackSELL kernel.
+// Plain SELL-C-sigma SpMV (sec. 3): the float32 / float64 / half-value
+// comparator, with the same lane mapping and batched loads as the PackSELL
+// kernel.  Values are VT (T, or half with T = float), vectors and sums T.
 // BUF (C = 64 and arrays below 4 GiB): columns and values are streamed
 // through per-slice buffer resources, as the PackSELL words are.
-template <typename T, bool CWAVE, bool BUF = false>
+template <typename T, bool CWAVE, bool BUF = false, typename VT = T>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict__ offset,
                                                       const int32_t *__restrict__ scol,
-                                                      const T *__restrict__ sval, const void *perm,
+                                                      const VT *__restrict__ sval, const void *perm,
                                                       int32_t perm_bytes, const T *__restrict__ x,
                                                       T *__restrict__ y, uint32_t n,
                                                       uint32_t n_slices, int32_t C, RowGeo g) {
@@ -328,11 +329,11 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
   const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)C;
   T acc = 0;
   const int32_t *pc = scol + ln.s + ln.l;
-  const T *pv = sval + ln.s + ln.l;
+  const VT *pv = sval + ln.s + ln.l;
   // (BUF implies C = 64, where ln.s is wave-uniform)
   const __amdgpu_buffer_rsrc_t rc = BUF ? make_rsrc(scol + ln.s, w * 256u) : make_rsrc(scol, 0u);
   const __amdgpu_buffer_rsrc_t rv =
-      BUF ? make_rsrc(sval + ln.s, w * kWave * (uint32_t)sizeof(T)) : make_rsrc(sval, 0u);
+      BUF ? make_rsrc(sval + ln.s, w * kWave * (uint32_t)sizeof(VT)) : make_rsrc(sval, 0u);
   for (uint32_t j = 0; j < w; j += kUnroll) {
     int32_t cc[kUnroll];
     T vv[kUnroll];
@@ -341,10 +342,10 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
       const bool in = j + q < w;
       if constexpr (BUF) {
         cc[q] = in ? stream_elem<int32_t>(rc, ln.l, j + q) : 0;
-        vv[q] = in ? stream_elem<T>(rv, ln.l, j + q) : T(0);
+        vv[q] = in ? (T)stream_elem<VT>(rv, ln.l, j + q) : T(0);
       } else {
         cc[q] = in ? __builtin_nontemporal_load(pc + (j + q) * stride) : 0;
-        vv[q] = in ? __builtin_nontemporal_load(pv + (j + q) * stride) : T(0);
+        vv[q] = in ? (T)__builtin_nontemporal_load(pv + (j + q) * stride) : T(0);
       }
     }
 #pragma unroll
@@ -357,10 +358,10 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
 
 // SELL with C = 64 and streamed slots, two slices per wave in 128-thread
 // workgroups: the comparator gets the same structure as k_spmv_pair.
-template <typename T, bool IMPL>
+template <typename T, bool IMPL, typename VT = T>
 __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restrict__ offset,
                                                          const int32_t *__restrict__ scol,
-                                                         const T *__restrict__ sval,
+                                                         const VT *__restrict__ sval,
                                                          const void *perm, int32_t perm_bytes,
                                                          const T *__restrict__ x,
                                                          T *__restrict__ y, uint32_t n,
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
     w[i] = (uint32_t)((off[i + 1] - off[i]) >> 6);
     wm = max(wm, w[i]);
     rc[i] = make_rsrc(scol + off[i], w[i] * 256u);
-    rv[i] = make_rsrc(sval + off[i], w[i] * kWave * (uint32_t)sizeof(T));
+    rv[i] = make_rsrc(sval + off[i], w[i] * kWave * (uint32_t)sizeof(VT));
     acc[i] = T(0);
   }
   for (uint32_t j = 0; j < wm; j += kUnroll) {
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
       for (int q = 0; q < kUnroll; ++q) {
         const bool in = j + q < w[i];
         cc[i][q] = in ? stream_elem<int32_t>(rc[i], lane, j + q) : 0;
-        vv[i][q] = in ? stream_elem<T>(rv[i], lane, j + q) : T(0);
+        vv[i][q] = in ? (T)stream_elem<VT>(rv[i], lane, j + q) : T(0);
       }
     T xv[S][kUnroll];
 #pragma unroll
@@ -750,39 +751,48 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
   if (S->n == 0) return PKSELL_OK;
   const void *perm = S->perm_mode == PKSELL_IMPLICIT ? S->perm : nullptr;
   if (S->m == 0) {
-    if (S->dtype == PKSELL_F32) return zero_f32(static_cast<float *>(y), S->n, st);
+    if (S->dtype != PKSELL_F64) return zero_f32(static_cast<float *>(y), S->n, st);
     k_fill_zero<double><<<cdiv(S->n, kBlock), kBlock, 0, st>>>(static_cast<double *>(y), S->n);
     PKS_LAUNCHED();
     return PKSELL_OK;
   }
   PKS_CHECK(x, PKSELL_EINVAL, "null x");
   const int64_t grid = cdiv(S->n_slices * S->C, kBlock);
-#define PKS_SELL(T, CW, BF)                                                                   \
-  k_sell_spmv<T, CW, BF><<<grid, kBlock, 0, st>>>(S->offset, S->col, static_cast<const T *>(S->val), \
-                                             perm, S->perm_bytes, static_cast<const T *>(x),     \
-                                             static_cast<T *>(y), (uint32_t)S->n,                \
-                                             (uint32_t)S->n_slices, S->C,                        \
-                                             make_geo(S->sigma, 0, S->C))
+#define PKS_SELL(T, CW, BF, VT)                                                             \
+  k_sell_spmv<T, CW, BF, VT><<<grid, kBlock, 0, st>>>(                                       \
+      S->offset, S->col, static_cast<const VT *>(S->val), perm, S->perm_bytes,               \
+      static_cast<const T *>(x), static_cast<T *>(y), (uint32_t)S->n, (uint32_t)S->n_slices, \
+      S->C, make_geo(S->sigma, 0, S->C))
   const bool buf = S->C == kWave && S->n_slots < (int64_t(1) << 29);
-  // two slices per wave for narrow float32 slices (float64 ran slower paired)
-  if (buf && S->dtype == PKSELL_F32 && pair_slices(S->n_slots, S->n_slices)) {
+  // two slices per wave for narrow float32-vector slices (float64 ran
+  // slower paired)
+  if (buf && S->dtype != PKSELL_F64 && pair_slices(S->n_slots, S->n_slices)) {
     const int64_t pg = cdiv(cdiv(S->n_slices, 2), kPairBlock / kWave);
-#define PKS_SELL2(T, IMPL)                                                                     \
-  k_sell_pair<T, IMPL><<<pg, kPairBlock, 0, st>>>(                                             \
-      S->offset, S->col, static_cast<const T *>(S->val), perm, S->perm_bytes,                  \
-      static_cast<const T *>(x), static_cast<T *>(y), (uint32_t)S->n, (uint32_t)S->n_slices,   \
-      make_geo(S->sigma, 0, S->C))
-    if (perm) PKS_SELL2(float, true);
-    else PKS_SELL2(float, false);
+#define PKS_SELL2(IMPL, VT)                                                                    \
+  k_sell_pair<float, IMPL, VT><<<pg, kPairBlock, 0, st>>>(                                     \
+      S->offset, S->col, static_cast<const VT *>(S->val), perm, S->perm_bytes,                 \
+      static_cast<const float *>(x), static_cast<float *>(y), (uint32_t)S->n,                  \
+      (uint32_t)S->n_slices, make_geo(S->sigma, 0, S->C))
+    if (S->dtype == PKSELL_F16) {
+      if (perm) PKS_SELL2(true, _Float16);
+      else PKS_SELL2(false, _Float16);
+    } else {
+      if (perm) PKS_SELL2(true, float);
+      else PKS_SELL2(false, float);
+    }
 #undef PKS_SELL2
+  } else if (S->dtype == PKSELL_F16) {
+    if (buf) PKS_SELL(float, true, true, _Float16);
+    else if (S->C == kWave) PKS_SELL(float, true, false, _Float16);
+    else PKS_SELL(float, false, false, _Float16);
   } else if (S->dtype == PKSELL_F32) {
-    if (buf) PKS_SELL(float, true, true);
-    else if (S->C == kWave) PKS_SELL(float, true, false);
-    else PKS_SELL(float, false, false);
+    if (buf) PKS_SELL(float, true, true, float);
+    else if (S->C == kWave) PKS_SELL(float, true, false, float);
+    else PKS_SELL(float, false, false, float);
   } else {
-    if (buf) PKS_SELL(double, true, true);
-    else if (S->C == kWave) PKS_SELL(double, true, false);
-    else PKS_SELL(double, false, false);
+    if (buf) PKS_SELL(double, true, true, double);
+    else if (S->C == kWave) PKS_SELL(double, true, false, double);
+    else PKS_SELL(double, false, false, double);
   }
 #undef PKS_SELL
   PKS_LAUNCHED();

@@ -75,12 +75,18 @@ def test_encode_query_rejects(kw, code):
     assert B.lib().pksell_last_error()
 
 
-def test_sell_query_rejects_bad_dtype():
+def test_sell_query_dtypes():
+    """float32, float64 and half values are accepted; anything else is not."""
     desc = B.CSell()
     ws = ctypes.c_size_t()
-    rc = B.lib().pksell_sell_query(10, 10, 10, 64, 256, 2, B.IMPLICIT, ctypes.byref(desc),
-                                   ctypes.byref(ws))
-    assert rc == B.EINVAL
+    for dt in (B.F32, B.F64, B.F16):
+        rc = B.lib().pksell_sell_query(10, 10, 10, 64, 256, dt, B.IMPLICIT, ctypes.byref(desc),
+                                       ctypes.byref(ws))
+        assert rc == B.OK and desc.dtype == dt
+    for dt in (0, 1, 3, 16):
+        rc = B.lib().pksell_sell_query(10, 10, 10, 64, 256, dt, B.IMPLICIT, ctypes.byref(desc),
+                                       ctypes.byref(ws))
+        assert rc == B.EINVAL
 
 
 @pytest.mark.parametrize("C,J", [(64, 12), (64, 4), (64, 1 << 25), (32, 64), (64, -8)])

@@ -156,23 +156,60 @@ def test_m2_laplace3d_full_size(fmt, D):
     check_spmv(A, a, fmt, D, x, B.IMPLICIT, E)
 
 
-def test_sell_fp32_fp64():
+def sell_values(val, dt):
+    """The values a SELL matrix of value type dt holds, in float64: float32
+    and half values are rounded from float32 (float64 input rounded to
+    float32 first), ties to even."""
+    if dt == torch.float64:
+        return np.asarray(val, np.float64)
+    v32 = np.asarray(val).astype(np.float32)
+    return (v32.astype(np.float16) if dt == torch.float16 else v32).astype(np.float64)
+
+
+@pytest.mark.parametrize("C", [64, 32])
+def test_sell_fp32_fp64_fp16(C):
     a = random_csr(3, 3000, 2500, per_row=12)
     x = W.uniform_vector(a.m, 4)
-    for dt in (torch.float32, torch.float64):
+    for dt in (torch.float32, torch.float64, torch.float16):
+        vdt = torch.float64 if dt == torch.float64 else torch.float32  # vector dtype
         for mode in (B.IMPLICIT, B.EXPLICIT):
-            S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, dt, 64, 256, mode, DEV)
-            y = B.sell_spmv(S, torch.from_numpy(x.astype(np.float64)).to(DEV, dt)).cpu().numpy()
-            vals = a.val.astype(np.float32).astype(np.float64) if dt == torch.float32 else a.val
+            S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, dt, C, 256, mode, DEV)
+            assert S.value_dtype == dt and S.dtype == vdt
+            y = B.sell_spmv(S, torch.from_numpy(x.astype(np.float64)).to(DEV, vdt)).cpu().numpy()
+            vals = sell_values(a.val, dt)
             ref = L.spmv(a.rowptr, a.col, vals, x)
             if mode == B.EXPLICIT:
                 # SELL sorts rows by nonzero count; PackSELL with deltas that
                 # never overflow (D = 22 > log2 m) has the same counts
-                E = P.encode(a.rowptr, a.col, a.val, a.n, a.m, F.FMT_E8MY, 22, 64, 256, mode)
+                E = P.encode(a.rowptr, a.col, a.val, a.n, a.m, F.FMT_E8MY, 22, C, 256, mode)
                 assert E.n_dummies == 0
                 ref = ref[E.stored_rows]
-            tol = SPMV_TOL if dt == torch.float32 else 1e-14
+            tol = 1e-14 if dt == torch.float64 else SPMV_TOL
             assert normalised_error(y, ref, a, vals, x) <= tol
+
+
+def test_sell_fp16_matches_packsell_fp16_laplace3d_128():
+    """SELL with half values holds the same values as the FP16 PackSELL
+    words (both round float32 to binary16, ties to even) and sums them in
+    the same order, so on the 128^3 Laplacian at the benchmark's launch
+    configuration (C = 64, sigma = 256, explicit order) the two products
+    agree to float32 rounding; both are checked against the oracle."""
+    a = W.m2_laplace3d()
+    x = W.uniform_vector(a.m, 3)
+    xd = torch.from_numpy(x).to(DEV)
+    S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float16, 64, 256, B.EXPLICIT, DEV)
+    A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 64, 256, B.EXPLICIT, DEV)
+    ys = B.sell_spmv(S, xd).cpu().numpy().astype(np.float64)
+    yp = B.spmv(A, xd).cpu().numpy().astype(np.float64)
+    vals = sell_values(a.val, torch.float16)
+    E = P.encode(a.rowptr, a.col, a.val, a.n, a.m, F.FMT_FP16, 15, 64, 256, P.PERM_EXPLICIT)
+    ref = L.spmv(a.rowptr, a.col, vals, x)[E.stored_rows]
+    assert normalised_error(ys, ref, a, vals, x) <= SPMV_TOL
+    assert normalised_error(yp, ref, a, vals, x) <= SPMV_TOL
+    den = L.inf_norm(a.rowptr, vals) * float(np.abs(x).max())
+    assert float(np.max(np.abs(ys - yp))) / den <= 2 * SPMV_TOL
+    # bytes: 6 per SELL slot (int32 column + half) against 4 per word
+    assert S.n_slots == A.n_words
 
 
 def test_spmv_t_and_grad_values():
