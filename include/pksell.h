@@ -53,6 +53,16 @@ extern "C" {
                           FP64-compatible float with Y = 51 - D mantissa bits,
                           the E8MY construction applied to FP64; 1 <= D <= 51.
                           Products in float64 through pksell_spmv_f64 only. */
+/* 16-bit words (sec. 4.2.1 with W = 16): a value word has its delta in bits
+ * 1..D and 15 - D value bits; a dummy carries at most 2^15 - 1, so a larger
+ * delta takes a chain of dummies (all but the last carrying 2^15 - 1)
+ * before its value word.  C must be 64.  Products through pksell_spmv with
+ * k = 1 only; every other entry point rejects these formats. */
+#define PKSELL_E5MY 4  /* binary16-compatible float, Y = 9 - D mantissa bits
+                          (the E8MY construction applied to binary16; D = 7 is
+                          8-bit E5M2); 1 <= D <= 8 */
+#define PKSELL_FIX16 5 /* (15-D)-bit two's-complement integer times a per-row
+                          power of two (D = 7: int8); 1 <= D <= 13 */
 
 /* ---- row permutation modes (sec. 3) ------------------------------------ */
 #define PKSELL_EXPLICIT 0 /* results are produced in stored (sorted) row order */
@@ -74,12 +84,17 @@ extern "C" {
  *   pack     uint32[n_words]     slice k occupies [offset[k], offset[k+1]),
  *                                word j of lane l at offset[k] + j*C + l
  *                                (E11MY: uint64[n_words], 64-bit words, the
- *                                same layout; the pointer is cast)
+ *                                same layout; the pointer is cast.  E5MY and
+ *                                FIX16: uint32[n_words / 2], 16-bit words two
+ *                                per slot -- words 2i (low half) and 2i + 1
+ *                                (high half) of lane l in slot offset[k]/2 +
+ *                                i*C + l; every lane's word count is rounded
+ *                                up to even with a zero padding word)
  *   offset   int64[n_slices + 1] slice starts in words (sec. 3)
  *   perm     uint8 (sigma <= 256) or uint16 [n]  original row minus its
  *                                window start, per stored row (implicit mode
  *                                only; may be NULL in explicit mode)
- *   row_exp  int16[n]            FIX only: row scale exponent e, stored order
+ *   row_exp  int16[n]            FIX and FIX16: row scale exponent e, stored order
  *                                (decoded value = q * 2^e)
  *
  * Wide-slice splitting (C = 64 only; optional).  Set split_words = J (a
@@ -192,7 +207,8 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val,
 /* y = A_q x with float32 accumulation; y is overwritten (no beta term).  In
  * implicit mode y is in the original row order, in explicit mode in stored
  * order.  1 <= k <= 64.  With k a multiple of 4 and x, y 16-byte aligned, x
- * is gathered and y stored four columns at a time. */
+ * is gathered and y stored four columns at a time.  16-bit words (E5MY,
+ * FIX16): k = 1 only. */
 int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k,
                 void *stream);
 

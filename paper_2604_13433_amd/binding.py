@@ -17,10 +17,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpksell.so")
 
 OK, EINVAL, ERANGE, EWORKSPACE, EHIP, ENOTCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
-FP16, E8MY, FIX, E11MY = 0, 1, 2, 3
+FP16, E8MY, FIX, E11MY, E5MY, FIX16 = 0, 1, 2, 3, 4, 5  # E5MY, FIX16: 16-bit words
 EXPLICIT, IMPLICIT = 0, 1
 F32, F64, F16 = 4, 8, 2  # F16: SELL half values (float32 vectors)
-FMT_BY_NAME = {"fp16": FP16, "e8my": E8MY, "fix": FIX, "e11my": E11MY}
+FMT_BY_NAME = {"fp16": FP16, "e8my": E8MY, "fix": FIX, "e11my": E11MY, "e5my": E5MY,
+               "fix16": FIX16}
+W16 = (E5MY, FIX16)
 
 i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
 
@@ -205,10 +207,11 @@ class PackSELLMatrix:
             if d.perm_mode == IMPLICIT:
                 b += d.perm_bytes * d.n
             return int(b)
-        b = 4 * d.n_words + 8 * (d.n_slices + 1) + 4 * d.m * k + 4 * d.n * k
+        wb = 2 if d.fmt in W16 else 4  # bytes per word
+        b = wb * d.n_words + 8 * (d.n_slices + 1) + 4 * d.m * k + 4 * d.n * k
         if d.perm_mode == IMPLICIT:
             b += d.perm_bytes * d.n
-        if d.fmt == FIX:
+        if d.fmt in (FIX, FIX16):
             b += 2 * d.n
         return int(b)
 
@@ -308,9 +311,13 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
                            _ptr(ws), ws_bytes.value, st))
     if analyse_only:
         return A
-    wdt = torch.int64 if fmt == E11MY else torch.int32  # 64-bit words for E11MY
-    t["pack"] = torch.empty(max(1, desc.n_words), dtype=wdt, device=device)
-    if fmt == FIX:
+    if fmt == E11MY:  # 64-bit words
+        t["pack"] = torch.empty(max(1, desc.n_words), dtype=torch.int64, device=device)
+    elif fmt in W16:  # 16-bit words, two per 32-bit slot
+        t["pack"] = torch.empty(max(1, desc.n_words // 2), dtype=torch.int32, device=device)
+    else:
+        t["pack"] = torch.empty(max(1, desc.n_words), dtype=torch.int32, device=device)
+    if fmt in (FIX, FIX16):
         t["row_exp"] = torch.empty(max(1, n), dtype=torch.int16, device=device)
     if desc.n_split_units > 0:
         t["units"] = torch.empty(4 * desc.n_units, dtype=torch.int32, device=device)
@@ -371,7 +378,7 @@ def encode_transpose(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, 
     adjoint product A_q^T g."""
     if isinstance(fmt, str):
         fmt = FMT_BY_NAME[fmt]
-    if fmt == FIX:
+    if fmt in (FIX, FIX16):
         raise ValueError("FIX quantises per row: a transposed copy would not hold (A_q)^T")
     t_rowptr, t_col, t_val = csr_transpose(rowptr, col, val, n, m, device)
     return encode(t_rowptr, t_col, t_val, m, n, fmt, D, C, sigma, perm_mode, device,

@@ -113,4 +113,49 @@ __device__ inline uint32_t quant_fix(float v, int32_t e, int D) {
   return ((uint32_t)(int32_t)q) << (D + 1);
 }
 
+// ---- 16-bit words --------------------------------------------------------------
+
+// E5MY (16-bit words, Y = 9 - D): the binary16 pattern with its low D + 1
+// bits given to the delta and the flag.  The float32 input is rounded once,
+// straight onto that grid, with ties away from zero: for |v| >= 2^-14 by
+// the integer rule on the float32 magnitude (keep Y mantissa bits), below
+// it on the grid 2^(D + 1 - 24); past the largest finite value
+// (2 - 2^-Y) * 2^15 the result is infinity; NaN -> 0x7E00.  The result is
+// a binary16 value, so the final conversion is exact.  Returns the 16-bit
+// field in the low half.
+__device__ inline uint32_t quant_e5my(float v, int D) {
+  const uint32_t b = __float_as_uint(v);
+  const uint32_t sign16 = (b >> 16) & 0x8000u;
+  const uint32_t mag = b & 0x7FFFFFFFu;
+  if (mag > 0x7F800000u) return 0x7E00u;
+  if (mag == 0x7F800000u) return sign16 | 0x7C00u;
+  const int Y = 9 - D;
+  const float a = __uint_as_float(mag);
+  float q;
+  if (a >= 0x1p-14f) {
+    const uint32_t sh = 23u - (uint32_t)Y;  // dropped float32 mantissa bits
+    q = __uint_as_float((mag + (1u << (sh - 1))) & ~((1u << sh) - 1u));
+  } else {
+    q = ldexpf(roundf(ldexpf(a, 23 - D)), D - 23);
+  }
+  if (q > ldexpf(2.0f - ldexpf(1.0f, -Y), 15)) return sign16 | 0x7C00u;
+  return sign16 | (uint32_t)__half_as_ushort(__float2half_rn(q));
+}
+
+// FIX16: FIX with a V = 15 - D bit field: e = e(M) - (V - 1), q as in
+// quant_fix, returned in the upper V bits of the low half.
+__device__ inline int32_t fix16_row_exponent(float absmax, int D) {
+  if (absmax == 0.0f) return 0;
+  int e;
+  frexpf(absmax, &e);
+  return e - (15 - D - 1);
+}
+
+__device__ inline uint32_t quant_fix16(float v, int32_t e, int D) {
+  const int32_t lim = (1 << (15 - D - 1)) - 1;
+  int32_t q = (int32_t)roundf(ldexpf(v, -e));
+  q = q < -lim ? -lim : (q > lim ? lim : q);
+  return ((uint32_t)q << (D + 1)) & 0xFFFFu;
+}
+
 }  // namespace pksell

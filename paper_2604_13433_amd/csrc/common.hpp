@@ -49,6 +49,11 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Formats with 16-bit words (two per 32-bit slot).
+__host__ __device__ inline bool is_w16(int fmt) {
+  return fmt == PKSELL_E5MY || fmt == PKSELL_FIX16;
+}
+
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 // Carves aligned sub-buffers out of a caller workspace.

@@ -75,10 +75,13 @@ __global__ void k_check_rows(const int64_t *__restrict__ rowptr, const int32_t *
   }
 }
 
-// Stored words per row: nonzeros plus one dummy per delta >= 2^D (D = 31:
-// plain SELL, no dummies).
+// Stored words per row: nonzeros plus the dummies of every delta >= 2^D
+// (D = 31: plain SELL, no dummies): one with 32- and 64-bit words, a chain
+// of ceil(d / (2^15 - 1)) with 16-bit words (``chain``).
+constexpr uint32_t kDummyMax16 = (1u << 15) - 1u;
+
 __global__ void k_count(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                        int64_t n, int32_t sigma, int64_t k_left, int32_t D,
+                        int64_t n, int32_t sigma, int64_t k_left, int32_t D, int32_t chain,
                         int32_t *__restrict__ cnt, EncInfo *info) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long dum = 0;
@@ -88,7 +91,8 @@ __global__ void k_count(const int64_t *__restrict__ rowptr, const int32_t *__res
     const uint32_t lim = D >= 31 ? 0xFFFFFFFFu : (1u << D);
     for (int64_t e = rb; e < re; ++e) {
       uint32_t c = (uint32_t)col[e];
-      dum += (c - prev) >= lim;
+      const uint32_t d = c - prev;
+      if (d >= lim) dum += chain ? (d + kDummyMax16 - 1) / kDummyMax16 : 1u;
       prev = c;
     }
     cnt[i] = (int32_t)(re - rb + dum);
@@ -136,9 +140,11 @@ __global__ void k_sigma_rank(const int32_t *__restrict__ cnt, int64_t n, int32_t
   }
 }
 
-// offset[k + 1] = C * (max count over the slice's stored rows); offset[0] = 0.
+// offset[k + 1] = C * (max count over the slice's stored rows), rounded up
+// to even for 16-bit words (two per 32-bit slot); offset[0] = 0.
 __global__ void k_slice_width(const int32_t *__restrict__ cnt, const int32_t *__restrict__ stored_rows,
-                              int64_t n, int32_t C, int64_t n_slices, int64_t *__restrict__ offset) {
+                              int64_t n, int32_t C, int64_t n_slices, int32_t even,
+                              int64_t *__restrict__ offset) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0) offset[0] = 0;
   if (k >= n_slices) return;
@@ -150,6 +156,7 @@ __global__ void k_slice_width(const int32_t *__restrict__ cnt, const int32_t *__
       w = c > w ? c : w;
     }
   }
+  if (even) w += w & 1;
   offset[k + 1] = (int64_t)C * w;
 }
 
@@ -382,6 +389,60 @@ __global__ void k_fill_packsell64(const int64_t *__restrict__ rowptr, const int3
   for (; j < w; ++j) out[j * C] = 0ull;
 }
 
+// 16-bit words (E5MY, FIX16): one thread per stored row position, as
+// k_fill_packsell; words 2i and 2i + 1 of a lane share one 32-bit slot
+// (low and high half), and a delta >= 2^D is carried by a dummy chain.
+template <int FMT, typename VT>
+__global__ void k_fill_packsell16(const int64_t *__restrict__ rowptr,
+                                  const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                  int64_t n, int32_t C, int32_t sigma, int64_t k_left, int32_t D,
+                                  int64_t n_slices, const int32_t *__restrict__ stored_rows,
+                                  const int64_t *__restrict__ offset, uint32_t *__restrict__ pack,
+                                  int16_t *__restrict__ row_exp) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slices * C) return;
+  int64_t k = i / C, l = i - k * C;
+  int64_t s = offset[k] / 2;             // in slots
+  int64_t w2 = (offset[k + 1] - offset[k]) / (2 * C);
+  uint32_t *out = pack + s + l;
+  int64_t j = 0;      // words written
+  uint32_t half = 0;  // the pending low word of a slot
+  auto put = [&](uint32_t word) {
+    if (j & 1) out[(j >> 1) * C] = half | (word << 16);
+    else half = word;
+    ++j;
+  };
+  if (i < n) {
+    int64_t r = stored_rows[i];
+    int64_t rb = rowptr[r], re = rowptr[r + 1];
+    int32_t ex = 0;
+    if constexpr (FMT == PKSELL_FIX16) {
+      float mx = 0.0f;  // values were checked finite by the analyse phase
+      for (int64_t e = rb; e < re; ++e) mx = fmaxf(mx, fabsf(load_value(val, e)));
+      ex = fix16_row_exponent(mx, D);
+      row_exp[i] = (int16_t)ex;
+    }
+    uint32_t prev = left_offset(r, sigma, k_left);
+    const uint32_t lim = 1u << D;
+    for (int64_t e = rb; e < re; ++e) {
+      const uint32_t c = (uint32_t)col[e];
+      uint32_t d = c - prev;
+      prev = c;
+      const float v = load_value(val, e);
+      const uint32_t vb = FMT == PKSELL_E5MY ? quant_e5my(v, D) : quant_fix16(v, ex, D);
+      if (d >= lim) {
+        while (d > 0) {
+          const uint32_t step = d < kDummyMax16 ? d : kDummyMax16;
+          put(step << 1);
+          d -= step;
+        }
+      }
+      put(vb | (d << 1) | 1u);
+    }
+  }
+  while (j < 2 * w2) put(0u);
+}
+
 // A SELL slot value: half values are rounded from float32 (float64 input
 // first rounded to float32, the intermediate pinned by load_value), as the
 // FP16 PackSELL words are.
@@ -463,7 +524,7 @@ int check_common(int64_t n, int64_t m, int64_t nnz, int32_t C, int32_t sigma,
 int analyse(const int64_t *rowptr, const int32_t *col, const void *finite_val,
             int32_t val_dtype, int64_t n, int64_t m, int64_t nnz, int32_t C, int32_t sigma,
             int32_t D, int64_t n_slices, int64_t *offset, void *perm, int32_t perm_bytes,
-            int32_t split_words, const Plan &p, hipStream_t st, EncInfo *host) {
+            int32_t split_words, bool w16, const Plan &p, hipStream_t st, EncInfo *host) {
   PKS_HIP(hipMemsetAsync(p.info, 0, sizeof(EncInfo), st));
   const int64_t rb = cdiv(n, kBlock);
   if (n > 0) {
@@ -481,7 +542,8 @@ int analyse(const int64_t *rowptr, const int32_t *col, const void *finite_val,
             "malformed input (flags 0x%x: 1 rowptr, 2 column range, 4 column order, "
             "8 non-finite value for FIX)", host->err);
   if (n > 0) {
-    k_count<<<rb, kBlock, 0, st>>>(rowptr, col, n, sigma, host->k_left, D, p.cnt, p.info);
+    k_count<<<rb, kBlock, 0, st>>>(rowptr, col, n, sigma, host->k_left, D, w16 ? 1 : 0, p.cnt,
+                                   p.info);
     PKS_LAUNCHED();
     const int64_t nwin = cdiv(n, sigma);
     const int64_t chunks = cdiv(n < sigma ? n : sigma, kBlock);
@@ -489,7 +551,7 @@ int analyse(const int64_t *rowptr, const int32_t *col, const void *finite_val,
                                                   perm_bytes);
     PKS_LAUNCHED();
     k_slice_width<<<cdiv(n_slices, kBlock), kBlock, 0, st>>>(p.cnt, p.stored_rows, n, C,
-                                                            n_slices, offset);
+                                                            n_slices, w16 ? 1 : 0, offset);
     PKS_LAUNCHED();
     const int64_t ntiles = cdiv(n_slices, kScanTile);
     k_scan_tiles<<<ntiles, kBlock, 0, st>>>(offset + 1, n_slices, p.tile_sums);
@@ -570,8 +632,11 @@ int pksell_encode_query(int64_t n, int64_t m, int64_t nnz, int32_t C, int32_t si
     case PKSELL_E8MY: PKS_CHECK(D >= 1 && D <= 22, PKSELL_EINVAL, "E8MY needs 1 <= D <= 22"); break;
     case PKSELL_FIX: PKS_CHECK(D >= 1 && D <= 29, PKSELL_EINVAL, "FIX needs 1 <= D <= 29"); break;
     case PKSELL_E11MY: PKS_CHECK(D >= 1 && D <= 51, PKSELL_EINVAL, "E11MY needs 1 <= D <= 51"); break;
+    case PKSELL_E5MY: PKS_CHECK(D >= 1 && D <= 8, PKSELL_EINVAL, "E5MY needs 1 <= D <= 8"); break;
+    case PKSELL_FIX16: PKS_CHECK(D >= 1 && D <= 13, PKSELL_EINVAL, "FIX16 needs 1 <= D <= 13"); break;
     default: PKS_CHECK(false, PKSELL_EINVAL, "unknown format %d", fmt);
   }
+  PKS_CHECK(!is_w16(fmt) || C == kWave, PKSELL_EINVAL, "16-bit words need C = 64");
   std::memset(A, 0, sizeof(*A));
   A->n = n;
   A->m = m;
@@ -596,17 +661,18 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val, in
             "implicit mode needs perm");
   Plan p = carve(ws, A->n, A->n_slices);
   PKS_CHECK(ws && ws_bytes >= p.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes", p.bytes);
-  PKS_CHECK(A->split_words == 0 || A->fmt != PKSELL_E11MY, PKSELL_EINVAL,
-            "split_words: not for 64-bit words (E11MY)");
+  PKS_CHECK(A->split_words == 0 || (A->fmt != PKSELL_E11MY && !is_w16(A->fmt)), PKSELL_EINVAL,
+            "split_words: 32-bit words only");
   PKS_CHECK(A->split_words == 0 || (A->C == kWave && A->split_words % 8 == 0 &&
                                     A->split_words >= 8 && A->split_words <= (1 << 24)),
             PKSELL_EINVAL, "split_words must be 0 or a multiple of 8 in [8, 2^24], with C = 64");
   hipStream_t st = as_stream(stream);
   if (A->pack == nullptr) {
     EncInfo h{};
-    int rc = analyse(rowptr, col, A->fmt == PKSELL_FIX ? val : nullptr, val_dtype, A->n, A->m,
-                     A->nnz, A->C, A->sigma, A->D, A->n_slices, A->offset, A->perm,
-                     A->perm_bytes, A->split_words, p, st, &h);
+    const bool fix = A->fmt == PKSELL_FIX || A->fmt == PKSELL_FIX16;
+    int rc = analyse(rowptr, col, fix ? val : nullptr, val_dtype, A->n, A->m, A->nnz, A->C,
+                     A->sigma, A->D, A->n_slices, A->offset, A->perm, A->perm_bytes,
+                     A->split_words, is_w16(A->fmt), p, st, &h);
     if (rc) return rc;
     A->k_left = h.k_left;
     A->n_dummies = (int64_t)h.n_dummies;
@@ -617,7 +683,8 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val, in
     A->n_split_slices = h.split_slices;
     return PKSELL_OK;
   }
-  PKS_CHECK(A->fmt != PKSELL_FIX || A->row_exp, PKSELL_EINVAL, "FIX needs row_exp");
+  PKS_CHECK((A->fmt != PKSELL_FIX && A->fmt != PKSELL_FIX16) || A->row_exp, PKSELL_EINVAL,
+            "FIX needs row_exp");
   const int64_t rows = A->n_slices * A->C;
   if (rows == 0) return PKSELL_OK;
   const bool split = A->split_words > 0 && A->n_split_units > 0;
@@ -639,6 +706,23 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val, in
       k_fill_packsell64<double><<<g, kBlock, 0, st>>>(rowptr, col, static_cast<const double *>(val),
                                                       A->n, A->C, A->sigma, A->k_left, A->D,
                                                       A->n_slices, p.stored_rows, A->offset, pk);
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
+  if (is_w16(A->fmt)) {
+#define PKS_FILL16(F, VT)                                                                     \
+  k_fill_packsell16<F, VT><<<g, kBlock, 0, st>>>(rowptr, col, static_cast<const VT *>(val), \
+                                                 A->n, A->C, A->sigma, A->k_left, A->D,     \
+                                                 A->n_slices, p.stored_rows, A->offset,     \
+                                                 A->pack, A->row_exp)
+    if (val_dtype == PKSELL_F32) {
+      if (A->fmt == PKSELL_E5MY) PKS_FILL16(PKSELL_E5MY, float);
+      else PKS_FILL16(PKSELL_FIX16, float);
+    } else {
+      if (A->fmt == PKSELL_E5MY) PKS_FILL16(PKSELL_E5MY, double);
+      else PKS_FILL16(PKSELL_FIX16, double);
+    }
+#undef PKS_FILL16
     PKS_LAUNCHED();
     return PKSELL_OK;
   }
@@ -697,7 +781,7 @@ int pksell_sell_encode(const int64_t *rowptr, const int32_t *col, const void *va
   if (S->val == nullptr) {
     EncInfo h{};
     int rc = analyse(rowptr, col, nullptr, val_dtype, S->n, S->m, S->nnz, S->C, S->sigma, 31,
-                     S->n_slices, S->offset, S->perm, S->perm_bytes, 0, p, st, &h);
+                     S->n_slices, S->offset, S->perm, S->perm_bytes, 0, false, p, st, &h);
     if (rc) return rc;
     S->n_slots = h.n_words;
     return PKSELL_OK;

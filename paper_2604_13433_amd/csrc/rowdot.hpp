@@ -58,7 +58,7 @@ template <int FMT>
 __device__ inline RowOut row_out(const void *perm, int32_t perm_bytes, const int16_t *row_exp,
                                  uint32_t t, uint32_t n, const RowGeo &g) {
   RowOut r = row_out(perm, perm_bytes, t, n, g);
-  if constexpr (FMT == PKSELL_FIX)
+  if constexpr (FMT == PKSELL_FIX || FMT == PKSELL_FIX16)
     r.e = __builtin_amdgcn_raw_buffer_load_b16(make_rsrc(row_exp, 2u * n), 2u * t, 0, 0);
   return r;
 }

@@ -516,6 +516,8 @@ int check_matrix(const pksell_matrix *A) {
   PKS_CHECK(A, PKSELL_EINVAL, "null matrix");
   PKS_CHECK(A->fmt != PKSELL_E11MY, PKSELL_EINVAL,
             "64-bit words (E11MY): use pksell_spmv_f64, the only entry point for them");
+  PKS_CHECK(!is_w16(A->fmt), PKSELL_EINVAL,
+            "16-bit words (E5MY, FIX16): pksell_spmv with k = 1 is their only product");
   PKS_CHECK(A->n == 0 || (A->offset && (A->n_words == 0 || A->pack)), PKSELL_EINVAL,
             "matrix arrays not set");
   PKS_CHECK(A->perm_mode != PKSELL_IMPLICIT || A->n == 0 || A->perm, PKSELL_EINVAL,
@@ -643,6 +645,9 @@ int zero_f32(float *p, int64_t len, hipStream_t st) {
 
 int check_matrix_public(const pksell_matrix *A) { return check_matrix(A); }
 
+// 16-bit words (spmv16.hip).
+int spmv16(const pksell_matrix *A, const float *x, float *y, int64_t k, hipStream_t st);
+
 }  // namespace pksell
 
 using namespace pksell;
@@ -650,6 +655,7 @@ using namespace pksell;
 extern "C" {
 
 int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, void *stream) {
+  if (A && is_w16(A->fmt)) return spmv16(A, x, y, k, as_stream(stream));
   int rc = check_matrix(A);
   if (rc) return rc;
   PKS_CHECK(k >= 1 && k <= 64, PKSELL_EINVAL, "k must be in [1, 64]");

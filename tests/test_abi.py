@@ -159,3 +159,14 @@ def test_pcg64_rejects_on_host():
         assert L.pksell_last_error()
     rc, desc, _ = _query(fmt=B.E8MY, D=9)
     assert L.pksell_pcg64_workspace(None, ctypes.byref(desc), ctypes.byref(ws)) == B.EINVAL
+
+
+def test_encode_query_16_bit_words():
+    """E5MY takes 1 <= D <= 8, FIX16 1 <= D <= 13, both only with C = 64."""
+    for fmt, lo, hi in ((B.E5MY, 1, 8), (B.FIX16, 1, 13)):
+        for D in (lo, hi):
+            rc, d, _ = _query(fmt=fmt, D=D, C=64)
+            assert rc == B.OK and d.fmt == fmt and d.D == D
+        for D in (lo - 1, hi + 1):
+            assert _query(fmt=fmt, D=D, C=64)[0] == B.EINVAL
+        assert _query(fmt=fmt, D=lo, C=32)[0] == B.EINVAL

@@ -1,0 +1,158 @@
+"""GPU parity for 16-bit-word PackSELL (E5MY and FIX16 values).
+
+The device keeps two consecutive words of a row in each 32-bit slot, and
+rounds every lane's word count up to even.  The tests unfold those slots
+back into the paper's column-major 16-bit layout.  The words must then
+equal the 16-bit oracle's bit for bit, and the extra padding word must be
+zero.  Products must equal the oracle's float64 product on the same
+quantised values within 1e-6, normalised by ||A_q||_inf ||x||_inf.  Every
+other entry point, and k > 1, must reject these formats.
+"""
+import numpy as np
+import pytest
+import torch
+
+from helpers import SPMV_TOL, random_csr
+from oracle import linalg as L
+from oracle import packsell16 as P16
+from paper_2604_13433_amd import binding as B
+from paper_2604_13433_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+FMT = {"e5my": P16.FMT_E5MY, "fix16": P16.FMT_FIX16}
+
+
+def encode_both(a, fmt, D, sigma=256, mode=B.IMPLICIT):
+    A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, sigma, mode, DEV)
+    E = P16.encode(a.rowptr, a.col, a.val, a.n, a.m, FMT[fmt], D, 64, sigma,
+                   P16.PERM_IMPLICIT if mode == B.IMPLICIT else P16.PERM_EXPLICIT)
+    return A, E
+
+
+def unfold(A):
+    """Device slots -> per-slice arrays of 16-bit words, shape (2 * w2, 64)."""
+    off = A.offset.cpu().numpy()
+    slots = A.pack.cpu().numpy().view(np.uint32)[: A.n_words // 2]
+    out = []
+    for k in range(A.desc.n_slices):
+        s = slots[off[k] // 2: off[k + 1] // 2].reshape(-1, 64)
+        words = np.empty((2 * s.shape[0], 64), np.uint16)
+        words[0::2] = (s & 0xFFFF).astype(np.uint16)
+        words[1::2] = (s >> 16).astype(np.uint16)
+        out.append(words)
+    return out
+
+
+def check_words(A, E):
+    assert A.k_left == E.k_left and A.n_dummies == E.n_dummies
+    assert np.array_equal(A.perm.cpu().numpy()[: A.n].astype(np.int64), E.perm)
+    for k, words in enumerate(unfold(A)):
+        w = (E.offset[k + 1] - E.offset[k]) // 64
+        assert words.shape[0] == w + (w & 1), k
+        assert np.array_equal(words[:w], E.pack[E.offset[k]: E.offset[k + 1]].reshape(w, 64)), k
+        assert not words[w:].any(), k
+    if E.row_exp is not None:
+        assert np.array_equal(A.t["row_exp"].cpu().numpy()[: A.n].astype(np.int64), E.row_exp)
+
+
+def check_product(A, a, fmt, D, x, E, mode=B.IMPLICIT):
+    y = B.spmv(A, torch.from_numpy(x.astype(np.float32)).to(DEV)).cpu().numpy().astype(np.float64)
+    q = P16.quantized(a.rowptr, a.val, a.n, FMT[fmt], D)
+    ref = L.spmv(a.rowptr, a.col, q, x.astype(np.float32).astype(np.float64))
+    if mode == B.EXPLICIT:
+        ref = ref[E.stored_rows]
+    den = L.inf_norm(a.rowptr, q) * float(np.abs(x).max())
+    err = float(np.max(np.abs(y - ref))) / den if den else float(np.max(np.abs(y - ref)))
+    assert err <= SPMV_TOL, err
+    return y
+
+
+@pytest.mark.parametrize("fmt,D", [("e5my", 7), ("e5my", 2), ("e5my", 8), ("fix16", 7),
+                                   ("fix16", 13), ("fix16", 1)])
+@pytest.mark.parametrize("mode", [B.IMPLICIT, B.EXPLICIT])
+def test_random_words_and_product(fmt, D, mode):
+    for si, (n, m, dens) in enumerate([(37, 53, 0.2), (700, 650, 0.03), (2500, 3000, None)]):
+        a = random_csr(60 + si, n, m, density=dens) if dens else random_csr(60 + si, n, m,
+                                                                           per_row=11)
+        A, E = encode_both(a, fmt, D, mode=mode)
+        check_words(A, E)
+        check_product(A, a, fmt, D, np.random.default_rng(si).uniform(-1, 1, a.m), E, mode)
+
+
+def test_long_dummy_chains():
+    """Columns up to 2^17 apart: chains of up to five dummies per jump."""
+    rng = np.random.default_rng(11)
+    n, m = 3000, 150000
+    rows, cols = [], []
+    for i in range(n):
+        c = np.sort(rng.choice(m, size=rng.integers(0, 9), replace=False))
+        rows += [i] * c.size
+        cols += list(c)
+    a = W.csr_from_triplets(n, m, rows, cols, rng.standard_normal(len(rows)))
+    for fmt, D in (("e5my", 6), ("fix16", 10)):
+        A, E = encode_both(a, fmt, D, sigma=64)
+        assert E.n_dummies > a.nnz  # long chains
+        check_words(A, E)
+        check_product(A, a, fmt, D, rng.uniform(-1, 1, m), E)
+
+
+def test_laplace3d_128_full_size():
+    """The 7-point 128^3 Laplacian with E5M2 values (D = 7) at the
+    benchmark's launch configuration (sigma = 256, explicit order)."""
+    a = W.m2_laplace3d(128)
+    A, E = encode_both(a, "e5my", 7, mode=B.EXPLICIT)
+    check_words(A, E)
+    check_product(A, a, "e5my", 7, W.uniform_vector(a.m, 3).astype(np.float64), E, B.EXPLICIT)
+
+
+def test_poisson2d_fix16_int4_is_exact():
+    """The 5-point 2048^2 Poisson matrix (values 4 and -1) with FIX16 at
+    D = 11 (4-bit integers): dummies only where a grid line ends (a jump of
+    exactly 2048), and the quantised values are the values themselves, so
+    the product is the float32 product of A."""
+    a = W.poisson2d(2048)
+    A, E = encode_both(a, "fix16", 11, mode=B.EXPLICIT)
+    assert A.n_dummies == 2 * 2048 - 2
+    assert np.array_equal(P16.quantized(a.rowptr, a.val, a.n, P16.FMT_FIX16, 11), a.val)
+    check_words(A, E)
+    check_product(A, a, "fix16", 11, W.uniform_vector(a.m, 5).astype(np.float64), E, B.EXPLICIT)
+
+
+def test_edges():
+    empty = W.csr_from_triplets(0, 0, [], [], [])
+    A = B.encode(empty.rowptr, empty.col, empty.val, 0, 0, "e5my", 7, 64, 256, B.IMPLICIT, DEV)
+    assert B.spmv(A, torch.zeros(0, device=DEV)).numel() == 0
+    hollow = W.csr_from_triplets(130, 40000, [3, 3, 129], [0, 39999, 20], [1.0, -2.0, 0.5])
+    for fmt, D in (("e5my", 5), ("fix16", 9)):
+        A, E = encode_both(hollow, fmt, D)
+        check_words(A, E)
+        x = np.zeros(40000)
+        x[0], x[39999], x[20] = 1.0, 2.0, 4.0
+        y = B.spmv(A, torch.from_numpy(x.astype(np.float32)).to(DEV)).cpu().numpy()
+        want = np.zeros(130)
+        want[3], want[129] = 1.0 - 4.0, 2.0
+        assert np.array_equal(y, want)
+    a0 = W.csr_from_triplets(70, 0, [], [], [])  # m = 0: y = 0
+    A = B.encode(a0.rowptr, a0.col, a0.val, 70, 0, "e5my", 7, 64, 256, B.IMPLICIT, DEV)
+    assert not B.spmv(A, torch.zeros(0, device=DEV), torch.ones(70, device=DEV)).any()
+
+
+def test_other_entry_points_reject_16_bit_words():
+    a = random_csr(51, 300, 300, per_row=5)
+    A, _ = encode_both(a, "e5my", 7)
+    with pytest.raises(B.PackSELLError):
+        B.spmv(A, torch.zeros(a.m, 4, device=DEV))  # k > 1
+    with pytest.raises(B.PackSELLError):
+        B.spmv_t(A, torch.zeros(a.n, device=DEV))
+    with pytest.raises(B.PackSELLError):
+        B.BatchedSpMV([A], [torch.zeros(a.m, device=DEV)], [torch.zeros(a.n, device=DEV)])
+    with pytest.raises(B.PackSELLError):
+        B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e5my", 7, 64, 256, B.IMPLICIT, DEV,
+                 split_words=64)
+    with pytest.raises(B.PackSELLError):
+        B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e5my", 7, 32, 256, B.IMPLICIT, DEV)
+    hi = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float64, 64, 256, B.IMPLICIT, DEV)
+    with pytest.raises(B.PackSELLError):
+        B.pcg(A, hi, torch.ones(a.n, dtype=torch.float64, device=DEV), tol=1e-8, m_in=5,
+              max_outer=5)
