@@ -276,6 +276,7 @@ def main():
         out["laplace3d_256"] = large_leg(args, torch, B, W)
     if not args.no_extra:
         out["fp64_words"] = fp64_leg(args, a, torch, B, W)
+        out["words16"] = w16_leg(args, torch, B, W)
     if not args.no_batched:
         out["batched"] = batched_leg(args, torch, B, W)
     if not args.no_pcg:
@@ -496,6 +497,52 @@ def block_leg(args, torch, B, W):
                                                   "sell_fp32": B.sell_spmv(S, x).cpu().numpy()}))
     log(f"[bench] block3_27pt: {res}")
     return res
+
+
+def w16_leg(args, torch, B, W):
+    """16-bit words against 32-bit words and half-value SELL on the same
+    matrix, explicit order, sigma = 256: E5M2 values (E5MY, D = 7) on the
+    7-point 128^3 Laplacian, and 4-bit FIX16 (D = 11, exact for the 4 / -1
+    values) on the 5-point 2048^2 Poisson matrix.  Backward errors (eq. 5)
+    against the float64 product are computed in the CPU leg."""
+    dev = torch.device("cuda:0")
+    out = {}
+    for label, a, fmt, D in (("laplace3d_128_e5m2", W.m2_laplace3d(128), "e5my", 7),
+                             ("poisson2d_2048_fix16_int4", W.poisson2d(2048), "fix16", 11)):
+        res = {"n": a.n, "nnz": a.nnz}
+        x = torch.from_numpy(W.uniform_vector(a.m, 13)).to(dev)
+        ys = {}
+        for name, mk in ((f"packsell16_{fmt}", lambda: B.encode(a.rowptr, a.col, a.val, a.n, a.m,
+                                                                  fmt, D, 64, 256, B.EXPLICIT,
+                                                                  dev)),
+                         ("packsell_fp16", lambda: B.encode(a.rowptr, a.col, a.val, a.n, a.m,
+                                                            "fp16", 15, 64, 256, B.EXPLICIT,
+                                                            dev)),
+                         ("sell_fp16", lambda: B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m,
+                                                             torch.float16, 64, 256, B.EXPLICIT,
+                                                             dev))):
+            M = mk()
+            ms, per, _ = time_variant(args, torch, B, M, a.m, a.n)
+            r = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
+                 "hbm_frac": round(per / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), "bytes": per}
+            if isinstance(M, B.PackSELLMatrix):
+                r["words"], r["dummies"] = M.n_words, M.n_dummies
+                # product in the original row order for the error check
+                y = B.spmv(M, x).cpu().numpy()
+                orig = (np.arange(a.n) // 256) * 256 + M.perm.cpu().numpy()[: a.n]
+                yo = np.empty_like(y)
+                yo[orig] = y
+                ys[name] = yo
+            res[name] = r
+            del M
+        for name in list(res):
+            if name.startswith("packsell16"):
+                res["speedup_vs_packsell_fp16"] = round(res["packsell_fp16"]["us"] / res[name]["us"], 3)
+                res["speedup_vs_sell_fp16"] = round(res["sell_fp16"]["us"] / res[name]["us"], 3)
+        EXTRA_CHECKS.append((label, a, x.cpu().numpy(), ys))
+        log(f"[bench] 16-bit words {label}: {res}")
+        out[label] = res
+    return out
 
 
 def multirhs_leg(args, a, A, torch, B, W):

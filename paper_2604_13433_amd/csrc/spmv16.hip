@@ -5,12 +5,14 @@
 // in the low half, 2i + 1 in the high half), slots column-major per slice of
 // C = 64 rows, so a lane reads a dword per two words and a wave a 256-byte
 // line per slot index, as with 32-bit words.  A wave walks S consecutive
-// slices together (S = 2 for narrow slices), eight slots (sixteen words)
-// in flight per slice; each word is decoded in registers (flag, delta of D
+// slices together (S = 2 for narrow slices), G slots (2G words) in flight
+// per slice; each word is decoded in registers (flag, delta of D
 // or 15 bits, value field), the running column gathers x (flag-0 words
 // gather past the buffer resource: 0, no request), and the products are
 // summed in float32 in word order.  FIX16 rows are scaled by 2^(e - D - 1)
 // once at the end.
+#include <algorithm>
+
 #include "rowdot.hpp"
 
 namespace pksell {
@@ -18,7 +20,6 @@ namespace pksell {
 namespace {
 
 constexpr int kB16 = 128;  // threads per workgroup
-constexpr int kSlots = 8;  // slots (two words each) in flight per slice
 
 struct Spmv16Args {
   const uint32_t *pack;
@@ -42,7 +43,11 @@ __device__ inline float value16(uint32_t bits) {
   else return (float)(int32_t)(int16_t)(uint16_t)bits;
 }
 
-template <int FMT, bool IMPL, int S>
+// G slots (2G words) per group and slice, sized on the host to the
+// matrix's slice width: every slot of a group issues a load and both of its
+// words a gather, so a group wider than the slices issues instructions for
+// padding (each a full 64-lane instruction, however few bytes it moves).
+template <int FMT, bool IMPL, int S, int G>
 __global__ __launch_bounds__(kB16) void k_spmv16(Spmv16Args a) {
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(b * (kB16 / kWave) + threadIdx.x / kWave);
@@ -73,33 +78,33 @@ __global__ __launch_bounds__(kB16) void k_spmv16(Spmv16Args a) {
     acc[i] = 0.0f;
     rs[i] = slice_words(a.pack + (off[i] >> 1), w[i]);
   }
-  for (uint32_t j = 0; j < wm; j += kSlots) {
-    uint32_t p[S][kSlots];
+  for (uint32_t j = 0; j < wm; j += G) {
+    uint32_t p[S][G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < kSlots; ++q) p[i][q] = j + q < w[i] ? stream_word(rs[i], lane, j + q) : 0u;
-    uint32_t o[S][2 * kSlots];
-    float v[S][2 * kSlots];
+      for (int q = 0; q < G; ++q) p[i][q] = j + q < w[i] ? stream_word(rs[i], lane, j + q) : 0u;
+    uint32_t o[S][2 * G];
+    float v[S][2 * G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int h = 0; h < 2 * kSlots; ++h) {
+      for (int h = 0; h < 2 * G; ++h) {
         const uint32_t wd = (h & 1) ? p[i][h >> 1] >> 16 : p[i][h >> 1] & 0xFFFFu;
         const bool flag = wd & 1u;
         c[i] += flag ? (wd >> 1) & a.dmask : (wd >> 1);
         o[i][h] = flag ? c[i] << 2 : oob;
         v[i][h] = value16<FMT>(flag ? wd & a.vmask : 0u);
       }
-    float xv[S][2 * kSlots];
+    float xv[S][2 * G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int h = 0; h < 2 * kSlots; ++h) xv[i][h] = buffer_load_f32(rx, o[i][h]);
+      for (int h = 0; h < 2 * G; ++h) xv[i][h] = buffer_load_f32(rx, o[i][h]);
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int h = 0; h < 2 * kSlots; ++h) acc[i] = fmaf(v[i][h], xv[i][h], acc[i]);
+      for (int h = 0; h < 2 * G; ++h) acc[i] = fmaf(v[i][h], xv[i][h], acc[i]);
   }
 #pragma unroll
   for (int i = 0; i < S; ++i) {
@@ -116,12 +121,27 @@ __global__ void k_zero16(float *y, int64_t n) {
   if (i < n) y[i] = 0.0f;
 }
 
-template <int FMT, bool IMPL>
-void launch16(const Spmv16Args &a, bool pair, hipStream_t st) {
-  if (pair)
-    k_spmv16<FMT, IMPL, 2><<<cdiv(cdiv(a.n_slices, 2), kB16 / kWave), kB16, 0, st>>>(a);
+// Two slices per wave with G < 8 (narrow slices), one with G = 8.
+template <int FMT, bool IMPL, int G>
+void launch16g(const Spmv16Args &a, hipStream_t st) {
+  if constexpr (G < 8)
+    k_spmv16<FMT, IMPL, 2, G><<<cdiv(cdiv(a.n_slices, 2), kB16 / kWave), kB16, 0, st>>>(a);
   else
-    k_spmv16<FMT, IMPL, 1><<<cdiv(a.n_slices, kB16 / kWave), kB16, 0, st>>>(a);
+    k_spmv16<FMT, IMPL, 1, G><<<cdiv(a.n_slices, kB16 / kWave), kB16, 0, st>>>(a);
+}
+
+template <int FMT, bool IMPL>
+void launch16(const Spmv16Args &a, int G, hipStream_t st) {
+  switch (G) {
+    case 1: launch16g<FMT, IMPL, 1>(a, st); break;
+    case 2: launch16g<FMT, IMPL, 2>(a, st); break;
+    case 3: launch16g<FMT, IMPL, 3>(a, st); break;
+    case 4: launch16g<FMT, IMPL, 4>(a, st); break;
+    case 5: launch16g<FMT, IMPL, 5>(a, st); break;
+    case 6: launch16g<FMT, IMPL, 6>(a, st); break;
+    case 7: launch16g<FMT, IMPL, 7>(a, st); break;
+    default: launch16g<FMT, IMPL, 8>(a, st); break;
+  }
 }
 
 }  // namespace
@@ -161,15 +181,16 @@ int spmv16(const pksell_matrix *A, const float *x, float *y, int64_t k, hipStrea
   a.geo = make_geo(A->sigma, A->k_left, A->C);
   a.dmask = (1u << A->D) - 1u;
   a.vmask = 0xFFFFu & ~((2u << A->D) - 1u);
-  // two slices per wave while a lane holds at most 8 slots (16 words)
-  const bool pair = A->n_words <= 16 * (int64_t)kWave * A->n_slices;
+  // slots per group: the average slots per lane, rounded up, at most 8
+  const int64_t slots = A->n_words / 2, lanes = (int64_t)kWave * A->n_slices;
+  const int G = (int)std::min<int64_t>(8, std::max<int64_t>(1, cdiv(slots, lanes)));
   const bool impl = A->perm_mode == PKSELL_IMPLICIT;
   if (A->fmt == PKSELL_E5MY) {
-    if (impl) launch16<PKSELL_E5MY, true>(a, pair, st);
-    else launch16<PKSELL_E5MY, false>(a, pair, st);
+    if (impl) launch16<PKSELL_E5MY, true>(a, G, st);
+    else launch16<PKSELL_E5MY, false>(a, G, st);
   } else {
-    if (impl) launch16<PKSELL_FIX16, true>(a, pair, st);
-    else launch16<PKSELL_FIX16, false>(a, pair, st);
+    if (impl) launch16<PKSELL_FIX16, true>(a, G, st);
+    else launch16<PKSELL_FIX16, false>(a, G, st);
   }
   PKS_LAUNCHED();
   return PKSELL_OK;
