@@ -141,13 +141,21 @@ struct SellView {
   const uint64_t *words;
   uint32_t dmask;   // 64-bit words: the flag-1 delta after >> 1 (columns < 2^30)
   uint64_t vmask;   // 64-bit words: the value field
+  int32_t group;    // slots per group of the product loops (host side)
 };
+
+// Slots per group for a loop over w slots per lane on average: w spread
+// evenly over the fewest groups of at most 8, at least 4.
+inline int32_t group_for(int64_t slots, int64_t lanes) {
+  const int64_t w = std::max<int64_t>(1, cdiv(slots, lanes > 0 ? lanes : 1));
+  return (int32_t)std::max<int64_t>(4, cdiv(w, cdiv(w, 8)));
+}
 
 // Row dot product of a 64-bit-word PackSELL lane (sec. 4.4 with W = 64):
 // columns from the eq. 4 offset plus the deltas, value * gather(column) for
 // flag-1 words; flag-0 words add 0 * gather(column) (a valid column of the
 // square operator), which keeps the loop branch-free.
-template <bool CWAVE, typename Gather>
+template <bool CWAVE, int G, typename Gather>
 __device__ inline double words64_row(const SellView &S, const Lane &ln, uint32_t stride,
                                      Gather gather) {
   const uint64_t *P = S.words + ln.s + ln.l;
@@ -156,10 +164,10 @@ __device__ inline double words64_row(const SellView &S, const Lane &ln, uint32_t
       make_rsrc(CWAVE ? S.words + ln.s : S.words, buf ? ln.w * 512u : 0u);
   uint32_t c = left_offset32(ln.t, S.geo);
   double acc = 0.0;
-  for (uint32_t j = 0; j < ln.w; j += kUnroll) {
-    uint64_t p[kUnroll];
+  for (uint32_t j = 0; j < ln.w; j += G) {
+    uint64_t p[G];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
+    for (int q = 0; q < G; ++q) {
       uint64_t v = 0ull;
       if (j + q < ln.w)
         v = buf ? __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(
@@ -168,10 +176,10 @@ __device__ inline double words64_row(const SellView &S, const Lane &ln, uint32_t
                 : __builtin_nontemporal_load(P + (j + q) * stride);
       p[q] = v;
     }
-    uint32_t cq[kUnroll];
-    double vv[kUnroll];
+    uint32_t cq[G];
+    double vv[G];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
+    for (int q = 0; q < G; ++q) {
       const uint32_t lo = (uint32_t)p[q];
       const bool flag = lo & 1u;
       c += flag ? ((lo >> 1) & S.dmask) : (uint32_t)(p[q] >> 1);
@@ -179,17 +187,19 @@ __device__ inline double words64_row(const SellView &S, const Lane &ln, uint32_t
       vv[q] = flag ? __builtin_bit_cast(double, p[q] & S.vmask) : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) acc = fma(vv[q], gather((int32_t)cq[q]), acc);
+    for (int q = 0; q < G; ++q) acc = fma(vv[q], gather((int32_t)cq[q]), acc);
   }
   return acc;
 }
 
 // Row dot product of a lane of the float64 operator: sum over its w slots
 // of val * gather(col).
-template <bool CWAVE, typename Gather>
+// G slots (or words) per group, sized on the host to the operator's slice
+// width (each slot of a group issues its loads and a gather, padding or not).
+template <bool CWAVE, int G, typename Gather>
 __device__ inline double sell_row(const SellView &S, const Lane &ln, uint32_t stride,
                                   Gather gather) {
-  if (S.kind == 1) return words64_row<CWAVE>(S, ln, stride, gather);
+  if (S.kind == 1) return words64_row<CWAVE, G>(S, ln, stride, gather);
   const int32_t *pc = S.col + ln.s + ln.l;
   const double *pv = S.val + ln.s + ln.l;
   // streamed slots need a wave-uniform slice start (C = 64)
@@ -198,11 +208,11 @@ __device__ inline double sell_row(const SellView &S, const Lane &ln, uint32_t st
   const __amdgpu_buffer_rsrc_t rv =
       make_rsrc(CWAVE ? S.val + ln.s : S.val, buf ? ln.w * 512u : 0u);
   double acc = 0.0;
-  for (uint32_t j = 0; j < ln.w; j += kUnroll) {
-    int32_t cc[kUnroll];
-    double vv[kUnroll];
+  for (uint32_t j = 0; j < ln.w; j += G) {
+    int32_t cc[G];
+    double vv[G];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
+    for (int q = 0; q < G; ++q) {
       const uint32_t jj = min(j + q, ln.w - 1);
       if (buf) {
         cc[q] = stream_elem<int32_t>(rc, ln.l, jj);
@@ -213,7 +223,7 @@ __device__ inline double sell_row(const SellView &S, const Lane &ln, uint32_t st
       }
     }
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) acc = fma(vv[q], gather(cc[q]), acc);
+    for (int q = 0; q < G; ++q) acc = fma(vv[q], gather(cc[q]), acc);
   }
   return acc;
 }
@@ -279,7 +289,9 @@ __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restr
 // overlaps the beta prologue.  Same arithmetic per row as k_inner_a.
 constexpr int kPairB = 128;
 
-template <int FMT, bool BUF>
+// G words per group and slice, sized on the host to the matrix's slice
+// width (each word of a group issues a load and a gather, padding or not).
+template <int FMT, bool BUF, int G = kUnroll>
 __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__restrict__ r,
                                                     const float *__restrict__ p_old,
                                                     float *__restrict__ p_new,
@@ -292,7 +304,7 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t k0 = wave * S;
   int64_t off[S + 1];
-  uint32_t w[S], p[S][kUnroll];
+  uint32_t w[S], p[S][G];
   __amdgpu_buffer_rsrc_t rs[S];
 #pragma unroll
   for (int i = 0; i <= S; ++i) off[i] = A.offset[min(k0 + i, A.n_slices)];
@@ -310,7 +322,7 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
     w[i] = stop ? 0u : (uint32_t)((off[i + 1] - off[i]) >> 6);
     rs[i] = slice_words(A.pack + off[i], w[i]);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < G; ++u) {
       uint32_t v = 0u;
       if (u < (int)w[i]) v = word(i, u);
       p[i][u] = v;
@@ -341,38 +353,38 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
     acc[i] = 0.0f;
     wm = max(wm, w[i]);
   }
-  for (uint32_t j = 0; j < wm; j += kUnroll) {
+  for (uint32_t j = 0; j < wm; j += G) {
     if (j > 0) {
 #pragma unroll
       for (int i = 0; i < S; ++i)
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < G; ++u) {
           uint32_t v = 0u;
           if (j + u < w[i]) v = word(i, j + u);
           p[i][u] = v;
         }
     }
-    uint32_t o[S][kUnroll];
-    float v[S][kUnroll];
+    uint32_t o[S][G];
+    float v[S][G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < G; ++u) {
         const Unpacked d = unpack(p[i][u], A.cd);
         c[i] += d.delta;
         o[i][u] = (p[i][u] & 1u) ? c[i] << 2 : oob;
         v[i][u] = decode_value<FMT>(d.vbits);
       }
-    float xv[S][kUnroll];
+    float xv[S][G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
+      for (int u = 0; u < G; ++u)
         xv[i][u] = fmaf(beta, buffer_load_f32(rp, o[i][u]), buffer_load_f32(rr_r, o[i][u]));
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) acc[i] = fmaf(v[i][u], xv[i][u], acc[i]);
+      for (int u = 0; u < G; ++u) acc[i] = fmaf(v[i][u], xv[i][u], acc[i]);
   }
   double part = 0.0;
 #pragma unroll
@@ -475,7 +487,7 @@ __device__ inline void axpy_pair(uint32_t n, double alpha, double *__restrict__ 
 // else the totals of the previous update's partials) gives the stopping
 // test and beta; then p_new = r + beta p_old, q = A p_new, partials of
 // p_new . q.
-template <bool CWAVE>
+template <bool CWAVE, int G = kUnroll>
 __global__ __launch_bounds__(kB) void k_cg_a(SellView S, const double *__restrict__ r,
                                             const double *__restrict__ p_old,
                                             double *__restrict__ p_new, double *__restrict__ q,
@@ -506,7 +518,7 @@ __global__ __launch_bounds__(kB) void k_cg_a(SellView S, const double *__restric
     // among them (the same fma of the same values), else loaded
     double own = 0.0;
     bool found = false;
-    const double qi = sell_row<CWAVE>(S, ln, stride, [&](int32_t c) {
+    const double qi = sell_row<CWAVE, G>(S, ln, stride, [&](int32_t c) {
       const double g = fma(beta, p_old[c], r[c]);
       if ((uint32_t)c - ri.base == ri.p) {  // column c is the row's own index
         own = g;
@@ -624,7 +636,7 @@ __global__ __launch_bounds__(kB) void k_outer_p(uint32_t n, const float *__restr
 }
 
 // q = A p (float64 SELL) with partials of p.q and p.r.
-template <bool CWAVE>
+template <bool CWAVE, int G = kUnroll>
 __global__ __launch_bounds__(kB) void k_outer_aq(SellView S, const double *__restrict__ p,
                                                 const double *__restrict__ r,
                                                 double *__restrict__ q, State *st,
@@ -638,7 +650,7 @@ __global__ __launch_bounds__(kB) void k_outer_aq(SellView S, const double *__res
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
     double own = 0.0;  // p at the row's own index, from the gathers when possible
     bool found = false;
-    const double qi = sell_row<CWAVE>(S, ln, stride, [&](int32_t c) {
+    const double qi = sell_row<CWAVE, G>(S, ln, stride, [&](int32_t c) {
       const double g = p[c];
       if ((uint32_t)c - ri.base == ri.p) {  // column c is the row's own index
         own = g;
@@ -699,7 +711,7 @@ __global__ __launch_bounds__(kB) void k_outer_check(State *st, Parts rr_in) {
 }
 
 // True residual r = b - A x with partials of r.r and b.b (float64 SELL).
-template <bool CWAVE>
+template <bool CWAVE, int G = kUnroll>
 __global__ __launch_bounds__(kB) void k_residual(SellView S, const double *__restrict__ b,
                                                 const double *__restrict__ x,
                                                 double *__restrict__ r, Parts out) {
@@ -709,7 +721,7 @@ __global__ __launch_bounds__(kB) void k_residual(SellView S, const double *__res
   double rr = 0.0, bb = 0.0;
   if (live) {
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)S.C;
-    const double ax = sell_row<CWAVE>(S, ln, stride, [&](int32_t c) { return x[c]; });
+    const double ax = sell_row<CWAVE, G>(S, ln, stride, [&](int32_t c) { return x[c]; });
     if (ln.t < S.n) {
       const uint32_t i = dst.row();
       const double ri = b[i] - ax;
@@ -791,6 +803,7 @@ SellView sell_view(const pksell_sell *S) {
   v.words = nullptr;
   v.dmask = 0;
   v.vmask = 0;
+  v.group = group_for(S->n_slots, S->n_slices * S->C);
   return v;
 }
 
@@ -811,6 +824,7 @@ SellView words64_view(const pksell_matrix *A) {
   v.words = reinterpret_cast<const uint64_t *>(A->pack);
   v.dmask = A->D >= 31 ? 0x7FFFFFFFu : (1u << A->D) - 1u;
   v.vmask = ~((2ull << A->D) - 1ull);
+  v.group = group_for(A->n_words, A->n_slices * A->C);
   return v;
 }
 
@@ -829,6 +843,17 @@ PackView pack_view(const pksell_matrix *A) {
   return v;
 }
 
+// Runs the launch statement given after G (which names the group size GG)
+// with GG = G in [4, 8].
+#define PKS_G(G, ...)                                      \
+  switch (G) {                                             \
+    case 4: { constexpr int GG = 4; __VA_ARGS__; } break;  \
+    case 5: { constexpr int GG = 5; __VA_ARGS__; } break;  \
+    case 6: { constexpr int GG = 6; __VA_ARGS__; } break;  \
+    case 7: { constexpr int GG = 7; __VA_ARGS__; } break;  \
+    default: { constexpr int GG = 8; __VA_ARGS__; } break; \
+  }
+
 struct Solve {
   const pksell_matrix *lo;
   SellView hv;  // the float64 operator
@@ -839,6 +864,7 @@ struct Solve {
   uint32_t n, vb;
   uint32_t gs, gp;  // grids of the SELL and PackSELL product kernels
   bool stream_ok;   // the inner words are addressable by 32-bit byte offsets
+  int g_in;         // inner product: words per group (4..8)
 
   Parts pa_for(uint32_t grid) const { return {w.pa.p, grid}; }
   Parts vec(const Parts &p) const { return {p.p, vb}; }
@@ -847,9 +873,9 @@ struct Solve {
   int residual() {
     const SellView &S = hv;
     const Parts out = pa_for(gs);
-    if (hv.C == kWave)
-      k_residual<true><<<gs, kB, 0, s>>>(S, b, x, w.r, out);
-    else
+    if (hv.C == kWave) {
+      PKS_G(hv.group, k_residual<true, GG><<<gs, kB, 0, s>>>(S, b, x, w.r, out));
+    } else
       k_residual<false><<<gs, kB, 0, s>>>(S, b, x, w.r, out);
     PKS_LAUNCHED();
     k_residual_totals<<<1, kB, 0, s>>>(w.st, out);
@@ -867,9 +893,9 @@ struct Solve {
       const Parts rr_in = vec((it & 1) ? w.pb0 : w.pb1);
       const Parts rr_out = vec((it & 1) ? w.pb1 : w.pb0);
       const Parts pq = pa_for(gs);
-      if (hv.C == kWave)
-        k_cg_a<true><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, rr_in, pq);
-      else
+      if (hv.C == kWave) {
+        PKS_G(hv.group, k_cg_a<true, GG><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, rr_in, pq));
+      } else
         k_cg_a<false><<<gs, kB, 0, s>>>(S, w.r, po, pn, w.q, w.st, rr_in, pq);
       PKS_LAUNCHED();
       k_cg_b<<<vb, kB, 0, s>>>(n, x, w.r, pn, w.q, w.st, pq, rr_out);
@@ -883,10 +909,20 @@ struct Solve {
     // gp workgroups either way: 4 slices each (256 threads x 1 slice per
     // wave, or 128 threads x 2 slices per wave), so the partial count agrees
     if constexpr (CW) {
-      if (stream_ok)
-        k_inner_a2<FMT, true><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
-      else
+      if (stream_ok) {
+#define PKS_IA2(GG)                                                                       \
+  k_inner_a2<FMT, true, GG><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out)
+        switch (g_in) {
+          case 4: PKS_IA2(4); break;
+          case 5: PKS_IA2(5); break;
+          case 6: PKS_IA2(6); break;
+          case 7: PKS_IA2(7); break;
+          default: PKS_IA2(8); break;
+        }
+#undef PKS_IA2
+      } else {
         k_inner_a2<FMT, false><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
+      }
     } else
       k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
   }
@@ -918,9 +954,9 @@ struct Solve {
     k_outer_p<<<vb, kB, 0, s>>>(n, w.zin, w.p0, w.st, vec(w.pb0));
     PKS_LAUNCHED();
     const Parts paq = pa_for(gs);
-    if (hv.C == kWave)
-      k_outer_aq<true><<<gs, kB, 0, s>>>(S, w.p0, w.r, w.q, w.st, paq);
-    else
+    if (hv.C == kWave) {
+      PKS_G(hv.group, k_outer_aq<true, GG><<<gs, kB, 0, s>>>(S, w.p0, w.r, w.q, w.st, paq));
+    } else
       k_outer_aq<false><<<gs, kB, 0, s>>>(S, w.p0, w.r, w.q, w.st, paq);
     PKS_LAUNCHED();
     k_outer_update<<<vb, kB, 0, s>>>(n, x, w.r, w.p0, w.q, w.st, paq, vec(w.pb1));
@@ -1070,6 +1106,7 @@ int run_pcg(const pksell_matrix *A_lo, const SellView &hv, int64_t n, const doub
   sv.gs = (uint32_t)cdiv((int64_t)hv.n_slices * hv.C, kB);
   sv.gp = A_lo ? (uint32_t)cdiv(A_lo->n_slices * A_lo->C, kB) : 0u;
   sv.stream_ok = A_lo && A_lo->n_words < (int64_t(1) << 30);
+  sv.g_in = A_lo ? group_for(A_lo->n_words, A_lo->n_slices * A_lo->C) : 8;
   sv.w = carve_work(ws, n, max_blocks_of(hv, A_lo));
   PKS_CHECK(ws && ws_bytes >= sv.w.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes",
             sv.w.bytes);

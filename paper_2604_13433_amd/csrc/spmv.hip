@@ -10,6 +10,8 @@
 // past the end (padding of empty rows can point past m).  Accumulation is
 // float32, in word order.  Workgroups are remapped so each XCD walks one
 // contiguous range of slices and its L2 serves the x window they share.
+#include <algorithm>
+
 #include "rowdot.hpp"
 
 namespace pksell {
@@ -29,6 +31,7 @@ struct SpmvArgs {
   int32_t C, perm_bytes, k, r0;
   RowGeo geo;
   Codec cd;
+  int32_t group;  // two-slice kernels: words per group (host side only)
 };
 
 // KB right-hand sides (columns r0 .. r0+KB-1 of the row-major x / y blocks;
@@ -124,9 +127,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv_group(SpmvArgs a) {
 // words (and then the gathers) of both are in flight at once -- more bytes
 // per wave between its dependent loads (offsets, words, x) than one slice
 // gives.  Same arithmetic, in the same word order per row, as k_spmv.
+// Words per group for the two-slice kernels: the average words per lane w
+// (rounded up) spread evenly over the fewest groups of at most 8, i.e.
+// ceil(w / ceil(w / 8)), at least 2.
+inline int pair_group(int64_t words, int64_t n_slices) {
+  const int64_t w = std::max<int64_t>(1, cdiv(words, (int64_t)kWave * (n_slices > 0 ? n_slices : 1)));
+  return (int)std::max<int64_t>(2, cdiv(w, cdiv(w, 8)));
+}
+
 constexpr int kPairBlock = 128;
 
-template <int FMT, bool BUF, bool IMPL>
+// G words per group and slice: the host sizes it to the matrix's slice
+// width (every word of a group issues a load and a gather, padding or not,
+// each a full 64-lane instruction).
+template <int FMT, bool BUF, bool IMPL, int G = kUnroll>
 __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
   constexpr int S = 2;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -157,39 +171,39 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
   __amdgpu_buffer_rsrc_t rs[S];
 #pragma unroll
   for (int i = 0; i < S; ++i) rs[i] = slice_words(a.pack + off[i], w[i]);
-  for (uint32_t j = 0; j < wm; j += kUnroll) {
-    uint32_t p[S][kUnroll];
+  for (uint32_t j = 0; j < wm; j += G) {
+    uint32_t p[S][G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
+      for (int q = 0; q < G; ++q) {
         uint32_t v = 0u;  // past the slice's width: a padding word
         if (j + q < w[i])
           v = BUF ? stream_word(rs[i], lane, j + q)
                   : __builtin_nontemporal_load(a.pack + off[i] + lane + (j + q) * kWave);
         p[i][q] = v;
       }
-    uint32_t cq[S][kUnroll];
-    float v[S][kUnroll];
+    uint32_t cq[S][G];
+    float v[S][G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
+      for (int q = 0; q < G; ++q) {
         const Unpacked u = unpack(p[i][q], a.cd);
         c[i] += u.delta;
         cq[i][q] = c[i];
         v[i][q] = decode_value<FMT>(u.vbits);
       }
-    float xv[S][kUnroll];
+    float xv[S][G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q)
+      for (int q = 0; q < G; ++q)
         xv[i][q] = buffer_load_f32(rx, (p[i][q] & 1u) ? cq[i][q] << 2 : a.m * 4u);
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) acc[i] = fmaf(v[i][q], xv[i][q], acc[i]);
+      for (int q = 0; q < G; ++q) acc[i] = fmaf(v[i][q], xv[i][q], acc[i]);
   }
 #pragma unroll
   for (int i = 0; i < S; ++i) {
@@ -358,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
 
 // SELL with C = 64 and streamed slots, two slices per wave in 128-thread
 // workgroups: the comparator gets the same structure as k_spmv_pair.
-template <typename T, bool IMPL, typename VT = T>
+template <typename T, bool IMPL, typename VT = T, int G = kUnroll>
 __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restrict__ offset,
                                                          const int32_t *__restrict__ scol,
                                                          const VT *__restrict__ sval,
@@ -392,26 +406,26 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
     rv[i] = make_rsrc(sval + off[i], w[i] * kWave * (uint32_t)sizeof(VT));
     acc[i] = T(0);
   }
-  for (uint32_t j = 0; j < wm; j += kUnroll) {
-    int32_t cc[S][kUnroll];
-    T vv[S][kUnroll];
+  for (uint32_t j = 0; j < wm; j += G) {
+    int32_t cc[S][G];
+    T vv[S][G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
+      for (int q = 0; q < G; ++q) {
         const bool in = j + q < w[i];
         cc[i][q] = in ? stream_elem<int32_t>(rc[i], lane, j + q) : 0;
         vv[i][q] = in ? (T)stream_elem<VT>(rv[i], lane, j + q) : T(0);
       }
-    T xv[S][kUnroll];
+    T xv[S][G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) xv[i][q] = j + q < w[i] ? x[cc[i][q]] : T(0);
+      for (int q = 0; q < G; ++q) xv[i][q] = j + q < w[i] ? x[cc[i][q]] : T(0);
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q)
+      for (int q = 0; q < G; ++q)
         if (j + q < w[i]) acc[i] += vv[i][q] * xv[i][q];
   }
 #pragma unroll
@@ -506,6 +520,7 @@ SpmvArgs make_args(const pksell_matrix *A, const float *x, float *y, int64_t k) 
   a.k = (int32_t)k;
   a.r0 = 0;
   a.cd = make_codec(A->D);
+  a.group = pair_group(A->n_words, A->n_slices);
   return a;
 }
 
@@ -535,6 +550,19 @@ inline bool pair_slices(int64_t words, int64_t n_slices) {
   return n_slices > 0 && words <= 16 * (int64_t)kWave * n_slices;
 }
 
+template <int FMT, bool IMPL>
+void launch_pair(const SpmvArgs &a, int G, int64_t pg, hipStream_t st) {
+  switch (G) {
+    case 2: k_spmv_pair<FMT, true, IMPL, 2><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 3: k_spmv_pair<FMT, true, IMPL, 3><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 4: k_spmv_pair<FMT, true, IMPL, 4><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 5: k_spmv_pair<FMT, true, IMPL, 5><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 6: k_spmv_pair<FMT, true, IMPL, 6><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 7: k_spmv_pair<FMT, true, IMPL, 7><<<pg, kPairBlock, 0, st>>>(a); break;
+    default: k_spmv_pair<FMT, true, IMPL, 8><<<pg, kPairBlock, 0, st>>>(a); break;
+  }
+}
+
 template <int FMT, bool CW>
 int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, bool buf, bool pair,
                   hipStream_t st) {
@@ -550,8 +578,9 @@ int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, bool buf, bool 
       }
       const int64_t pg = cdiv(cdiv(base.n_slices, 2), kPairBlock / kWave);
       const bool impl = base.perm != nullptr;
-      if (buf && impl) k_spmv_pair<FMT, true, true><<<pg, kPairBlock, 0, st>>>(base);
-      else if (buf) k_spmv_pair<FMT, true, false><<<pg, kPairBlock, 0, st>>>(base);
+      const int G = base.group;
+      if (buf && impl) launch_pair<FMT, true>(base, G, pg, st);
+      else if (buf) launch_pair<FMT, false>(base, G, pg, st);
       else if (impl) k_spmv_pair<FMT, false, true><<<pg, kPairBlock, 0, st>>>(base);
       else k_spmv_pair<FMT, false, false><<<pg, kPairBlock, 0, st>>>(base);
     } else {
@@ -644,6 +673,30 @@ int zero_f32(float *p, int64_t len, hipStream_t st) {
 }
 
 int check_matrix_public(const pksell_matrix *A) { return check_matrix(A); }
+
+// The two-slice SELL comparator with G slots per group, as k_spmv_pair.
+template <bool IMPL, typename VT>
+void launch_sell_pair(const pksell_sell *S, const void *x, void *y, const void *perm, int G,
+                      int64_t pg, hipStream_t st) {
+  const VT *val = static_cast<const VT *>(S->val);
+  const float *xf = static_cast<const float *>(x);
+  float *yf = static_cast<float *>(y);
+  const RowGeo g = make_geo(S->sigma, 0, S->C);
+  const uint32_t n = (uint32_t)S->n, ns = (uint32_t)S->n_slices;
+#define PKS_SP(GG)                                                                       \
+  k_sell_pair<float, IMPL, VT, GG><<<pg, kPairBlock, 0, st>>>(S->offset, S->col, val, perm, \
+                                                              S->perm_bytes, xf, yf, n, ns, g)
+  switch (G) {
+    case 2: PKS_SP(2); break;
+    case 3: PKS_SP(3); break;
+    case 4: PKS_SP(4); break;
+    case 5: PKS_SP(5); break;
+    case 6: PKS_SP(6); break;
+    case 7: PKS_SP(7); break;
+    default: PKS_SP(8); break;
+  }
+#undef PKS_SP
+}
 
 // 16-bit words (spmv16.hip).
 int spmv16(const pksell_matrix *A, const float *x, float *y, int64_t k, hipStream_t st);
@@ -774,19 +827,14 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
   // slower paired)
   if (buf && S->dtype != PKSELL_F64 && pair_slices(S->n_slots, S->n_slices)) {
     const int64_t pg = cdiv(cdiv(S->n_slices, 2), kPairBlock / kWave);
-#define PKS_SELL2(IMPL, VT)                                                                    \
-  k_sell_pair<float, IMPL, VT><<<pg, kPairBlock, 0, st>>>(                                     \
-      S->offset, S->col, static_cast<const VT *>(S->val), perm, S->perm_bytes,                 \
-      static_cast<const float *>(x), static_cast<float *>(y), (uint32_t)S->n,                  \
-      (uint32_t)S->n_slices, make_geo(S->sigma, 0, S->C))
+    const int G = pair_group(S->n_slots, S->n_slices);
     if (S->dtype == PKSELL_F16) {
-      if (perm) PKS_SELL2(true, _Float16);
-      else PKS_SELL2(false, _Float16);
+      if (perm) launch_sell_pair<true, _Float16>(S, x, y, perm, G, pg, st);
+      else launch_sell_pair<false, _Float16>(S, x, y, perm, G, pg, st);
     } else {
-      if (perm) PKS_SELL2(true, float);
-      else PKS_SELL2(false, float);
+      if (perm) launch_sell_pair<true, float>(S, x, y, perm, G, pg, st);
+      else launch_sell_pair<false, float>(S, x, y, perm, G, pg, st);
     }
-#undef PKS_SELL2
   } else if (S->dtype == PKSELL_F16) {
     if (buf) PKS_SELL(float, true, true, _Float16);
     else if (S->C == kWave) PKS_SELL(float, true, false, _Float16);
