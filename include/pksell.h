@@ -319,6 +319,9 @@ typedef struct pksell_batch {
   int32_t units_per_wave, waves;  /* wave w takes units w, w + waves, ... */
   int32_t vec4;             /* k % 4 == 0 and 16-byte aligned blocks: 16-byte gathers */
   int32_t group;            /* lanes per row: L = 2..16 (forward, vec4, k >= 8), else 1 */
+  int32_t words_per_group;  /* k = 1 loop: words per group, from the batch's average
+                               slice width (4..8) */
+  int32_t reserved;
   void *items;
   void *unit_start;
 } pksell_batch;

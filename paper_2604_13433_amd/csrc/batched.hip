@@ -166,51 +166,51 @@ __device__ inline Unit unit_at(const Item *items, const uint32_t *unit_start, ui
   return x;
 }
 
-// Words j .. j+7 of lane l of the slice starting at word s (w is
+// Words j .. j+G-1 of lane l of the slice starting at word s (w is
 // wave-uniform; words past w are padding).  Nontemporal when one wave reads
 // each word (L = 1), plain when lane groups share them.  (Streamed buffer
 // loads, faster in the single-matrix kernels, made this pipelined loop 20 %
 // slower.)
-template <bool NT>
+template <bool NT, int G>
 __device__ inline void load_words(const Item &it, int64_t s, uint32_t l, uint32_t w, uint32_t j,
-                                  uint32_t (&p)[kUnroll]) {
+                                  uint32_t (&p)[G]) {
   const uint32_t *P = it.pack + s + l;
 #pragma unroll
-  for (int q = 0; q < kUnroll; ++q) {
+  for (int q = 0; q < G; ++q) {
     uint32_t v = 0u;
     if (j + q < w) v = load_word<NT>(P + (j + q) * kWave);
     p[q] = v;
   }
 }
 
-// Decode eight words and accumulate; flag-0 words gather at ``oob`` (past
+// Decode G words and accumulate; flag-0 words gather at ``oob`` (past
 // the resource: 0, no memory request).
-template <int FMT, int L, int NA>
-__device__ inline void fma_words(const uint32_t (&p)[kUnroll], uint32_t &c, const Codec &cd,
+template <int FMT, int L, int NA, int G>
+__device__ inline void fma_words(const uint32_t (&p)[G], uint32_t &c, const Codec &cd,
                                  __amdgpu_buffer_rsrc_t rx, uint32_t kx, uint32_t xq,
                                  uint32_t oob, float (&acc)[NA]) {
-  uint32_t cq[kUnroll];
-  float v[kUnroll];
+  uint32_t cq[G];
+  float v[G];
 #pragma unroll
-  for (int q = 0; q < kUnroll; ++q) {
+  for (int q = 0; q < G; ++q) {
     const Unpacked u = unpack(p[q], cd);
     c += u.delta;
     cq[q] = c;
     v[q] = decode_value<FMT>(u.vbits);
   }
   if constexpr (L == 1) {
-    float xv[kUnroll];
+    float xv[G];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) xv[q] = buffer_load_f32(rx, (p[q] & 1u) ? cq[q] << 2 : oob);
+    for (int q = 0; q < G; ++q) xv[q] = buffer_load_f32(rx, (p[q] & 1u) ? cq[q] << 2 : oob);
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) acc[0] = fmaf(v[q], xv[q], acc[0]);
+    for (int q = 0; q < G; ++q) acc[0] = fmaf(v[q], xv[q], acc[0]);
   } else {
-    f32x4 xv[kUnroll];
+    f32x4 xv[G];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q)
+    for (int q = 0; q < G; ++q)
       xv[q] = buffer_load_f32x4(rx, (p[q] & 1u) ? cq[q] * kx + xq : oob);
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
+    for (int q = 0; q < G; ++q) {
       acc[0] = fmaf(v[q], xv[q].x, acc[0]);
       acc[1] = fmaf(v[q], xv[q].y, acc[1]);
       acc[2] = fmaf(v[q], xv[q].z, acc[2]);
@@ -219,7 +219,7 @@ __device__ inline void fma_words(const uint32_t (&p)[kUnroll], uint32_t &c, cons
   }
 }
 
-template <int FMT, int L>
+template <int FMT, int L, int G = kUnroll>
 __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ items,
                                                     const uint32_t *__restrict__ unit_start,
                                                     uint32_t count, uint32_t total, int k) {
@@ -233,17 +233,17 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
   const uint32_t k4 = (uint32_t)k >> 2, kx = (uint32_t)k * 4u;
   Unit cur = unit_at<L>(items, unit_start, find_item(unit_start, count, u), u, lane, k4);
   constexpr bool NT = L == 1;
-  uint32_t p[kUnroll];
-  load_words<NT>(items[cur.item], cur.s, cur.l, cur.w, 0, p);
+  uint32_t p[G];
+  load_words<NT, G>(items[cur.item], cur.s, cur.l, cur.w, 0, p);
   for (;;) {
     const bool more = u + stride < total;
     Unit nx;
-    uint32_t pn[kUnroll];
+    uint32_t pn[G];
     if (more) {  // the next unit's bounds and first words, before this unit's gathers
       uint32_t itn = cur.item;
       while (u + stride >= unit_start[itn + 1]) ++itn;
       nx = unit_at<L>(items, unit_start, itn, u + stride, lane, k4);
-      load_words<NT>(items[itn], nx.s, nx.l, nx.w, 0, pn);
+      load_words<NT, G>(items[itn], nx.s, nx.l, nx.w, 0, pn);
     }
     const Item &I = items[cur.item];
     const uint32_t t = cur.ks * kWave + cur.l;
@@ -254,11 +254,11 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
 #pragma unroll
     for (int r = 0; r < NA; ++r) acc[r] = 0.0f;
     const uint32_t oob = I.m * kx;
-    fma_words<FMT, L, NA>(p, c, I.cd, rx, kx, xq, oob, acc);
-    for (uint32_t j = kUnroll; j < cur.w; j += kUnroll) {  // slices wider than one group
-      uint32_t pr[kUnroll];
-      load_words<NT>(I, cur.s, cur.l, cur.w, j, pr);
-      fma_words<FMT, L, NA>(pr, c, I.cd, rx, kx, xq, oob, acc);
+    fma_words<FMT, L, NA, G>(p, c, I.cd, rx, kx, xq, oob, acc);
+    for (uint32_t j = G; j < cur.w; j += G) {  // slices wider than one group
+      uint32_t pr[G];
+      load_words<NT, G>(I, cur.s, cur.l, cur.w, j, pr);
+      fma_words<FMT, L, NA, G>(pr, c, I.cd, rx, kx, xq, oob, acc);
     }
     if (t < I.n && cur.live) {
       if constexpr (FMT == PKSELL_FIX) {
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
     if (!more) break;
     cur = nx;
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) p[q] = pn[q];
+    for (int q = 0; q < G; ++q) p[q] = pn[q];
     u += stride;
   }
 }
@@ -285,9 +285,16 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
 typedef void (*PipeKernel)(const Item *, const uint32_t *, uint32_t, uint32_t, int);
 
 template <int FMT>
-PipeKernel k_batched_pipe_for(int L) {
+PipeKernel k_batched_pipe_for(int L, int G) {
   switch (L) {
-    case 1: return k_batched_pipe<FMT, 1>;
+    case 1:
+      switch (G) {
+        case 4: return k_batched_pipe<FMT, 1, 4>;
+        case 5: return k_batched_pipe<FMT, 1, 5>;
+        case 6: return k_batched_pipe<FMT, 1, 6>;
+        case 7: return k_batched_pipe<FMT, 1, 7>;
+        default: return k_batched_pipe<FMT, 1, 8>;
+      }
     case 2: return k_batched_pipe<FMT, 2>;
     case 4: return k_batched_pipe<FMT, 4>;
     case 8: return k_batched_pipe<FMT, 8>;
@@ -303,9 +310,9 @@ bool uses_pipe(const pksell_batch &p) { return !p.transpose && (p.k == 1 || p.gr
 int resident_blocks(const pksell_batch &p) {
   const void *fn = nullptr;
   if (uses_pipe(p)) {
-    fn = p.fmt == PKSELL_FP16   ? (const void *)k_batched_pipe_for<PKSELL_FP16>(p.group)
-         : p.fmt == PKSELL_E8MY ? (const void *)k_batched_pipe_for<PKSELL_E8MY>(p.group)
-                                : (const void *)k_batched_pipe_for<PKSELL_FIX>(p.group);
+    fn = p.fmt == PKSELL_FP16   ? (const void *)k_batched_pipe_for<PKSELL_FP16>(p.group, p.words_per_group)
+         : p.fmt == PKSELL_E8MY ? (const void *)k_batched_pipe_for<PKSELL_E8MY>(p.group, p.words_per_group)
+                                : (const void *)k_batched_pipe_for<PKSELL_FIX>(p.group, p.words_per_group);
   } else {
     fn = (const void *)k_batched<PKSELL_E8MY, 8, false, false>;  // the largest pass kernel
   }
@@ -358,6 +365,7 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
     aligned &= ((reinterpret_cast<uintptr_t>(items[i].in) |
                  reinterpret_cast<uintptr_t>(items[i].out)) & 15) == 0;
   const int L = (aligned && !transpose && k >= 8) ? group_size(k) : 1;  // lanes per row
+  int64_t all_words = 0, all_slices = 0;
   for (int32_t i = 0; i < count; ++i) {
     const pksell_matrix *A = items[i].A;
     PKS_CHECK(A, PKSELL_EINVAL, "item %d: null matrix", i);
@@ -385,6 +393,8 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
     h.perm_bytes = (uint32_t)A->perm_bytes;
     h.geo = make_geo(A->sigma, A->k_left, A->C);
     h.cd = make_codec(A->D);
+    all_words += A->n_words;
+    all_slices += A->n_slices;
     const int64_t next = (int64_t)start[(size_t)i] + A->n_slices * L;
     PKS_CHECK(next < (int64_t(1) << 32), PKSELL_ERANGE, "too many work units");
     start[(size_t)i + 1] = (uint32_t)next;
@@ -408,6 +418,10 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
   plan->transpose = transpose ? 1 : 0;
   plan->vec4 = aligned ? 1 : 0;
   plan->group = L;
+  // k = 1: the batch's average words per lane spread evenly over the fewest
+  // groups of at most 8 (at least 4); lane groups keep 8
+  const int64_t wl = std::max<int64_t>(1, cdiv(all_words, (int64_t)kWave * std::max<int64_t>(1, all_slices)));
+  plan->words_per_group = L == 1 ? (int32_t)std::max<int64_t>(4, cdiv(wl, cdiv(wl, 8))) : kUnroll;
   plan->total_units = start[(size_t)count];
   // a chip-filling grid: as many workgroups as fit on every CU at once
   const int64_t max_waves = (int64_t)cus * resident_blocks(*plan) * (kB / kWave);
@@ -439,9 +453,9 @@ int pksell_spmv_batched(const pksell_batch *plan, void *stream) {
     PKS_CHECK(plan->group == 1 || (v4 && k >= 8 && plan->group == group_size(k)), PKSELL_EINVAL,
               "bad plan");
     switch (plan->fmt) {
-      case PKSELL_FP16: k_batched_pipe_for<PKSELL_FP16>(plan->group)<<<grid, kB, 0, st>>>(items, start, cnt, tot, k); break;
-      case PKSELL_E8MY: k_batched_pipe_for<PKSELL_E8MY>(plan->group)<<<grid, kB, 0, st>>>(items, start, cnt, tot, k); break;
-      default: k_batched_pipe_for<PKSELL_FIX>(plan->group)<<<grid, kB, 0, st>>>(items, start, cnt, tot, k); break;
+      case PKSELL_FP16: k_batched_pipe_for<PKSELL_FP16>(plan->group, plan->words_per_group)<<<grid, kB, 0, st>>>(items, start, cnt, tot, k); break;
+      case PKSELL_E8MY: k_batched_pipe_for<PKSELL_E8MY>(plan->group, plan->words_per_group)<<<grid, kB, 0, st>>>(items, start, cnt, tot, k); break;
+      default: k_batched_pipe_for<PKSELL_FIX>(plan->group, plan->words_per_group)<<<grid, kB, 0, st>>>(items, start, cnt, tot, k); break;
     }
     PKS_LAUNCHED();
     return PKSELL_OK;

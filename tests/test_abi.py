@@ -170,3 +170,37 @@ def test_encode_query_16_bit_words():
         for D in (lo - 1, hi + 1):
             assert _query(fmt=fmt, D=D, C=64)[0] == B.EINVAL
         assert _query(fmt=fmt, D=lo, C=32)[0] == B.EINVAL
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes struct of the binding has the C struct's size and field
+    offsets, read from a program compiled against include/pksell.h (a
+    mismatch would hand the library shifted pointers)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"pksell_matrix": B.CMatrix, "pksell_sell": B.CSell, "pksell_batch": B.CBatch,
+               "pksell_batch_item": B.CBatchItem, "pksell_pcg_info": B.CPcgInfo}
+    rename = {"inp": "in"}  # a Python keyword in the binding
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pksell.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            cf = rename.get(f, f)
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", HEADER_DIR, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in filter(None, out):
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
