@@ -329,7 +329,7 @@ __global__ void k_fill_zero(T *p, int64_t len) {
 // kernel.  Values are VT (T, or half with T = float), vectors and sums T.
 // BUF (C = 64 and arrays below 4 GiB): columns and values are streamed
 // through per-slice buffer resources, as the PackSELL words are.
-template <typename T, bool CWAVE, bool BUF = false, typename VT = T>
+template <typename T, bool CWAVE, bool BUF = false, typename VT = T, int G = kUnroll>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict__ offset,
                                                       const int32_t *__restrict__ scol,
                                                       const VT *__restrict__ sval, const void *perm,
@@ -348,11 +348,11 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
   const __amdgpu_buffer_rsrc_t rc = BUF ? make_rsrc(scol + ln.s, w * 256u) : make_rsrc(scol, 0u);
   const __amdgpu_buffer_rsrc_t rv =
       BUF ? make_rsrc(sval + ln.s, w * kWave * (uint32_t)sizeof(VT)) : make_rsrc(sval, 0u);
-  for (uint32_t j = 0; j < w; j += kUnroll) {
-    int32_t cc[kUnroll];
-    T vv[kUnroll];
+  for (uint32_t j = 0; j < w; j += G) {
+    int32_t cc[G];
+    T vv[G];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
+    for (int q = 0; q < G; ++q) {
       const bool in = j + q < w;
       if constexpr (BUF) {
         cc[q] = in ? stream_elem<int32_t>(rc, ln.l, j + q) : 0;
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
       }
     }
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q)
+    for (int q = 0; q < G; ++q)
       if (j + q < w) acc += vv[q] * x[cc[q]];
   }
   if (t >= n) return;
@@ -456,7 +456,7 @@ struct Spmv64Args {
 // float64, gathers of x in float64 (flag-0 words past the resource), float64
 // FMA in word order.  BUF (C = 64, words below 4 GiB): words streamed
 // through a buffer resource on the slice, as in the 32-bit kernels.
-template <bool CWAVE, bool BUF>
+template <bool CWAVE, bool BUF, int G = kUnroll>
 __global__ __launch_bounds__(kBlock) void k_spmv64(Spmv64Args a) {
   Lane ln;
   if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
@@ -468,10 +468,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv64(Spmv64Args a) {
   const uint64_t *P = a.pack + ln.s + ln.l;
   uint32_t c = left_offset32(t, a.geo);
   double acc = 0.0;
-  for (uint32_t j = 0; j < w; j += kUnroll) {
-    uint64_t p[kUnroll];
+  for (uint32_t j = 0; j < w; j += G) {
+    uint64_t p[G];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
+    for (int q = 0; q < G; ++q) {
       uint64_t v = 0ull;
       if (j + q < w) {
         if constexpr (BUF)
@@ -482,22 +482,22 @@ __global__ __launch_bounds__(kBlock) void k_spmv64(Spmv64Args a) {
       }
       p[q] = v;
     }
-    uint32_t off[kUnroll];
-    double val[kUnroll];
+    uint32_t off[G];
+    double val[G];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
+    for (int q = 0; q < G; ++q) {
       const uint32_t lo = (uint32_t)p[q];
       const bool flag = lo & 1u;
       c += flag ? ((lo >> 1) & a.dmask) : (uint32_t)(p[q] >> 1);
       off[q] = flag ? c * 8u : a.m * 8u;
       val[q] = flag ? __builtin_bit_cast(double, p[q] & a.vmask) : 0.0;
     }
-    double xv[kUnroll];
+    double xv[G];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q)
+    for (int q = 0; q < G; ++q)
       xv[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, off[q], 0, 0));
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) acc = fma(val[q], xv[q], acc);
+    for (int q = 0; q < G; ++q) acc = fma(val[q], xv[q], acc);
   }
   if (t >= a.n) return;
   a.y[dst.row()] = acc;
@@ -549,6 +549,22 @@ int check_matrix(const pksell_matrix *A) {
 inline bool pair_slices(int64_t words, int64_t n_slices) {
   return n_slices > 0 && words <= 16 * (int64_t)kWave * n_slices;
 }
+
+// The same rule for the one-slice-per-wave kernels, at least 4 words.
+inline int slice_group(int64_t words, int64_t n_slices) {
+  return std::max(4, pair_group(words, n_slices));
+}
+
+// Runs the launch statement given after G (which names the group size GG)
+// with GG = G in [4, 8].
+#define PKS_GROUP(G, ...)                                  \
+  switch (G) {                                             \
+    case 4: { constexpr int GG = 4; __VA_ARGS__; } break;  \
+    case 5: { constexpr int GG = 5; __VA_ARGS__; } break;  \
+    case 6: { constexpr int GG = 6; __VA_ARGS__; } break;  \
+    case 7: { constexpr int GG = 7; __VA_ARGS__; } break;  \
+    default: { constexpr int GG = 8; __VA_ARGS__; } break; \
+  }
 
 template <int FMT, bool IMPL>
 void launch_pair(const SpmvArgs &a, int G, int64_t pg, hipStream_t st) {
@@ -776,8 +792,10 @@ int pksell_spmv_f64(const pksell_matrix *A, const double *x, double *y, void *st
   a.vmask = ~((2ull << A->D) - 1ull);
   const int64_t grid = cdiv(A->n_slices * A->C, kBlock);
   const bool buf = A->C == kWave && A->n_words < (int64_t(1) << 29);
-  if (buf) k_spmv64<true, true><<<grid, kBlock, 0, st>>>(a);
-  else if (A->C == kWave) k_spmv64<true, false><<<grid, kBlock, 0, st>>>(a);
+  if (buf) {
+    PKS_GROUP(slice_group(A->n_words, A->n_slices),
+              k_spmv64<true, true, GG><<<grid, kBlock, 0, st>>>(a));
+  } else if (A->C == kWave) k_spmv64<true, false><<<grid, kBlock, 0, st>>>(a);
   else k_spmv64<false, false><<<grid, kBlock, 0, st>>>(a);
   PKS_LAUNCHED();
   return PKSELL_OK;
@@ -844,8 +862,13 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
     else if (S->C == kWave) PKS_SELL(float, true, false, float);
     else PKS_SELL(float, false, false, float);
   } else {
-    if (buf) PKS_SELL(double, true, true, double);
-    else if (S->C == kWave) PKS_SELL(double, true, false, double);
+    if (buf) {
+      PKS_GROUP(slice_group(S->n_slots, S->n_slices),
+                k_sell_spmv<double, true, true, double, GG><<<grid, kBlock, 0, st>>>(
+                    S->offset, S->col, static_cast<const double *>(S->val), perm, S->perm_bytes,
+                    static_cast<const double *>(x), static_cast<double *>(y), (uint32_t)S->n,
+                    (uint32_t)S->n_slices, S->C, make_geo(S->sigma, 0, S->C)));
+    } else if (S->C == kWave) PKS_SELL(double, true, false, double);
     else PKS_SELL(double, false, false, double);
   }
 #undef PKS_SELL
