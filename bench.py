@@ -643,6 +643,15 @@ def pcg_leg(args, torch, B, W):
     r["speedup_vs_fp64_cg"] = round(res["fp64_cg"]["ms"] / r["ms"], 3)
     res["iocg_e8m8_min20_words64_outer"] = r
     log(f"[bench] IO-CG E8M8 m_in=20, 64-bit-word outer: {r}")
+    # 16-bit-word inner operators: fewer bytes, coarser values, more restarts
+    for fmt, D, label in (("e5my", 4, "iocg_w16_e5m5_min20"), ("fix16", 7, "iocg_w16_int8_min20")):
+        lo16 = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 256, B.IMPLICIT, dev)
+        r = run_with(hi, lo16, 20, run_fn=B.pcg, b=b)
+        r["speedup_vs_fp64_cg"] = round(res["fp64_cg"]["ms"] / r["ms"], 3)
+        r["words_per_row"] = round(lo16.n_words / a.n, 2)
+        res[label] = r
+        log(f"[bench] IO-CG {label}: {r}")
+        del lo16
     return res
 
 

@@ -57,7 +57,8 @@ extern "C" {
  * 1..D and 15 - D value bits; a dummy carries at most 2^15 - 1, so a larger
  * delta takes a chain of dummies (all but the last carrying 2^15 - 1)
  * before its value word.  C must be 64.  Products through pksell_spmv with
- * k = 1 only; every other entry point rejects these formats. */
+ * k = 1, and the solvers' inner operator (pksell_pcg, pksell_pcg64); every
+ * other entry point rejects these formats. */
 #define PKSELL_E5MY 4  /* binary16-compatible float, Y = 9 - D mantissa bits
                           (the E8MY construction applied to binary16; D = 7 is
                           8-bit E5M2); 1 <= D <= 8 */
@@ -357,7 +358,8 @@ int pksell_pcg_workspace(const pksell_matrix *A_lo, const pksell_sell *A_hi,
  *  - A_lo != NULL: the inner-outer CG of sec. 5.2.2.  Outer iterations are
  *    flexible CG (one previous direction kept) in float64 on A_hi; each is
  *    preconditioned by m_in float32 CG iterations on A_lo, the PackSELL
- *    encoding of the same matrix (implicit row order), started from zero on
+ *    encoding of the same matrix (implicit row order; FP16, E8MY or FIX
+ *    words, or 16-bit E5MY or FIX16 words with C = 64), started from zero on
  *    the right-hand side r / ||r||.  Inner dot products, alpha and beta are
  *    accumulated in float64.  max_outer bounds outer iterations.
  *  - A_lo == NULL: plain float64 CG on A_hi (the baseline); max_outer bounds

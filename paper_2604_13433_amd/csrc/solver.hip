@@ -403,6 +403,117 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
   put_partials<1, kPairB>(vv, pq_out);
 }
 
+// (A) for 16-bit words (E5MY, FIX16; C = 64): the step of k_inner_a2 with
+// every 32-bit slot holding two consecutive words of a row (low half
+// first), G slots (2G words) per group, the first slots requested before
+// the previous partials are summed.  Same grid and partial layout as
+// k_inner_a2 (two slices per wave, 128-thread workgroups).
+template <int FMT, int G>
+__global__ __launch_bounds__(kPairB) void k_inner16(PackView A, const float *__restrict__ r,
+                                                   const float *__restrict__ p_old,
+                                                   float *__restrict__ p_new,
+                                                   float *__restrict__ q, State *st,
+                                                   Parts rr_in, Parts pq_out) {
+  constexpr int S = 2;
+  const bool stop = outer_stopped(st) || st->inner_stop;
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(b * (kPairB / kWave) + threadIdx.x / kWave);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t k0 = wave * S;
+  int64_t off[S + 1];
+  uint32_t w[S], p[S][G];  // w: slots per lane
+  __amdgpu_buffer_rsrc_t rs[S];
+#pragma unroll
+  for (int i = 0; i <= S; ++i) off[i] = A.offset[min(k0 + i, A.n_slices)];
+  RowOut ro[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+    ro[i] = row_out<FMT>(A.perm, A.perm_bytes, A.row_exp, stop ? A.n : (k0 + i) * kWave + lane,
+                         A.n, A.geo);
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    w[i] = stop ? 0u : (uint32_t)((off[i + 1] - off[i]) >> 7);
+    rs[i] = slice_words(A.pack + (off[i] >> 1), w[i]);
+#pragma unroll
+    for (int u = 0; u < G; ++u) p[i][u] = u < (int)w[i] ? stream_word(rs[i], lane, u) : 0u;
+  }
+  const bool first = st->in_first;
+  double rr[1] = {0.0};
+  if (!stop) get_totals<1, kPairB>(rr_in, rr);
+  const double beta_d = first ? 0.0 : rr[0] / st->in_rr_used;
+  const bool quit = !stop && !(rr[0] > 0.0 && isfinite(beta_d));  // inner residual vanished
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->in_step_ok = !(stop || quit);
+    if (quit) st->inner_stop = 1;
+    st->in_rr_cur = rr[0];
+    st->in_beta = beta_d;
+  }
+  if (stop || quit) return;
+  const float beta = (float)beta_d;
+  const __amdgpu_buffer_rsrc_t rr_r = make_rsrc(r, A.n * 4u);
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(p_old, A.n * 4u);
+  const uint32_t oob = A.n * 4u;  // flag-0 words: past the resources, no request
+  const uint32_t dmask = A.cd.dmask, vmask = A.cd.vmask & 0xFFFFu;
+  uint32_t c[S];
+  float acc[S];
+  uint32_t wm = 0;
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    c[i] = left_offset32((k0 + i) * kWave + lane, A.geo);
+    acc[i] = 0.0f;
+    wm = max(wm, w[i]);
+  }
+  for (uint32_t j = 0; j < wm; j += G) {
+    if (j > 0) {
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int u = 0; u < G; ++u) p[i][u] = j + u < w[i] ? stream_word(rs[i], lane, j + u) : 0u;
+    }
+    uint32_t o[S][2 * G];
+    float v[S][2 * G];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int h = 0; h < 2 * G; ++h) {
+        const uint32_t wd = (h & 1) ? p[i][h >> 1] >> 16 : p[i][h >> 1] & 0xFFFFu;
+        const bool flag = wd & 1u;
+        c[i] += flag ? (wd >> 1) & dmask : (wd >> 1);
+        o[i][h] = flag ? c[i] << 2 : oob;
+        const uint32_t bits = flag ? wd & vmask : 0u;
+        if constexpr (FMT == PKSELL_E5MY)
+          v[i][h] = __half2float(__ushort_as_half((unsigned short)bits));
+        else
+          v[i][h] = (float)(int32_t)(int16_t)(uint16_t)bits;  // FIX16: q * 2^(D+1)
+      }
+    float xv[S][2 * G];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int h = 0; h < 2 * G; ++h)
+        xv[i][h] = fmaf(beta, buffer_load_f32(rp, o[i][h]), buffer_load_f32(rr_r, o[i][h]));
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int h = 0; h < 2 * G; ++h) acc[i] = fmaf(v[i][h], xv[i][h], acc[i]);
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    const uint32_t t = (k0 + i) * kWave + lane;
+    if (k0 + i >= A.n_slices || t >= A.n) continue;
+    float qi = acc[i];
+    if constexpr (FMT == PKSELL_FIX16) qi = ldexpf(qi, ro[i].shift(A.cd));
+    const uint32_t row = ro[i].row();
+    const float pn = fmaf(beta, p_old[row], r[row]);
+    p_new[row] = pn;
+    q[row] = qi;
+    part += (double)pn * (double)qi;
+  }
+  double vv[1] = {part};
+  put_partials<1, kPairB>(vv, pq_out);
+}
+
 // (B) float32 inner update: alpha = rr / pq; z += alpha p, r -= alpha q;
 // partials of the new r.r.
 __global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ z,
@@ -865,6 +976,7 @@ struct Solve {
   uint32_t gs, gp;  // grids of the SELL and PackSELL product kernels
   bool stream_ok;   // the inner words are addressable by 32-bit byte offsets
   int g_in;         // inner product: words per group (4..8)
+  int g16;          // 16-bit inner words: slots per group (2..4)
 
   Parts pa_for(uint32_t grid) const { return {w.pa.p, grid}; }
   Parts vec(const Parts &p) const { return {p.p, vb}; }
@@ -927,6 +1039,19 @@ struct Solve {
       k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
   }
 
+  // 16-bit inner words (C = 64): g16 slots per group.
+  template <int FMT>
+  void inner16(const PackView &A, const float *po, float *pn, Parts rr_in, Parts pq_out) {
+#define PKS_I16(GG) \
+  k_inner16<FMT, GG><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out)
+    switch (g16) {
+      case 2: PKS_I16(2); break;
+      case 3: PKS_I16(3); break;
+      default: PKS_I16(4); break;
+    }
+#undef PKS_I16
+  }
+
   // Enqueues one flexible-CG outer iteration with m_in inner iterations.
   int outer_iteration(int m_in) {
     const SellView &S = hv;
@@ -943,6 +1068,8 @@ struct Solve {
       switch (lo->fmt) {
         case PKSELL_FP16: cw ? inner_a<PKSELL_FP16, true>(A, po, pn, rr_in, ppq) : inner_a<PKSELL_FP16, false>(A, po, pn, rr_in, ppq); break;
         case PKSELL_E8MY: cw ? inner_a<PKSELL_E8MY, true>(A, po, pn, rr_in, ppq) : inner_a<PKSELL_E8MY, false>(A, po, pn, rr_in, ppq); break;
+        case PKSELL_E5MY: inner16<PKSELL_E5MY>(A, po, pn, rr_in, ppq); break;
+        case PKSELL_FIX16: inner16<PKSELL_FIX16>(A, po, pn, rr_in, ppq); break;
         default: cw ? inner_a<PKSELL_FIX, true>(A, po, pn, rr_in, ppq) : inner_a<PKSELL_FIX, false>(A, po, pn, rr_in, ppq); break;
       }
       PKS_LAUNCHED();
@@ -1090,9 +1217,12 @@ int run_pcg(const pksell_matrix *A_lo, const SellView &hv, int64_t n, const doub
     PKS_CHECK(A_lo->n == n && A_lo->m == n, PKSELL_EINVAL, "shape mismatch");
     PKS_CHECK(A_lo->perm_mode == PKSELL_IMPLICIT && A_lo->perm && A_lo->pack && A_lo->offset,
               PKSELL_EINVAL, "inner PackSELL matrix must be implicit with arrays set");
-    PKS_CHECK(A_lo->fmt >= PKSELL_FP16 && A_lo->fmt <= PKSELL_FIX, PKSELL_EINVAL,
-              "the inner matrix takes FP16, E8MY or FIX words");
-    PKS_CHECK(A_lo->fmt != PKSELL_FIX || A_lo->row_exp, PKSELL_EINVAL, "FIX needs row_exp");
+    PKS_CHECK((A_lo->fmt >= PKSELL_FP16 && A_lo->fmt <= PKSELL_FIX) || is_w16(A_lo->fmt),
+              PKSELL_EINVAL, "the inner matrix takes FP16, E8MY, FIX, E5MY or FIX16 words");
+    PKS_CHECK((A_lo->fmt != PKSELL_FIX && A_lo->fmt != PKSELL_FIX16) || A_lo->row_exp,
+              PKSELL_EINVAL, "FIX needs row_exp");
+    PKS_CHECK(!is_w16(A_lo->fmt) || (A_lo->C == kWave && A_lo->n_words < (int64_t(1) << 31)),
+              PKSELL_EINVAL, "16-bit inner words need C = 64 and fewer than 2^31 words");
     PKS_CHECK(m_in >= 1 && m_in <= 10000, PKSELL_EINVAL, "m_in must be in [1, 10000]");
   }
   PKS_CHECK(tol > 0.0 && max_outer >= 1, PKSELL_EINVAL, "tol must be > 0, max_outer >= 1");
@@ -1107,6 +1237,12 @@ int run_pcg(const pksell_matrix *A_lo, const SellView &hv, int64_t n, const doub
   sv.gp = A_lo ? (uint32_t)cdiv(A_lo->n_slices * A_lo->C, kB) : 0u;
   sv.stream_ok = A_lo && A_lo->n_words < (int64_t(1) << 30);
   sv.g_in = A_lo ? group_for(A_lo->n_words, A_lo->n_slices * A_lo->C) : 8;
+  sv.g16 = 4;
+  if (A_lo && is_w16(A_lo->fmt) && A_lo->n_slices > 0) {
+    // slots per lane spread evenly over the fewest groups of at most 4
+    const int64_t ws = std::max<int64_t>(1, cdiv(A_lo->n_words / 2, (int64_t)kWave * A_lo->n_slices));
+    sv.g16 = (int)std::max<int64_t>(2, cdiv(ws, cdiv(ws, 4)));
+  }
   sv.w = carve_work(ws, n, max_blocks_of(hv, A_lo));
   PKS_CHECK(ws && ws_bytes >= sv.w.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes",
             sv.w.bytes);

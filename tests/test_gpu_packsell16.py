@@ -6,7 +6,8 @@ back into the paper's column-major 16-bit layout.  The words must then
 equal the 16-bit oracle's bit for bit, and the extra padding word must be
 zero.  Products must equal the oracle's float64 product on the same
 quantised values within 1e-6, normalised by ||A_q||_inf ||x||_inf.  Every
-other entry point, and k > 1, must reject these formats.
+other entry point except the solvers' inner operator, and k > 1, must
+reject these formats.
 """
 import numpy as np
 import pytest
@@ -152,7 +153,3 @@ def test_other_entry_points_reject_16_bit_words():
                  split_words=64)
     with pytest.raises(B.PackSELLError):
         B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e5my", 7, 32, 256, B.IMPLICIT, DEV)
-    hi = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float64, 64, 256, B.IMPLICIT, DEV)
-    with pytest.raises(B.PackSELLError):
-        B.pcg(A, hi, torch.ones(a.n, dtype=torch.float64, device=DEV), tol=1e-8, m_in=5,
-              max_outer=5)

@@ -145,3 +145,25 @@ def test_iocg_with_64_bit_outer_operator(inner):
     assert ref.converged
     assert np.max(np.abs(x - ref.x)) < 1e-7
     assert abs(info["outer_iterations"] - ref.iterations) <= max(2, ref.iterations // 3)
+
+
+@pytest.mark.parametrize("fmt,D", [("fix16", 7), ("fix16", 5), ("e5my", 4)])
+def test_iocg_with_16_bit_inner_operator(fmt, D):
+    """IO-CG with a 16-bit-word inner operator (int8 / int10 FIX16, E5M5):
+    the solution and the outer iteration count follow the oracle's IO-CG on
+    the same quantised inner values."""
+    from oracle import packsell16 as P16
+
+    a, b = system(20, 4)
+    lo, hi = operators(a, fmt, D)
+    x, info = B.pcg(lo, hi, torch.from_numpy(b).to(DEV), tol=1e-10, m_in=20, max_outer=500)
+    x = x.cpu().numpy()
+    assert info["rel_residual"] < 1e-10
+    true = np.linalg.norm(b - L.spmv(a.rowptr, a.col, a.val, x)) / np.linalg.norm(b)
+    assert true < 1e-10
+    q_lo = P16.quantized(a.rowptr, a.val, a.n, {"fix16": P16.FMT_FIX16, "e5my": P16.FMT_E5MY}[fmt],
+                         D)
+    ref = L.iocg(a.rowptr, a.col, a.val, q_lo, b, m_in=20, tol=1e-10)
+    assert ref.converged
+    assert np.max(np.abs(x - ref.x)) < 1e-7
+    assert abs(info["outer_iterations"] - ref.iterations) <= max(2, ref.iterations // 3)
