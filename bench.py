@@ -373,7 +373,9 @@ def time_variant(args, torch, B, A, m, n, mk_y=None):
 def powerlaw_leg(args, torch, B, W):
     """Irregular power-law rows, n = 10^6 (mean 30, max 5000, RSD 4.3):
     PackSELL FP16 and E8M10 (D = 12) at sigma = 65536 against FP32 SELL,
-    with and without wide-slice splitting (J words per work unit)."""
+    with and without wide-slice splitting (J words per work unit), and the
+    CSR-packed words (no padding, no sort) with the product balanced over
+    chunks of J words."""
     dev = torch.device("cuda:0")
     t0 = time.time()
     a = W.m3_powerlaw()
@@ -382,14 +384,24 @@ def powerlaw_leg(args, torch, B, W):
     variants = [("packsell_fp16", "fp16", 15, 0), ("packsell_e8m10", "e8my", 12, 0)]
     variants += [(f"packsell_fp16_split{J}", "fp16", 15, J) for J in (128, 256, 512)]
     variants += [("packsell_e8m10_split256", "e8my", 12, 256)]
+    variants += [(f"packed_csr_fp16_chunk{J}", "fp16", 15, J) for J in (256, 512, 1024)]
+    variants += [("packed_csr_e8m10_chunk512", "e8my", 12, 512)]
     for name, fmt, D, J in variants:
-        A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 65536, B.EXPLICIT, dev,
-                     split_words=J)
+        csr = name.startswith("packed_csr")
+        if csr:
+            A = B.encode_packed_csr(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, J, dev)
+        else:
+            A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 65536, B.EXPLICIT, dev,
+                         split_words=J)
         ms, per, R = time_variant(args, torch, B, A, a.m, a.n)
         res[name] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
                      "GFLOP/s": round(2 * a.nnz / (ms * 1e-3) / 1e9, 1),
-                     "words_per_nnz": round(A.n_words / a.nnz, 3), "sigma": 65536}
-        if J:
+                     "words_per_nnz": round(A.n_words / a.nnz, 3)}
+        if csr:
+            res[name].update(chunk_words=J, chunks=A.n_units)
+        else:
+            res[name]["sigma"] = 65536
+        if J and not csr:
             res[name].update(split_words=J, units=A.n_units, split_units=A.n_split_units)
         log(f"[bench] powerlaw {name}: {res[name]}")
         del A

@@ -112,6 +112,27 @@ extern "C" {
  * and the fill phase writes units, splits and ckpt.  Products with k = 1 then
  * run one work unit per wave and add each split slice's chunk sums in chunk
  * order (deterministic); other calls ignore the split arrays.
+ *
+ * CSR-packed matrices (C = 1 and sigma = 1; 32-bit words).  With one-row
+ * slices and no sort, every row's words lie together in row order with no
+ * padding, and offset is a word row pointer: delta-value packing in a
+ * CSR-based layout, which the paper leaves to future work (sec. 6).  Set
+ * split_words = T (256, 512 or 1024) after pksell_encode_query to give
+ * pksell_spmv (k = 1) a product balanced over words: the word stream is
+ * cut into n_units = ceil(n_words / T) chunks of T words, one per wave,
+ * whatever rows they fall in.  The analyse phase sets n_units
+ * (n_split_units = n_split_slices = 0); the caller then allocates
+ *   units    uint32[n_units + 1]  first row whose words start at or after
+ *                                 word c*T (units[n_units] = n)
+ *   ckpt     uint32[n_units]      column reached before word c*T (the row's
+ *                                 eq. 4 left offset when a row starts there)
+ *   partial  float[3 * n_units]   scratch of pksell_spmv (one product at a
+ *                                 time per matrix): pieces of the rows that
+ *                                 cross chunk edges and those rows' indices
+ * and the fill phase writes units and ckpt.  pack must be 16-byte aligned
+ * for these products.  Rows crossing chunk edges are summed piece by piece
+ * in chunk order by a second kernel: results are deterministic.  Products
+ * with k > 1 and the other entry points ignore the plan.
  */
 typedef struct pksell_matrix {
   int64_t n, m, nnz;

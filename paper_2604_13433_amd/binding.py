@@ -214,6 +214,8 @@ class PackSELLMatrix:
             b += d.perm_bytes * d.n
         if d.fmt in (FIX, FIX16):
             b += 2 * d.n
+        if d.C == 1 and d.split_words > 0 and k == 1 and d.n_units > 0:
+            b += 12 * d.n_units + 4  # chunk plan read, each chunk's row marker written
         return int(b)
 
     def replicate(self):
@@ -282,7 +284,9 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
     holds n_words, n_dummies, k_left and the work-unit counts, and no words
     are written.  ``split_words`` = J > 0 (C = 64, a multiple of 8) splits
     slices wider than J words per lane into chunks of J words for the
-    single-vector product."""
+    single-vector product; with C = 1 and sigma = 1 (CSR-packed: every
+    row's words together, no padding) J = 256, 512 or 1024 cuts the word
+    stream into chunks of J words for a product balanced over words."""
     if isinstance(fmt, str):
         fmt = FMT_BY_NAME[fmt]
     device = torch.device(device)
@@ -320,6 +324,10 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
         t["pack"] = torch.empty(max(1, desc.n_words), dtype=torch.int32, device=device)
     if fmt in (FIX, FIX16):
         t["row_exp"] = torch.empty(max(1, n), dtype=torch.int16, device=device)
+    if desc.C == 1 and desc.split_words > 0 and desc.n_units > 0:  # CSR-packed chunk plan
+        t["units"] = torch.empty(desc.n_units + 1, dtype=torch.int32, device=device)
+        t["ckpt"] = torch.empty(desc.n_units, dtype=torch.int32, device=device)
+        t["partial"] = torch.empty(3 * desc.n_units, dtype=torch.float32, device=device)
     if desc.n_split_units > 0:
         t["units"] = torch.empty(4 * desc.n_units, dtype=torch.int32, device=device)
         t["splits"] = torch.empty(4 * desc.n_split_slices, dtype=torch.int32, device=device)
@@ -329,6 +337,14 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
     _check(L.pksell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
                            _ptr(ws), ws_bytes.value, st))
     return A
+
+
+def encode_packed_csr(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15,
+                      chunk: int = 512, device="cuda") -> PackSELLMatrix:
+    """CSR-based delta-value packing: PackSELL words of each row stored
+    together in row order (one-row slices, no sort, no padding), with the
+    plan of a product balanced over chunks of ``chunk`` words."""
+    return encode(rowptr, col, val, n, m, fmt, D, 1, 1, EXPLICIT, device, split_words=chunk)
 
 
 class StreamRead:

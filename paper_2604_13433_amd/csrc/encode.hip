@@ -300,7 +300,8 @@ __global__ void k_fill_packsell(const int64_t *__restrict__ rowptr, const int32_
                                 const int32_t *__restrict__ stored_rows,
                                 const int64_t *__restrict__ offset, uint32_t *__restrict__ pack,
                                 int16_t *__restrict__ row_exp, int32_t J,
-                                const int64_t *__restrict__ ucnt, uint32_t *__restrict__ ckpt) {
+                                const int64_t *__restrict__ ucnt, uint32_t *__restrict__ ckpt,
+                                int64_t T, uint32_t *__restrict__ anchor) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_slices * C) return;
   int64_t k = i / C, l = i - k * C;
@@ -313,8 +314,11 @@ __global__ void k_fill_packsell(const int64_t *__restrict__ rowptr, const int32_
   uint32_t *ck = nullptr;
   if (J > 0 && w > J) ck = ckpt + (uint64_t)(((uint64_t)ucnt[k]) >> 32) * kWave + l;
   uint32_t run = left_offset(i < n ? stored_rows[i] : i, sigma, k_left);
+  // CSR-packed chunks (C = 1, T > 0): the column reached before every word
+  // position that starts a chunk of T words.
   auto put = [&](uint32_t word, uint32_t col_after) {
     if (ck && j % J == 0) ck[(j / J) * kWave] = run;
+    if (anchor && (s + j) % T == 0) anchor[(s + j) / T] = run;
     out[j * C] = word;
     run = col_after;
     ++j;
@@ -478,6 +482,27 @@ __global__ void k_fill_sell(const int64_t *__restrict__ rowptr, const int32_t *_
     scol[s + j * C + l] = last;
     sval[s + j * C + l] = (OT)0;
   }
+}
+
+// Chunk plan of a CSR-packed matrix: lo[c] = the first row whose words start
+// at or after word c*T (offsets ascend; offset[n] = n_words > c*T for every
+// chunk), lo[n_chunks] = n.
+__global__ void k_csr_lo(const int64_t *__restrict__ offset, int64_t n, int64_t n_chunks,
+                         int64_t T, uint32_t *__restrict__ lo) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > n_chunks) return;
+  if (c == n_chunks) {
+    lo[c] = (uint32_t)n;
+    return;
+  }
+  const int64_t p = c * T;
+  int64_t a = 0, b = n;
+  while (a < b) {
+    const int64_t mid = (a + b) / 2;
+    if (offset[mid] < p) a = mid + 1;
+    else b = mid;
+  }
+  lo[c] = (uint32_t)a;
 }
 
 // ---- shared host driver ------------------------------------------------------
@@ -663,21 +688,34 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val, in
   PKS_CHECK(ws && ws_bytes >= p.bytes, PKSELL_EWORKSPACE, "workspace: need %zu bytes", p.bytes);
   PKS_CHECK(A->split_words == 0 || (A->fmt != PKSELL_E11MY && !is_w16(A->fmt)), PKSELL_EINVAL,
             "split_words: 32-bit words only");
-  PKS_CHECK(A->split_words == 0 || (A->C == kWave && A->split_words % 8 == 0 &&
-                                    A->split_words >= 8 && A->split_words <= (1 << 24)),
-            PKSELL_EINVAL, "split_words must be 0 or a multiple of 8 in [8, 2^24], with C = 64");
+  const bool chunked = A->C == 1 && A->split_words > 0;
+  PKS_CHECK(A->split_words == 0 ||
+                (A->C == kWave && A->split_words % 8 == 0 && A->split_words >= 8 &&
+                 A->split_words <= (1 << 24)) ||
+                (chunked && A->sigma == 1 &&
+                 (A->split_words == 256 || A->split_words == 512 || A->split_words == 1024)),
+            PKSELL_EINVAL,
+            "split_words must be 0, a multiple of 8 in [8, 2^24] with C = 64, or 256, 512 "
+            "or 1024 with C = 1 and sigma = 1");
   hipStream_t st = as_stream(stream);
   if (A->pack == nullptr) {
     EncInfo h{};
     const bool fix = A->fmt == PKSELL_FIX || A->fmt == PKSELL_FIX16;
     int rc = analyse(rowptr, col, fix ? val : nullptr, val_dtype, A->n, A->m, A->nnz, A->C,
                      A->sigma, A->D, A->n_slices, A->offset, A->perm, A->perm_bytes,
-                     A->split_words, is_w16(A->fmt), p, st, &h);
+                     chunked ? 0 : A->split_words, is_w16(A->fmt), p, st, &h);
     if (rc) return rc;
     A->k_left = h.k_left;
     A->n_dummies = (int64_t)h.n_dummies;
     A->n_words = h.n_words;
     PKS_CHECK(A->n_words < (int64_t(1) << 40), PKSELL_ERANGE, "too many words");
+    if (chunked) {
+      A->n_units = cdiv(A->n_words, A->split_words);
+      A->n_split_units = 0;
+      A->n_split_slices = 0;
+      PKS_CHECK(A->n_units < (int64_t(1) << 31), PKSELL_ERANGE, "too many chunks");
+      return PKSELL_OK;
+    }
     A->n_units = (int64_t)(uint32_t)h.units;
     A->n_split_units = (int64_t)((uint64_t)h.units >> 32);
     A->n_split_slices = h.split_slices;
@@ -687,9 +725,16 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val, in
             "FIX needs row_exp");
   const int64_t rows = A->n_slices * A->C;
   if (rows == 0) return PKSELL_OK;
-  const bool split = A->split_words > 0 && A->n_split_units > 0;
+  const bool split = !chunked && A->split_words > 0 && A->n_split_units > 0;
   PKS_CHECK(!split || (A->units && A->splits && A->ckpt), PKSELL_EINVAL,
             "split slices need units, splits and ckpt");
+  const bool plan = chunked && A->n_units > 0;
+  PKS_CHECK(!plan || (A->units && A->ckpt), PKSELL_EINVAL, "chunked matrices need units and ckpt");
+  if (plan) {
+    k_csr_lo<<<cdiv(A->n_units + 1, kBlock), kBlock, 0, st>>>(A->offset, A->n, A->n_units,
+                                                              A->split_words, A->units);
+    PKS_LAUNCHED();
+  }
   if (split) {
     k_unit_tables<<<cdiv(A->n_slices, kBlock), kBlock, 0, st>>>(p.ucnt, p.scnt, A->n_slices,
                                                                A->units, A->splits);
@@ -731,7 +776,9 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val, in
                                                A->n, A->C, A->sigma, A->k_left, A->D,       \
                                                A->n_slices, p.stored_rows, A->offset,       \
                                                A->pack, A->row_exp,                         \
-                                               split ? A->split_words : 0, p.ucnt, A->ckpt)
+                                               split ? A->split_words : 0, p.ucnt, A->ckpt, \
+                                               plan ? A->split_words : 0,                   \
+                                               plan ? A->ckpt : nullptr)
   if (val_dtype == PKSELL_F32) {
     if (A->fmt == PKSELL_FP16) PKS_FILL(PKSELL_FP16, float);
     else if (A->fmt == PKSELL_E8MY) PKS_FILL(PKSELL_E8MY, float);

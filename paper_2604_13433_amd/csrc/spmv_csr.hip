@@ -1,0 +1,320 @@
+// Products of CSR-packed matrices balanced over words.
+//
+// A CSR-packed matrix is PackSELL with one-row slices (C = 1) and no row
+// sort (sigma = 1): every row's words sit together, in order, with no
+// padding, and the slice offsets are a word row pointer.  The paper names
+// delta-value packing in a CSR-based format as future work (sec. 6), noting
+// that it needs care with load balancing and communication between
+// threads; this is the design used here.
+//
+// The word stream is cut into chunks of T = 64 K words, one per wave,
+// whatever rows they fall in, so every wave moves the same bytes however
+// uneven the rows are.  Lane l takes the K consecutive words at c T + l K
+// (loaded as 16-byte vectors) and walks them in order:
+//
+//  * Row starts ("heads") come from the rows the chunk owns (those whose
+//    words start inside it, lo[c] .. lo[c+1] - 1, from the plan): each lane
+//    marks one row's head in a per-wave bitmap in LDS, and writes y = 0 for
+//    an empty row.
+//  * Columns are running sums of deltas (sec. 4.4) from each row's eq. 4
+//    left offset.  A lane knows its columns from its first head on; before
+//    it, it needs the column reached at the end of the lane before.  A
+//    segmented scan over the 64 lanes (a head restarts the sum) gives it,
+//    seeded by the chunk's anchor (the running column before its first
+//    word, from the plan).
+//  * Products are summed per row in word order inside a lane; a row that
+//    continues across lanes is finished by a second segmented scan of the
+//    lanes' open sums, and the lane where it ends writes y.
+//  * A row that continues past the chunk leaves its piece in the chunk's
+//    scratch (the piece before the first head, and the open piece after
+//    the last), and a second kernel adds the pieces of each such row in
+//    chunk order.  Every sum has a fixed order: results are deterministic.
+#include "codec.hpp"
+#include "common.hpp"
+
+namespace pksell {
+
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCsrWaves = 4;  // waves (chunks) per workgroup
+constexpr int kCsrBlock = kCsrWaves * kWave;
+
+struct CsrArgs {
+  const uint32_t *pack;
+  const int64_t *rowptr;  // word row pointer (the slice offsets), n + 1
+  const uint32_t *lo;     // n_chunks + 1
+  const uint32_t *anchor; // n_chunks
+  const int16_t *row_exp;
+  const float *x;
+  float *y;
+  float *head_part;   // n_chunks: the piece of the row continued from earlier chunks
+  float *tail_part;   // n_chunks: the open piece of the chunk's last row
+  int32_t *tail_row;  // n_chunks: that row, or -1
+  int64_t n_words;
+  uint32_t n, m, n_chunks, k_left;
+  int32_t D;
+  Codec cd;
+};
+
+// Eq. 4 with one-row windows.
+__device__ inline uint32_t row_base(uint32_t r, uint32_t k_left) {
+  return r > k_left ? r - k_left : 0u;
+}
+
+template <int FMT>
+__device__ inline float row_scaled(float v, const CsrArgs &a, uint32_t r) {
+  if constexpr (FMT == PKSELL_FIX) return ldexpf(v, (int)a.row_exp[r] - a.D - 1);
+  else return v;
+}
+
+// Inclusive segmented scan over the wave in lane order: a lane with ``f``
+// set starts a new segment.  On return f tells whether a head lies at or
+// before this lane, and v (and r, the row of the last head) hold the
+// running values.
+__device__ inline void seg_scan_col(bool &f, uint32_t &v, uint32_t &r, uint32_t lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t pv = __shfl_up(v, o, kWave);
+    const uint32_t pr = __shfl_up(r, o, kWave);
+    const bool pf = __shfl_up((int)f, o, kWave) != 0;
+    if (lane >= (uint32_t)o && !f) {
+      v += pv;
+      r = pr;
+      f = pf;
+    }
+  }
+}
+
+__device__ inline void seg_scan_sum(bool f, float &s, uint32_t lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const float ps = __shfl_up(s, o, kWave);
+    const bool pf = __shfl_up((int)f, o, kWave) != 0;
+    if (lane >= (uint32_t)o && !f) {
+      s += ps;
+      f = pf;
+    }
+  }
+}
+
+template <int FMT, int K>
+__global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
+  constexpr uint32_t T = K * kWave;
+  __shared__ uint32_t s_heads[kCsrWaves][kWave];  // bit j of word l: position l K + j is a head
+  __shared__ uint32_t s_row[kCsrWaves][T];        // the row at each head position
+  const uint32_t wv = threadIdx.x / kWave;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t c =
+      __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * kCsrWaves + wv);
+  if (c >= a.n_chunks) return;
+  uint32_t *heads = s_heads[wv];
+  uint32_t *hrow = s_row[wv];
+  const int64_t p0 = (int64_t)c * T;
+  const uint32_t rlo = a.lo[c];
+  const uint32_t rhi = min(a.lo[c + 1], a.n);
+  const bool last = c + 1 == a.n_chunks;
+  // closed: the chunk's last word ends its row
+  const bool closed = last || a.rowptr[rhi] == p0 + T;
+
+  heads[lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t r = rlo + lane; r < rhi; r += kWave) {
+    const int64_t s = a.rowptr[r], e = a.rowptr[r + 1];
+    const uint64_t p = (uint64_t)(s - p0);
+    if (s == e) {
+      a.y[r] = 0.0f;
+    } else if (p < T) {  // always, for a plan built by the encoder
+      hrow[p] = r;
+      atomicOr(&heads[p / K], 1u << (p % K));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t hb = heads[lane];
+
+  // the lane's K words (zero words past the end: delta 0, no value)
+  const int64_t q0 = p0 + (int64_t)lane * K;
+  uint32_t w[K];
+  if (q0 + K <= a.n_words) {
+    const u32x4 *p4 = reinterpret_cast<const u32x4 *>(a.pack + q0);
+#pragma unroll
+    for (int i = 0; i < K / 4; ++i) {
+      const u32x4 u = __builtin_nontemporal_load(p4 + i);
+      w[4 * i] = u.x;
+      w[4 * i + 1] = u.y;
+      w[4 * i + 2] = u.z;
+      w[4 * i + 3] = u.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; ++j) w[j] = q0 + j < a.n_words ? a.pack[q0 + j] : 0u;
+  }
+
+  // pass 1: the lane's column aggregate (absolute after a head, else a
+  // delta sum) and the row of its last head
+  uint32_t run = 0, lrow = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t d = unpack(w[j], a.cd).delta;
+    if ((hb >> j) & 1u) {
+      lrow = hrow[lane * K + j];
+      run = row_base(lrow, a.k_left) + d;
+    } else {
+      run += d;
+    }
+  }
+  const bool has_head = hb != 0u;
+  bool f = has_head;
+  uint32_t v = run, rr = lrow;
+  seg_scan_col(f, v, rr, lane);
+  // exclusive values: what the lanes before this one leave open
+  bool ef = __shfl_up((int)f, 1, kWave) != 0;
+  uint32_t ev = __shfl_up(v, 1, kWave);
+  uint32_t er = __shfl_up(rr, 1, kWave);
+  if (lane == 0) {
+    ef = false;
+    ev = 0u;
+    er = rlo - 1u;
+  }
+  const uint32_t anchor = a.anchor[c];
+  uint32_t col = ef ? ev : anchor + ev;
+
+  // pass 2: columns, gathers, per-row sums in word order
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 4u);
+  const uint32_t oob = a.m * 4u;
+  float xv[K], val[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const Unpacked u = unpack(w[j], a.cd);
+    if ((hb >> j) & 1u) col = row_base(hrow[lane * K + j], a.k_left) + u.delta;
+    else col += u.delta;
+    val[j] = decode_value<FMT>(u.vbits);
+    xv[j] = buffer_load_f32(rx, (w[j] & 1u) ? col * 4u : oob);
+  }
+  float acc = 0.0f, lead = 0.0f;
+  bool open = false;
+  uint32_t cur = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if ((hb >> j) & 1u) {
+      if (open) a.y[cur] = row_scaled<FMT>(acc, a, cur);  // a row inside the lane
+      else lead = acc;
+      acc = 0.0f;
+      open = true;
+      cur = hrow[lane * K + j];
+    }
+    acc = fmaf(val[j], xv[j], acc);
+  }
+  if (!open) lead = acc;
+
+  // the lanes' open sums: segmented by the same heads as the columns
+  float s = has_head ? acc : lead;
+  seg_scan_sum(has_head, s, lane);
+  float es = __shfl_up(s, 1, kWave);
+  if (lane == 0) es = 0.0f;
+  if (has_head) {
+    // the row that ends just before this lane's first head
+    const float total = es + lead;
+    if (ef) a.y[er] = row_scaled<FMT>(total, a, er);
+    else a.head_part[c] = total;  // continued from earlier chunks
+  }
+  if (lane == kWave - 1) {
+    // f, s, rr: the chunk's last segment
+    if (closed) {
+      if (f) a.y[rr] = row_scaled<FMT>(s, a, rr);
+      else a.head_part[c] = s;
+      a.tail_row[c] = -1;
+    } else if (f) {
+      a.tail_part[c] = s;
+      a.tail_row[c] = (int32_t)rr;
+    } else {
+      a.head_part[c] = s;
+      a.tail_row[c] = -1;
+    }
+  }
+}
+
+// Rows that continue past the chunk where they start: the open piece of
+// that chunk plus the leading pieces of the following chunks, in chunk
+// order.
+template <int FMT>
+__global__ void k_csr_rows_across(CsrArgs a, uint32_t T) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_chunks) return;
+  const int32_t r = a.tail_row[c];
+  if (r < 0) return;
+  const int64_t end = a.rowptr[r + 1];
+  const uint32_t c_end = (uint32_t)min<int64_t>((end - 1) / T, a.n_chunks - 1);
+  float s = a.tail_part[c];
+  for (uint32_t k = c + 1; k <= c_end; ++k) s += a.head_part[k];
+  a.y[r] = row_scaled<FMT>(s, a, (uint32_t)r);
+}
+
+__global__ void k_csr_zero(float *y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = 0.0f;
+}
+
+template <int FMT>
+int launch_chunks(const CsrArgs &a, int K, hipStream_t st) {
+  const uint32_t blocks = (uint32_t)cdiv(a.n_chunks, kCsrWaves);
+  switch (K) {
+    case 4: k_csr_chunks<FMT, 4><<<blocks, kCsrBlock, 0, st>>>(a); break;
+    case 8: k_csr_chunks<FMT, 8><<<blocks, kCsrBlock, 0, st>>>(a); break;
+    default: k_csr_chunks<FMT, 16><<<blocks, kCsrBlock, 0, st>>>(a); break;
+  }
+  PKS_LAUNCHED();
+  k_csr_rows_across<FMT><<<cdiv(a.n_chunks, 256), 256, 0, st>>>(a, (uint32_t)(K * kWave));
+  PKS_LAUNCHED();
+  return PKSELL_OK;
+}
+
+}  // namespace
+
+// y = A_q x for a CSR-packed matrix with a chunk plan (C = 1, sigma = 1,
+// split_words = T); called by pksell_spmv for k = 1.
+int spmv_chunks(const pksell_matrix *A, const float *x, float *y, hipStream_t st) {
+  const int64_t T = A->split_words;
+  PKS_CHECK(A->C == 1 && A->sigma == 1 && (T == 256 || T == 512 || T == 1024), PKSELL_EINVAL,
+            "chunked products need C = 1, sigma = 1 and split_words 256, 512 or 1024");
+  PKS_CHECK(A->n_units == cdiv(A->n_words, T), PKSELL_EINVAL, "n_units does not match n_words");
+  PKS_CHECK(A->n_units < (int64_t(1) << 31), PKSELL_ERANGE, "too many chunks");
+  PKS_CHECK(A->n_units == 0 || (A->units && A->ckpt && A->partial), PKSELL_EINVAL,
+            "chunked products need units, ckpt and partial");
+  PKS_CHECK(((uintptr_t)A->pack & 15) == 0, PKSELL_EINVAL,
+            "chunked products need 16-byte aligned words");
+  if (A->n_units == 0) {  // no words: every row is empty
+    k_csr_zero<<<cdiv(A->n, 256), 256, 0, st>>>(y, A->n);
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
+  CsrArgs a;
+  a.pack = A->pack;
+  a.rowptr = A->offset;
+  a.lo = A->units;
+  a.anchor = A->ckpt;
+  a.row_exp = A->row_exp;
+  a.x = x;
+  a.y = y;
+  a.head_part = A->partial;
+  a.tail_part = A->partial + A->n_units;
+  a.tail_row = reinterpret_cast<int32_t *>(A->partial + 2 * A->n_units);
+  a.n_words = A->n_words;
+  a.n = (uint32_t)A->n;
+  a.m = (uint32_t)A->m;
+  a.n_chunks = (uint32_t)A->n_units;
+  a.k_left = (uint32_t)A->k_left;
+  a.D = A->D;
+  a.cd = make_codec(A->D);
+  const int K = (int)(T / kWave);
+  switch (A->fmt) {
+    case PKSELL_FP16: return launch_chunks<PKSELL_FP16>(a, K, st);
+    case PKSELL_E8MY: return launch_chunks<PKSELL_E8MY>(a, K, st);
+    default: return launch_chunks<PKSELL_FIX>(a, K, st);
+  }
+}
+
+}  // namespace pksell
