@@ -277,6 +277,7 @@ def main():
     if not args.no_extra:
         out["fp64_words"] = fp64_leg(args, a, torch, B, W)
         out["words16"] = w16_leg(args, torch, B, W)
+        out["trsv"] = trsv_leg(args, torch, B, W)
     if not args.no_batched:
         out["batched"] = batched_leg(args, torch, B, W)
     if not args.no_pcg:
@@ -412,6 +413,43 @@ def powerlaw_leg(args, torch, B, W):
     log(f"[bench] powerlaw sell_fp32: {res['sell_fp32']}")
     for name, *_ in variants:
         res[name]["speedup_vs_sell_fp32"] = round(res["sell_fp32"]["us"] / res[name]["us"], 3)
+    return res
+
+
+def trsv_leg(args, torch, B, W):
+    """Lower-triangular solve, level by level, on the lower triangle of the
+    7-point 128^3 Laplacian (values 6 and -1, exact in FP16; 382 levels):
+    CSR-packed FP16 words against plain CSR with float32 values."""
+    import copy
+    import scipy.sparse as sp
+    dev = torch.device("cuda:0")
+    a = W.m2_laplace3d(args.grid)
+    L = sp.tril(sp.csr_matrix((a.val, a.col, a.rowptr), shape=(a.n, a.m))).tocsr()
+    L.sort_indices()
+    rp, cl, vl = L.indptr.astype(np.int64), L.indices.astype(np.int32), L.data
+    res = {"n": a.n, "nnz": int(L.nnz)}
+    b = torch.from_numpy(W.uniform_vector(a.n, 8)).to(dev)
+    for name, fmt in (("packed_fp16", "fp16"), ("csr_fp32", None)):
+        S = B.TriangularSolve(rp, cl, vl, a.n, fmt, 15, dev)
+        per = S.bytes_per_solve()
+        R = max(2, int(math.ceil(args.replica_bytes / per)))
+        reps = [S]
+        for _ in range(R - 1):
+            c = copy.copy(S)
+            if fmt is None:
+                c.rp, c.cl, c.val = S.rp.clone(), S.cl.clone(), S.val.clone()
+            else:
+                c.L = S.L.replicate()
+            reps.append(c)
+        ys = [torch.empty(a.n, device=dev) for _ in range(R)]
+        ms = Timed(torch, lambda i: reps[i](b, ys[i]), R, min(args.steps, 40),
+                   min(args.warmup, 20)).run()
+        res[name] = {"us": round(ms * 1e3, 1), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
+                     "levels": S.n_levels, "bytes": per,
+                     "us_per_level": round(ms * 1e3 / S.n_levels, 2)}
+        log(f"[bench] trsv {name}: {res[name]}")
+        del reps, ys
+    res["speedup_vs_csr_fp32"] = round(res["csr_fp32"]["us"] / res["packed_fp16"]["us"], 3)
     return res
 
 

@@ -93,6 +93,9 @@ _PROTOS.update({
     "pksell_csr_transpose": ([vp, vp, vp, i32, i64, i64, i64, vp, vp, vp, vp, ctypes.c_size_t, vp],
                              ctypes.c_int),
     "pksell_stream_read": ([vp, ctypes.c_size_t, i32, i32, vp, vp], ctypes.c_int),
+    "pksell_trsv_levels": ([vp, vp, i64, vp, vp, ctypes.POINTER(i64), vp], ctypes.c_int),
+    "pksell_trsv": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp, vp, vp], ctypes.c_int),
+    "pksell_trsv_csr": ([vp, vp, vp, i64, vp, vp, i64, vp, vp, vp], ctypes.c_int),
     "pksell_batch_plan_bytes": ([i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_batch_plan": ([ctypes.POINTER(CBatchItem), i32, i64, i32, ctypes.POINTER(CBatch), vp,
                            ctypes.c_size_t, vp], ctypes.c_int),
@@ -345,6 +348,56 @@ def encode_packed_csr(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15,
     together in row order (one-row slices, no sort, no padding), with the
     plan of a product balanced over chunks of ``chunk`` words."""
     return encode(rowptr, col, val, n, m, fmt, D, 1, 1, EXPLICIT, device, split_words=chunk)
+
+
+class TriangularSolve:
+    """y = L_q^{-1} b for a lower-triangular L whose rows each end with their
+    diagonal: the CSR-packed words of L (FP16, E8MY or FIX) and its level
+    schedule, built once; each call launches one kernel per level.  With
+    ``fmt=None`` the solve runs on plain CSR (float32 values, int32
+    columns) instead, the comparator."""
+
+    def __init__(self, rowptr, col, val, n: int, fmt="fp16", D: int = 15, device="cuda"):
+        device = torch.device(device)
+        self.n, self.device = n, device
+        self.rp = _dev(rowptr, torch.int64, device)
+        self.cl = _dev(col, torch.int32, device)
+        self.order = torch.empty(max(1, n), dtype=torch.int32, device=device)
+        self.level_ptr = np.zeros(n + 1, dtype=np.int64)
+        nl = i64()
+        _check(lib().pksell_trsv_levels(_ptr(self.rp), _ptr(self.cl), n, _ptr(self.order),
+                                        self.level_ptr.ctypes.data_as(vp), ctypes.byref(nl),
+                                        _stream(device)))
+        self.n_levels = int(nl.value)
+        self.fmt = fmt
+        if fmt is None:
+            self.val = _dev(val, torch.float32, device)
+            self.L = None
+        else:
+            self.L = encode(rowptr, col, val, n, n, fmt, D, 1, 1, EXPLICIT, device)
+
+    def bytes_per_solve(self) -> int:
+        """Algorithmic bytes: the stored words (or 8 B per CSR entry), the
+        row pointer, the schedule, b once, y written once and y gathered
+        once per off-diagonal entry at 4 B."""
+        nnz = int(self.cl.numel())
+        stored = 4 * self.L.n_words if self.L is not None else 8 * nnz
+        return int(stored + 8 * (self.n + 1) + 4 * self.n + 8 * self.n + 4 * (nnz - self.n))
+
+    def __call__(self, b: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+        assert b.dtype == torch.float32 and b.is_contiguous() and b.shape == (self.n,)
+        if y is None:
+            y = torch.empty(self.n, dtype=torch.float32, device=b.device)
+        assert y.data_ptr() != b.data_ptr() or self.n == 0
+        lp = self.level_ptr.ctypes.data_as(vp)
+        if self.L is None:
+            _check(lib().pksell_trsv_csr(_ptr(self.rp), _ptr(self.cl), _ptr(self.val), self.n,
+                                         _ptr(self.order), lp, self.n_levels, _ptr(b), _ptr(y),
+                                         _stream(b.device)))
+        else:
+            _check(lib().pksell_trsv(ctypes.byref(self.L.desc), _ptr(self.order), lp,
+                                     self.n_levels, _ptr(b), _ptr(y), _stream(b.device)))
+        return y
 
 
 class StreamRead:

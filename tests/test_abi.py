@@ -204,3 +204,31 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_trsv_rejects_on_host():
+    """The triangular solves check their arguments before any device work:
+    a C = 64 matrix, a non-square one and a level pointer that does not span
+    the rows are rejected; an empty schedule needs no device."""
+    buf = (ctypes.c_double * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    L = B.lib()
+    lp = (ctypes.c_int64 * 3)(0, 2, 3)
+    for kw, levels in ((dict(fmt=B.FP16, D=15), 2), (dict(fmt=B.FP16, D=15, C=1, sigma=1, m=4), 2),
+                       (dict(fmt=B.FP16, D=15, C=1, sigma=1), 1)):
+        rc, desc, _ = _query(n=3, m=kw.pop("m", 3), **kw)
+        assert rc == B.OK
+        desc.offset = desc.pack = p
+        rc = L.pksell_trsv(ctypes.byref(desc), p, ctypes.cast(lp, ctypes.c_void_p), levels, p, p,
+                           None)
+        assert rc == B.EINVAL, kw
+        assert L.pksell_last_error()
+    assert L.pksell_trsv_csr(p, p, p, 3, p, ctypes.cast(lp, ctypes.c_void_p), 1, p, p,
+                             None) == B.EINVAL
+    nl = ctypes.c_int64(7)
+    lp0 = (ctypes.c_int64 * 1)(5)
+    assert L.pksell_trsv_levels(None, None, 0, None, ctypes.cast(lp0, ctypes.c_void_p),
+                                ctypes.byref(nl), None) == B.OK
+    assert nl.value == 0 and lp0[0] == 0
+    assert L.pksell_trsv_levels(None, None, -1, None, ctypes.cast(lp0, ctypes.c_void_p),
+                                ctypes.byref(nl), None) == B.ERANGE
