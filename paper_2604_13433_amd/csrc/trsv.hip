@@ -34,6 +34,11 @@ struct TrsvArgs {
   Codec cd;
 };
 
+constexpr int kTrsvGroup = 8;  // words (entries) of a row in flight together
+
+// One launch per level, one thread per row.  A row's words are loaded a
+// group at a time, all loads of a group first, then all its gathers of y,
+// so a short row costs one round of each rather than one per word.
 template <int FMT>
 __global__ __launch_bounds__(kTrsvBlock) void k_trsv_level(TrsvArgs a, const int32_t *rows,
                                                            uint32_t count) {
@@ -44,15 +49,28 @@ __global__ __launch_bounds__(kTrsvBlock) void k_trsv_level(TrsvArgs a, const int
   const int64_t s = a.offset[i], e = a.offset[i + 1];
   if (e <= s) return;  // rejected by the level analysis
   const __amdgpu_buffer_rsrc_t ry = make_rsrc(a.y, a.n * 4u);
+  const uint32_t oob = a.n * 4u;
   uint32_t col = i > a.k_left ? i - a.k_left : 0u;
   float acc = 0.0f;
-  for (int64_t p = s; p < e - 1; ++p) {
-    const uint32_t w = a.pack[p];
-    const Unpacked u = unpack(w, a.cd);
-    col += u.delta;
-    if (w & 1u) acc = fmaf(decode_value<FMT>(u.vbits), buffer_load_f32(ry, col * 4u), acc);
+  float d = 0.0f;
+  for (int64_t p = s; p < e; p += kTrsvGroup) {
+    uint32_t w[kTrsvGroup];
+#pragma unroll
+    for (int j = 0; j < kTrsvGroup; ++j) w[j] = p + j < e ? a.pack[p + j] : 0u;
+    float yv[kTrsvGroup], v[kTrsvGroup];
+#pragma unroll
+    for (int j = 0; j < kTrsvGroup; ++j) {
+      const Unpacked u = unpack(w[j], a.cd);
+      col += u.delta;
+      v[j] = decode_value<FMT>(u.vbits);
+      // the diagonal (the row's last word) and flag-0 words gather nothing
+      const bool off = (w[j] & 1u) && p + j < e - 1;
+      yv[j] = buffer_load_f32(ry, off ? col * 4u : oob);
+      if (p + j == e - 1) d = v[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kTrsvGroup; ++j) acc = fmaf(v[j], yv[j], acc);
   }
-  float d = decode_value<FMT>(unpack(a.pack[e - 1], a.cd).vbits);
   if constexpr (FMT == PKSELL_FIX) {
     const int sh = (int)a.row_exp[i] - a.D - 1;
     acc = ldexpf(acc, sh);
@@ -62,7 +80,7 @@ __global__ __launch_bounds__(kTrsvBlock) void k_trsv_level(TrsvArgs a, const int
 }
 
 // The same solve on plain CSR (int32 columns, float32 values): the
-// comparator at 8 bytes per stored entry.
+// comparator at 8 bytes per stored entry, grouped the same way.
 __global__ __launch_bounds__(kTrsvBlock) void k_trsv_csr_level(
     const int64_t *rowptr, const int32_t *col, const float *val, const float *b, float *y,
     uint32_t n, const int32_t *rows, uint32_t count) {
@@ -73,9 +91,22 @@ __global__ __launch_bounds__(kTrsvBlock) void k_trsv_csr_level(
   const int64_t s = rowptr[i], e = rowptr[i + 1];
   if (e <= s) return;
   const __amdgpu_buffer_rsrc_t ry = make_rsrc(y, n * 4u);
+  const uint32_t oob = n * 4u;
   float acc = 0.0f;
-  for (int64_t p = s; p < e - 1; ++p)
-    acc = fmaf(val[p], buffer_load_f32(ry, (uint32_t)col[p] * 4u), acc);
+  for (int64_t p = s; p < e - 1; p += kTrsvGroup) {
+    uint32_t c[kTrsvGroup];
+    float v[kTrsvGroup], yv[kTrsvGroup];
+#pragma unroll
+    for (int j = 0; j < kTrsvGroup; ++j) {
+      const bool in = p + j < e - 1;
+      c[j] = in ? (uint32_t)col[p + j] * 4u : oob;
+      v[j] = in ? val[p + j] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < kTrsvGroup; ++j) yv[j] = buffer_load_f32(ry, c[j]);
+#pragma unroll
+    for (int j = 0; j < kTrsvGroup; ++j) acc = fmaf(v[j], yv[j], acc);
+  }
   y[i] = (b[i] - acc) / val[e - 1];
 }
 
