@@ -87,6 +87,8 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the power-law and block-stencil legs")
+    p.add_argument("--leg", default="", choices=["", "powerlaw", "trsv"],
+                   help="run only this leg and print its JSON (for profiling one kernel)")
     p.add_argument("--calib-copy-mb", type=int, default=0,
                    help="first run one plain device copy of this many MiB (a known-size "
                         "kernel to scale hardware byte counters)")
@@ -160,6 +162,10 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
+    if args.leg:
+        leg = {"powerlaw": powerlaw_leg, "trsv": trsv_leg}[args.leg]
+        print(json.dumps({args.leg: leg(args, torch, B, W)}), flush=True)
+        return
     g = args.grid
     t0 = time.time()
     a = W.m2_laplace3d(g)
