@@ -10,7 +10,10 @@ candidates by bytes are then encoded and timed on the GPU (HIP events over
 graph replays), and the fastest wins.  The split width does not change the
 bytes, only how the work is cut into waves, so each timed C = 64 candidate
 is also timed with every J of ``split_list`` that splits at least one of its
-slices.  Precision is a constraint, not a
+slices.  For single-vector products the CSR-packed layout (C = 1, sigma = 1,
+no padding, a product balanced over chunks of words) is a candidate too:
+its fewest-bytes D is timed with every chunk size of ``csr_chunks``, and it
+wins when it is faster.  Precision is a constraint, not a
 goal: E8MY candidates keep at least ``min_mantissa`` mantissa bits
 (Y = 22 - D), FIX at least ``min_mantissa`` value bits.
 
@@ -31,6 +34,7 @@ from . import binding as B
 DEFAULT_C = (32, 64)
 DEFAULT_SIGMA = (64, 256, 1024, 8192, 65536)
 DEFAULT_SPLIT = (128, 256)
+DEFAULT_CSR_CHUNKS = (512,)
 
 
 def signature(rowptr, col, n: int, m: int, fmt: str, min_mantissa: int, k: int) -> str:
@@ -74,10 +78,12 @@ def _time_spmv(A, x, y, reps=50):
 def tune(rowptr, col, val, n: int, m: int, fmt: str = "e8my", min_mantissa: int = 13,
          perm_mode: int = B.IMPLICIT, k: int = 1, C_list=DEFAULT_C, sigma_list=DEFAULT_SIGMA,
          split_list=DEFAULT_SPLIT, time_top: int = 3, cache_path: str | None = None,
-         device="cuda") -> dict:
+         device="cuda", csr_chunks=DEFAULT_CSR_CHUNKS) -> dict:
     """Returns {"fmt", "D", "C", "sigma", "split_words", "bytes", "us",
-    "candidates": [...]}."""
-    key = signature(rowptr, col, n, m, fmt, min_mantissa, k) + f":{tuple(split_list)}"
+    "candidates": [...], "csr_candidates": [...]}.  C = 1 and sigma = 1 with
+    split_words > 0 selects the CSR-packed layout."""
+    key = (signature(rowptr, col, n, m, fmt, min_mantissa, k) +
+           f":{tuple(split_list)}:{tuple(csr_chunks)}")
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -120,10 +126,29 @@ def tune(rowptr, col, val, n: int, m: int, fmt: str = "e8my", min_mantissa: int 
             if us < c["us"]:
                 c["split_words"], c["us"] = int(J), us
     timed = [c for c in cands if "us" in c]
+    csr = []
+    if k == 1 and csr_chunks:
+        for D in d_candidates(fmt, min_mantissa):
+            A = B.encode(rp, cl, vl, n, m, fmt, D, 1, 1, B.EXPLICIT, device,
+                         analyse_only=True, split_words=int(csr_chunks[0]))
+            csr.append(dict(D=D, C=1, sigma=1, words=int(A.n_words),
+                            dummies=int(A.n_dummies), bytes=A.bytes_per_spmv(1)))
+        csr.sort(key=lambda c: c["bytes"])
+        c = csr[0]
+        c["chunk_us"], chunk_bytes = {}, {}
+        for T in csr_chunks:
+            A = B.encode_packed_csr(rp, cl, vl, n, m, fmt, c["D"], int(T), device)
+            c["chunk_us"][str(T)] = round(_time_spmv(A, x, y) * 1e3, 3)
+            chunk_bytes[str(T)] = A.bytes_per_spmv(1)  # the plan's size depends on T
+            del A
+        T, us = min(c["chunk_us"].items(), key=lambda kv: kv[1])
+        c["split_words"], c["us"], c["bytes"] = int(T), us, chunk_bytes[T]
+        timed.append(c)
     best = min(timed, key=lambda c: c["us"])
     out = dict(fmt=fmt, D=best["D"], C=best["C"], sigma=best["sigma"],
                split_words=best["split_words"], bytes=best["bytes"], us=best["us"],
-               min_mantissa=min_mantissa, k=k, candidates=cands[: max(10, time_top)])
+               min_mantissa=min_mantissa, k=k, candidates=cands[: max(10, time_top)],
+               csr_candidates=csr[:5])
     if cache_path:
         cache[key] = out
         tmp = cache_path + ".tmp"

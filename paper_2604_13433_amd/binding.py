@@ -213,11 +213,12 @@ class PackSELLMatrix:
             return int(b)
         wb = 2 if d.fmt in W16 else 4  # bytes per word
         b = wb * d.n_words + 8 * (d.n_slices + 1) + 4 * d.m * k + 4 * d.n * k
-        if d.perm_mode == IMPLICIT:
+        chunked = d.C == 1 and d.split_words > 0 and k == 1
+        if d.perm_mode == IMPLICIT and not chunked:  # rows stay in order: no perm read
             b += d.perm_bytes * d.n
         if d.fmt in (FIX, FIX16):
             b += 2 * d.n
-        if d.C == 1 and d.split_words > 0 and k == 1 and d.n_units > 0:
+        if chunked and d.n_units > 0:
             b += 12 * d.n_units + 4  # chunk plan read, each chunk's row marker written
         return int(b)
 

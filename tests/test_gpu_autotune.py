@@ -22,9 +22,9 @@ def test_tune_stencil(tmp_path):
     assert 22 - r["D"] >= 13
     # the chosen configuration's byte model equals the built matrix's
     A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e8my", r["D"], r["C"], r["sigma"],
-                 B.IMPLICIT, DEV)
+                 B.IMPLICIT, DEV, split_words=r["split_words"])
     assert A.bytes_per_spmv() == r["bytes"]
-    timed = [c for c in r["candidates"] if "us" in c]
+    timed = [c for c in r["candidates"] + r["csr_candidates"] if "us" in c]
     assert timed and r["us"] == min(c["us"] for c in timed)
     again = T.tune(a.rowptr, a.col, a.val, a.n, a.m, "e8my", min_mantissa=13,
                    cache_path=cache, device=DEV)
@@ -48,7 +48,7 @@ def test_tune_splits_wide_slices(tmp_path):
     a = W.powerlaw(60_000, seed=9)
     cache = os.path.join(tmp_path, "tune.json")
     r = T.tune(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 10, C_list=(64,), sigma_list=(65536,),
-               split_list=(128, 256), time_top=1, cache_path=cache, device=DEV)
+               split_list=(128, 256), time_top=1, cache_path=cache, device=DEV, csr_chunks=())
     top = r["candidates"][0]
     assert set(top["split_us"]) == {"128", "256"}  # both split some slice
     assert r["split_words"] in (0, 128, 256)
@@ -61,4 +61,26 @@ def test_tune_splits_wide_slices(tmp_path):
     assert normalised_error(y, ref, a, q, x) <= SPMV_TOL
     assert T.tune(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 10, C_list=(64,),
                   sigma_list=(65536,), split_list=(128, 256), time_top=1,
-                  cache_path=cache, device=DEV) == r
+                  cache_path=cache, device=DEV, csr_chunks=()) == r
+
+
+def test_tune_picks_csr_packing_for_power_law_rows():
+    """On power-law rows the CSR-packed layout is timed beside split SELL;
+    whichever wins, the chosen configuration rebuilds to the same bytes and
+    multiplies correctly."""
+    from helpers import FMTS, SPMV_TOL, normalised_error, oracle_product
+
+    a = W.powerlaw(200_000, seed=9)
+    r = T.tune(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 10, C_list=(64,), sigma_list=(65536,),
+               split_list=(128,), time_top=1, device=DEV, csr_chunks=(256, 512))
+    c = r["csr_candidates"][0]
+    assert set(c["chunk_us"]) == {"256", "512"} and c["C"] == 1 and c["sigma"] == 1
+    timed = [c for c in r["candidates"] + r["csr_candidates"] if "us" in c]
+    assert r["us"] == min(t["us"] for t in timed)
+    A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "fp16", r["D"], r["C"], r["sigma"],
+                 B.EXPLICIT, DEV, split_words=r["split_words"])
+    assert A.bytes_per_spmv() == r["bytes"]
+    x = W.uniform_vector(a.m, 4)
+    y = B.spmv(A, torch.from_numpy(x).to(DEV)).cpu().numpy()
+    ref, q = oracle_product(a, FMTS["fp16"], 15, x)
+    assert normalised_error(y, ref, a, q, x) <= SPMV_TOL

@@ -4,7 +4,10 @@ equal the eager product of the same inputs, bit for bit (up to float32
 rounding where atomics add in no fixed order).  The captured paths
 zero their outputs with kernels, never with memset nodes: the transposed
 batched plan, the atomic adjoint, split products (chunk sums combined by a
-second kernel) and 16-bit words."""
+second kernel), 16-bit words, CSR-packed chunk products (cross-chunk rows
+summed by a second kernel) and level-scheduled triangular solves (one
+launch per level)."""
+import numpy as np
 import pytest
 import torch
 
@@ -119,3 +122,28 @@ def test_half_value_sell_replays():
     x = torch.from_numpy(W.uniform_vector(a.m, 7)).to(DEV)
     y = torch.empty(a.n, device=DEV)
     replay_and_check(lambda: B.sell_spmv(S, x, y), [x], [y], lambda: [B.sell_spmv(S, x)])
+
+
+def test_packed_csr_product_replays():
+    """The chunk-balanced product writes its cross-chunk pieces to the
+    matrix's scratch and sums them in a second kernel: both in the graph."""
+    a = W.m3_powerlaw(n=30_000, seed=6)
+    A = B.encode_packed_csr(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 256, DEV)
+    assert A.desc.n_units > 1
+    x = torch.from_numpy(W.uniform_vector(a.m, 9)).to(DEV)
+    y = torch.empty(a.n, device=DEV)
+    replay_and_check(lambda: B.spmv(A, x, y), [x], [y], lambda: [B.spmv(A, x)])
+
+
+def test_triangular_solve_replays():
+    """One launch per level, all captured; y is scribbled on between replays."""
+    import scipy.sparse as sp
+    a = W.m2_laplace3d(24)
+    L = sp.tril(sp.csr_matrix((a.val, a.col, a.rowptr), shape=(a.n, a.m))).tocsr()
+    L.sort_indices()
+    for fmt in ("fp16", None):
+        S = B.TriangularSolve(L.indptr.astype(np.int64), L.indices.astype(np.int32), L.data, a.n,
+                              fmt, 15, DEV)
+        b = torch.from_numpy(W.uniform_vector(a.n, 10)).to(DEV)
+        y = torch.empty(a.n, device=DEV)
+        replay_and_check(lambda: S(b, y), [b], [y], lambda: [S(b)])
