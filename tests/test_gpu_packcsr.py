@@ -144,3 +144,25 @@ def test_powerlaw_full_size_sampled_rows():
         s, e = a.rowptr[r], a.rowptr[r + 1]
         ref = float(np.dot(q[s:e], x.astype(np.float32).astype(np.float64)[a.col[s:e]]))
         assert abs(float(y[r]) - ref) / den <= SPMV_TOL, r
+
+
+def test_adjoint_and_value_gradients_on_packed_csr():
+    """The adjoint A_q^T g and the value gradients g_i x_j run on the same
+    one-row-slice words (the chunk plan is not used by them)."""
+    import scipy.sparse as sp
+
+    a = hollow(11)
+    A, E = both(a, "e8my", 9, 512)
+    q = P.quantized_values(a.rowptr, a.col, a.val, a.n, FMTS["e8my"], 9)
+    rng = np.random.default_rng(12)
+    g = rng.uniform(-1, 1, a.n).astype(np.float32)
+    x = rng.uniform(-1, 1, a.m).astype(np.float32)
+    yt = B.spmv_t(A, torch.from_numpy(g).to(DEV)).cpu().numpy().astype(np.float64)
+    Aq = sp.csr_matrix((q, a.col, a.rowptr), shape=(a.n, a.m))
+    ref = Aq.T @ g.astype(np.float64)
+    colsum = float(np.max(abs(Aq).sum(axis=0)))
+    assert np.max(np.abs(yt - ref)) / (colsum * np.abs(g).max()) <= SPMV_TOL
+    rp = torch.from_numpy(a.rowptr).to(DEV)
+    gv = B.grad_values(A, rp, torch.from_numpy(g).to(DEV), torch.from_numpy(x).to(DEV))
+    want = (g[a.rows()] * x[a.col]).astype(np.float32)
+    assert np.array_equal(gv.cpu().numpy()[: a.nnz], want)
