@@ -39,3 +39,12 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_single_leg_option_is_checked():
+    """--leg accepts only the legs it can run alone; anything else is a
+    usage error before any GPU work."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--leg", "nonsense"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "powerlaw" in r.stderr and "trsv" in r.stderr
