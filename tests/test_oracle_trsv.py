@@ -1,4 +1,4 @@
-"""Pins of the triangular-solve oracle: scipy's triangular solver on the
+"""Pins of the triangular-solve oracle (lower and upper): scipy's triangular solver on the
 same quantised matrix, the residual of the solution, closed-form levels of
 grid Laplacians (level = i + j (+ k) in natural order), a dense solve, and
 the level property on random matrices."""
@@ -103,3 +103,42 @@ def test_rejects_a_row_without_its_diagonal():
     a = W.csr_from_triplets(3, 3, [0, 1, 2], [0, 0, 2], [1.0, 1.0, 1.0])
     with pytest.raises(ValueError):
         TR.levels(a.rowptr, a.col, 3)
+
+
+def transpose_of(a):
+    """The transpose as a CSR with sorted columns (upper when a is lower)."""
+    M = sp.csr_matrix((a.val, a.col, a.rowptr), shape=(a.n, a.m)).T.tocsr()
+    M.sort_indices()
+    return W.csr_from_triplets(a.m, a.n, np.repeat(np.arange(a.m), np.diff(M.indptr)),
+                               M.indices, M.data)
+
+
+@pytest.mark.parametrize("fmt,D", [("fp16", 15), ("e8my", 6), ("fix", 18)])
+def test_upper_solve_equals_scipy(fmt, D):
+    u = transpose_of(random_lower(4, 400, 6))
+    E = PC.encode(u.rowptr, u.col, u.val, u.n, u.n, FMTS[fmt], D)
+    b = np.random.default_rng(3).uniform(-1, 1, u.n)
+    y = TR.solve(E, b, upper=True)
+    q = TR.quantised_lower(u.rowptr, u.col, u.val, u.n, FMTS[fmt], D)
+    Uq = sp.csr_matrix((q, u.col, u.rowptr), shape=(u.n, u.n))
+    ref = spl.spsolve_triangular(Uq, b, lower=False)
+    assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(Uq @ y - b)) <= 1e-12
+
+
+def test_upper_levels_of_a_grid_laplacian():
+    """Upper triangle in natural order: a point depends on its upper
+    neighbours, so its level is the sum of its distances to the far
+    corner."""
+    dims = (6, 5, 4)
+    a = W.stencil(dims, "star", 1, 1.0, "lap")
+    M = sp.triu(sp.csr_matrix((a.val, a.col, a.rowptr), shape=(a.n, a.m))).tocsr()
+    M.sort_indices()
+    u = W.csr_from_triplets(a.n, a.n, np.repeat(np.arange(a.n), np.diff(M.indptr)), M.indices,
+                            M.data)
+    lev = TR.levels(u.rowptr, u.col, u.n, upper=True)
+    idx = np.indices(dims[::-1]).reshape(3, -1)
+    far = np.array(dims[::-1])[:, None] - 1 - idx
+    assert np.array_equal(lev, far.sum(axis=0))
+    with pytest.raises(ValueError):
+        TR.levels(u.rowptr, u.col, u.n, upper=False)  # the diagonal is not last
