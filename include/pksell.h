@@ -298,43 +298,44 @@ int pksell_decode(const pksell_matrix *A, int32_t *cols, float *vals,
                   void *stream);
 
 /* ------------------------------------------------------------------------
- * Sparse lower-triangular solves on CSR-packed words (not in the paper as
- * such: it names triangular solves as a kernel its packing should suit,
- * sec. 6).  L is n x n, lower triangular, and every row ends with its
- * diagonal entry; it is encoded as a CSR-packed matrix (C = 1, sigma = 1,
- * no split_words needed) with FP16, E8MY or FIX words, so the solve uses
- * the quantised L_q.
+ * Sparse triangular solves on CSR-packed words (not in the paper as such:
+ * it names triangular solves as a kernel its packing should suit, sec. 6).
+ * L is n x n and triangular: lower (upper = 0) with every row ending in its
+ * diagonal entry, or upper (upper = 1) with every row starting with it.  It
+ * is encoded as a CSR-packed matrix (C = 1, sigma = 1, no split_words
+ * needed) with FP16, E8MY or FIX words, so the solve uses the quantised L_q.
  * ---------------------------------------------------------------------- */
 
 /* Level schedule: level(i) = 0 for a row with only its diagonal, else
- * 1 + the largest level among its off-diagonal columns.  Input: the device
- * CSR of L (rowptr int64[n+1], col int32[nnz]).  Output: order (device
+ * 1 + the largest level among its off-diagonal columns (rows taken in
+ * ascending order for lower, descending for upper).  Input: the device
+ * CSR of L (rowptr int64[n+1], col int32[nnz]) and ``upper``.  Output: order (device
  * int32[n]: rows by ascending level, ascending row order inside a level),
  * level_ptr (HOST int64[n + 1]: level l holds order[level_ptr[l] ..
  * level_ptr[l+1])) and *n_levels (host).  Copies the CSR structure to the
- * host and walks it once in row order; SYNCHRONISES the stream.  EINVAL
- * when a row is empty, its last entry is not its diagonal, or its other
- * columns do not increase below the diagonal. */
+ * host and walks it once; SYNCHRONISES the stream.  EINVAL when a row is
+ * empty, its diagonal is not where ``upper`` puts it, or its other columns
+ * do not increase on that side of the diagonal. */
 int pksell_trsv_levels(const int64_t *rowptr, const int32_t *col, int64_t n,
-                       int32_t *order, int64_t *level_ptr, int64_t *n_levels,
-                       void *stream);
+                       int32_t upper, int32_t *order, int64_t *level_ptr,
+                       int64_t *n_levels, void *stream);
 
 /* Solves L_q y = b (float32 b and y, device, n each; y must not alias b):
- * y_i = (b_i - sum_{j<i} (L_q)_ij y_j) / (L_q)_ii with float32 sums in
+ * y_i = (b_i - sum_{j != i} (L_q)_ij y_j) / (L_q)_ii with float32 sums in
  * word order, one launch per level on ``stream`` (order on the device,
- * level_ptr on the host, from pksell_trsv_levels on the same CSR).  A zero
- * diagonal gives inf or NaN.  EINVAL unless L is CSR-packed with 32-bit
- * words, square, and level_ptr spans its n rows. */
-int pksell_trsv(const pksell_matrix *L, const int32_t *order,
+ * level_ptr on the host, from pksell_trsv_levels on the same CSR and the
+ * same ``upper``).  A zero diagonal gives inf or NaN.  EINVAL unless L is
+ * CSR-packed with 32-bit words, square, and level_ptr spans its n rows. */
+int pksell_trsv(const pksell_matrix *L, int32_t upper, const int32_t *order,
                 const int64_t *level_ptr, int64_t n_levels, const float *b,
                 float *y, void *stream);
 
 /* The same level-scheduled solve on plain CSR (int32 columns, float32
  * values, 8 bytes per entry): the comparator for pksell_trsv. */
 int pksell_trsv_csr(const int64_t *rowptr, const int32_t *col,
-                    const float *val, int64_t n, const int32_t *order,
-                    const int64_t *level_ptr, int64_t n_levels,
-                    const float *b, float *y, void *stream);
+                    const float *val, int64_t n, int32_t upper,
+                    const int32_t *order, const int64_t *level_ptr,
+                    int64_t n_levels, const float *b, float *y, void *stream);
 
 /* ------------------------------------------------------------------------
  * Plain SELL-C-sigma (sec. 3), the comparator and the float64 operator.

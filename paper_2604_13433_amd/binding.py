@@ -93,9 +93,9 @@ _PROTOS.update({
     "pksell_csr_transpose": ([vp, vp, vp, i32, i64, i64, i64, vp, vp, vp, vp, ctypes.c_size_t, vp],
                              ctypes.c_int),
     "pksell_stream_read": ([vp, ctypes.c_size_t, i32, i32, vp, vp], ctypes.c_int),
-    "pksell_trsv_levels": ([vp, vp, i64, vp, vp, ctypes.POINTER(i64), vp], ctypes.c_int),
-    "pksell_trsv": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp, vp, vp], ctypes.c_int),
-    "pksell_trsv_csr": ([vp, vp, vp, i64, vp, vp, i64, vp, vp, vp], ctypes.c_int),
+    "pksell_trsv_levels": ([vp, vp, i64, i32, vp, vp, ctypes.POINTER(i64), vp], ctypes.c_int),
+    "pksell_trsv": ([ctypes.POINTER(CMatrix), i32, vp, vp, i64, vp, vp, vp], ctypes.c_int),
+    "pksell_trsv_csr": ([vp, vp, vp, i64, i32, vp, vp, i64, vp, vp, vp], ctypes.c_int),
     "pksell_batch_plan_bytes": ([i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_batch_plan": ([ctypes.POINTER(CBatchItem), i32, i64, i32, ctypes.POINTER(CBatch), vp,
                            ctypes.c_size_t, vp], ctypes.c_int),
@@ -352,21 +352,24 @@ def encode_packed_csr(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15,
 
 
 class TriangularSolve:
-    """y = L_q^{-1} b for a lower-triangular L whose rows each end with their
-    diagonal: the CSR-packed words of L (FP16, E8MY or FIX) and its level
-    schedule, built once; each call launches one kernel per level.  With
-    ``fmt=None`` the solve runs on plain CSR (float32 values, int32
-    columns) instead, the comparator."""
+    """y = L_q^{-1} b for a triangular L: lower with every row ending in its
+    diagonal, or (``upper``) upper with every row starting with it.  The
+    CSR-packed words of L (FP16, E8MY or FIX) and its level schedule are
+    built once; each call launches one kernel per level.  With ``fmt=None``
+    the solve runs on plain CSR (float32 values, int32 columns) instead,
+    the comparator."""
 
-    def __init__(self, rowptr, col, val, n: int, fmt="fp16", D: int = 15, device="cuda"):
+    def __init__(self, rowptr, col, val, n: int, fmt="fp16", D: int = 15, device="cuda",
+                 upper: bool = False):
         device = torch.device(device)
-        self.n, self.device = n, device
+        self.n, self.device, self.upper = n, device, int(bool(upper))
         self.rp = _dev(rowptr, torch.int64, device)
         self.cl = _dev(col, torch.int32, device)
         self.order = torch.empty(max(1, n), dtype=torch.int32, device=device)
         self.level_ptr = np.zeros(n + 1, dtype=np.int64)
         nl = i64()
-        _check(lib().pksell_trsv_levels(_ptr(self.rp), _ptr(self.cl), n, _ptr(self.order),
+        _check(lib().pksell_trsv_levels(_ptr(self.rp), _ptr(self.cl), n, self.upper,
+                                        _ptr(self.order),
                                         self.level_ptr.ctypes.data_as(vp), ctypes.byref(nl),
                                         _stream(device)))
         self.n_levels = int(nl.value)
@@ -393,11 +396,11 @@ class TriangularSolve:
         lp = self.level_ptr.ctypes.data_as(vp)
         if self.L is None:
             _check(lib().pksell_trsv_csr(_ptr(self.rp), _ptr(self.cl), _ptr(self.val), self.n,
-                                         _ptr(self.order), lp, self.n_levels, _ptr(b), _ptr(y),
-                                         _stream(b.device)))
+                                         self.upper, _ptr(self.order), lp, self.n_levels,
+                                         _ptr(b), _ptr(y), _stream(b.device)))
         else:
-            _check(lib().pksell_trsv(ctypes.byref(self.L.desc), _ptr(self.order), lp,
-                                     self.n_levels, _ptr(b), _ptr(y), _stream(b.device)))
+            _check(lib().pksell_trsv(ctypes.byref(self.L.desc), self.upper, _ptr(self.order),
+                                     lp, self.n_levels, _ptr(b), _ptr(y), _stream(b.device)))
         return y
 
 

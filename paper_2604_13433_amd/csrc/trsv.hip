@@ -1,10 +1,12 @@
-// Sparse lower-triangular solves on CSR-packed words, level by level.
+// Sparse triangular solves on CSR-packed words, level by level.
 //
 // The paper names sparse triangular solves as a kernel its packing should
-// suit (sec. 6).  L is lower triangular and every row ends with its
-// diagonal; packed as CSR-based words (one-row slices, no sort), a row's
-// words are contiguous and its last word is the diagonal.  The solve
-//   y_i = (b_i - sum_{j<i} (L_q)_ij y_j) / (L_q)_ii
+// suit (sec. 6).  L is lower triangular with every row ending in its
+// diagonal, or upper triangular with every row starting with it; packed as
+// CSR-based words (one-row slices, no sort), a row's words are contiguous
+// and its last (lower) or first value word (upper) is the diagonal.  The
+// solve
+//   y_i = (b_i - sum_{j<i, or j>i} (L_q)_ij y_j) / (L_q)_ii
 // runs one launch per level of a level schedule (rows whose off-diagonal
 // columns all lie in lower levels), one thread per row: the thread walks
 // its row's words, rebuilding columns as running sums of deltas from the
@@ -39,7 +41,7 @@ constexpr int kTrsvGroup = 8;  // words (entries) of a row in flight together
 // One launch per level, one thread per row.  A row's words are loaded a
 // group at a time, all loads of a group first, then all its gathers of y,
 // so a short row costs one round of each rather than one per word.
-template <int FMT>
+template <int FMT, bool UPPER>
 __global__ __launch_bounds__(kTrsvBlock) void k_trsv_level(TrsvArgs a, const int32_t *rows,
                                                            uint32_t count) {
   const uint32_t t = blockIdx.x * kTrsvBlock + threadIdx.x;
@@ -53,6 +55,7 @@ __global__ __launch_bounds__(kTrsvBlock) void k_trsv_level(TrsvArgs a, const int
   uint32_t col = i > a.k_left ? i - a.k_left : 0u;
   float acc = 0.0f;
   float d = 0.0f;
+  bool have_d = false;  // upper: the first value word is the diagonal
   for (int64_t p = s; p < e; p += kTrsvGroup) {
     uint32_t w[kTrsvGroup];
 #pragma unroll
@@ -63,10 +66,15 @@ __global__ __launch_bounds__(kTrsvBlock) void k_trsv_level(TrsvArgs a, const int
       const Unpacked u = unpack(w[j], a.cd);
       col += u.delta;
       v[j] = decode_value<FMT>(u.vbits);
-      // the diagonal (the row's last word) and flag-0 words gather nothing
-      const bool off = (w[j] & 1u) && p + j < e - 1;
-      yv[j] = buffer_load_f32(ry, off ? col * 4u : oob);
-      if (p + j == e - 1) d = v[j];
+      // the diagonal and flag-0 words gather nothing
+      const bool live = w[j] & 1u;
+      const bool diag = UPPER ? live && !have_d : p + j == e - 1;
+      if (diag) {
+        d = v[j];
+        v[j] = 0.0f;
+        have_d = true;
+      }
+      yv[j] = buffer_load_f32(ry, live && !diag ? col * 4u : oob);
     }
 #pragma unroll
     for (int j = 0; j < kTrsvGroup; ++j) acc = fmaf(v[j], yv[j], acc);
@@ -81,6 +89,7 @@ __global__ __launch_bounds__(kTrsvBlock) void k_trsv_level(TrsvArgs a, const int
 
 // The same solve on plain CSR (int32 columns, float32 values): the
 // comparator at 8 bytes per stored entry, grouped the same way.
+template <bool UPPER>
 __global__ __launch_bounds__(kTrsvBlock) void k_trsv_csr_level(
     const int64_t *rowptr, const int32_t *col, const float *val, const float *b, float *y,
     uint32_t n, const int32_t *rows, uint32_t count) {
@@ -93,12 +102,14 @@ __global__ __launch_bounds__(kTrsvBlock) void k_trsv_csr_level(
   const __amdgpu_buffer_rsrc_t ry = make_rsrc(y, n * 4u);
   const uint32_t oob = n * 4u;
   float acc = 0.0f;
-  for (int64_t p = s; p < e - 1; p += kTrsvGroup) {
+  // off-diagonal entries: [s, e - 1) below the diagonal, [s + 1, e) above it
+  const int64_t os = UPPER ? s + 1 : s, oe = UPPER ? e : e - 1;
+  for (int64_t p = os; p < oe; p += kTrsvGroup) {
     uint32_t c[kTrsvGroup];
     float v[kTrsvGroup], yv[kTrsvGroup];
 #pragma unroll
     for (int j = 0; j < kTrsvGroup; ++j) {
-      const bool in = p + j < e - 1;
+      const bool in = p + j < oe;
       c[j] = in ? (uint32_t)col[p + j] * 4u : oob;
       v[j] = in ? val[p + j] : 0.0f;
     }
@@ -107,7 +118,7 @@ __global__ __launch_bounds__(kTrsvBlock) void k_trsv_csr_level(
 #pragma unroll
     for (int j = 0; j < kTrsvGroup; ++j) acc = fmaf(v[j], yv[j], acc);
   }
-  y[i] = (b[i] - acc) / val[e - 1];
+  y[i] = (b[i] - acc) / val[UPPER ? s : e - 1];
 }
 
 }  // namespace
@@ -118,8 +129,8 @@ using namespace pksell;
 
 extern "C" {
 
-int pksell_trsv_levels(const int64_t *rowptr, const int32_t *col, int64_t n, int32_t *order,
-                       int64_t *level_ptr, int64_t *n_levels, void *stream) {
+int pksell_trsv_levels(const int64_t *rowptr, const int32_t *col, int64_t n, int32_t upper,
+                       int32_t *order, int64_t *level_ptr, int64_t *n_levels, void *stream) {
   PKS_CHECK(n_levels && level_ptr, PKSELL_EINVAL, "null argument");
   PKS_CHECK(n >= 0 && n < (int64_t(1) << 30), PKSELL_ERANGE, "n must be in [0, 2^30)");
   *n_levels = 0;
@@ -135,20 +146,24 @@ int pksell_trsv_levels(const int64_t *rowptr, const int32_t *col, int64_t n, int
   std::vector<int32_t> cl(nnz);
   PKS_HIP(hipMemcpyAsync(cl.data(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
   PKS_HIP(hipStreamSynchronize(st));
-  // level(i) = 1 + max level over the row's off-diagonal columns (0 if none)
+  // level(i) = 1 + max level over the row's off-diagonal columns (0 if
+  // none), rows in dependency order: ascending (lower) or descending (upper)
   std::vector<int32_t> lev(n);
   int32_t top = 0;
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t i = upper ? n - 1 - k : k;
     const int64_t s = rp[i], e = rp[i + 1];
     PKS_CHECK(e > s && e <= nnz, PKSELL_EINVAL, "row %lld: no entries (needs its diagonal)",
               (long long)i);
-    PKS_CHECK(cl[e - 1] == i, PKSELL_EINVAL, "row %lld: the last entry is not the diagonal",
-              (long long)i);
+    PKS_CHECK(cl[upper ? s : e - 1] == i, PKSELL_EINVAL,
+              "row %lld: the %s entry is not the diagonal", (long long)i,
+              upper ? "first" : "last");
     int32_t l = -1;
-    int64_t prev = -1;
-    for (int64_t p = s; p < e - 1; ++p) {
-      PKS_CHECK(cl[p] > prev && cl[p] < i, PKSELL_EINVAL,
-                "row %lld: columns must increase and lie below the diagonal", (long long)i);
+    int64_t prev = upper ? i : -1;
+    for (int64_t p = upper ? s + 1 : s; p < (upper ? e : e - 1); ++p) {
+      PKS_CHECK(cl[p] > prev && (upper ? cl[p] < n : cl[p] < i), PKSELL_EINVAL,
+                "row %lld: columns must increase and lie on one side of the diagonal",
+                (long long)i);
       prev = cl[p];
       l = std::max(l, lev[cl[p]]);
     }
@@ -170,8 +185,9 @@ int pksell_trsv_levels(const int64_t *rowptr, const int32_t *col, int64_t n, int
   return PKSELL_OK;
 }
 
-int pksell_trsv(const pksell_matrix *L, const int32_t *order, const int64_t *level_ptr,
-                int64_t n_levels, const float *b, float *y, void *stream) {
+int pksell_trsv(const pksell_matrix *L, int32_t upper, const int32_t *order,
+                const int64_t *level_ptr, int64_t n_levels, const float *b, float *y,
+                void *stream) {
   PKS_CHECK(L, PKSELL_EINVAL, "null matrix");
   PKS_CHECK(L->C == 1 && L->sigma == 1, PKSELL_EINVAL,
             "triangular solves need a CSR-packed matrix (C = 1, sigma = 1)");
@@ -200,19 +216,25 @@ int pksell_trsv(const pksell_matrix *L, const int32_t *order, const int64_t *lev
     PKS_CHECK(cnt >= 0 && s + cnt <= L->n, PKSELL_EINVAL, "level_ptr must ascend");
     if (cnt == 0) continue;
     const uint32_t g = (uint32_t)cdiv(cnt, kTrsvBlock);
+#define PKS_TRSV(F)                                                                   \
+  {                                                                                   \
+    if (upper) k_trsv_level<F, true><<<g, kTrsvBlock, 0, st>>>(a, order + s, (uint32_t)cnt); \
+    else k_trsv_level<F, false><<<g, kTrsvBlock, 0, st>>>(a, order + s, (uint32_t)cnt);      \
+  }
     switch (L->fmt) {
-      case PKSELL_FP16: k_trsv_level<PKSELL_FP16><<<g, kTrsvBlock, 0, st>>>(a, order + s, (uint32_t)cnt); break;
-      case PKSELL_E8MY: k_trsv_level<PKSELL_E8MY><<<g, kTrsvBlock, 0, st>>>(a, order + s, (uint32_t)cnt); break;
-      default: k_trsv_level<PKSELL_FIX><<<g, kTrsvBlock, 0, st>>>(a, order + s, (uint32_t)cnt); break;
+      case PKSELL_FP16: PKS_TRSV(PKSELL_FP16); break;
+      case PKSELL_E8MY: PKS_TRSV(PKSELL_E8MY); break;
+      default: PKS_TRSV(PKSELL_FIX); break;
     }
+#undef PKS_TRSV
     PKS_LAUNCHED();
   }
   return PKSELL_OK;
 }
 
 int pksell_trsv_csr(const int64_t *rowptr, const int32_t *col, const float *val, int64_t n,
-                    const int32_t *order, const int64_t *level_ptr, int64_t n_levels,
-                    const float *b, float *y, void *stream) {
+                    int32_t upper, const int32_t *order, const int64_t *level_ptr,
+                    int64_t n_levels, const float *b, float *y, void *stream) {
   PKS_CHECK(n >= 0 && n < (int64_t(1) << 30), PKSELL_ERANGE, "n must be in [0, 2^30)");
   if (n == 0) return PKSELL_OK;
   PKS_CHECK(rowptr && col && val && order && level_ptr && b && y, PKSELL_EINVAL,
@@ -224,8 +246,13 @@ int pksell_trsv_csr(const int64_t *rowptr, const int32_t *col, const float *val,
     const int64_t s = level_ptr[l], cnt = level_ptr[l + 1] - s;
     PKS_CHECK(cnt >= 0 && s + cnt <= n, PKSELL_EINVAL, "level_ptr must ascend");
     if (cnt == 0) continue;
-    k_trsv_csr_level<<<(uint32_t)cdiv(cnt, kTrsvBlock), kTrsvBlock, 0, st>>>(
-        rowptr, col, val, b, y, (uint32_t)n, order + s, (uint32_t)cnt);
+    const uint32_t g = (uint32_t)cdiv(cnt, kTrsvBlock);
+    if (upper)
+      k_trsv_csr_level<true><<<g, kTrsvBlock, 0, st>>>(rowptr, col, val, b, y, (uint32_t)n,
+                                                      order + s, (uint32_t)cnt);
+    else
+      k_trsv_csr_level<false><<<g, kTrsvBlock, 0, st>>>(rowptr, col, val, b, y, (uint32_t)n,
+                                                       order + s, (uint32_t)cnt);
     PKS_LAUNCHED();
   }
   return PKSELL_OK;

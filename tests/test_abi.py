@@ -219,16 +219,16 @@ def test_trsv_rejects_on_host():
         rc, desc, _ = _query(n=3, m=kw.pop("m", 3), **kw)
         assert rc == B.OK
         desc.offset = desc.pack = p
-        rc = L.pksell_trsv(ctypes.byref(desc), p, ctypes.cast(lp, ctypes.c_void_p), levels, p, p,
-                           None)
+        rc = L.pksell_trsv(ctypes.byref(desc), 0, p, ctypes.cast(lp, ctypes.c_void_p), levels, p,
+                           p, None)
         assert rc == B.EINVAL, kw
         assert L.pksell_last_error()
-    assert L.pksell_trsv_csr(p, p, p, 3, p, ctypes.cast(lp, ctypes.c_void_p), 1, p, p,
+    assert L.pksell_trsv_csr(p, p, p, 3, 0, p, ctypes.cast(lp, ctypes.c_void_p), 1, p, p,
                              None) == B.EINVAL
     nl = ctypes.c_int64(7)
     lp0 = (ctypes.c_int64 * 1)(5)
-    assert L.pksell_trsv_levels(None, None, 0, None, ctypes.cast(lp0, ctypes.c_void_p),
+    assert L.pksell_trsv_levels(None, None, 0, 0, None, ctypes.cast(lp0, ctypes.c_void_p),
                                 ctypes.byref(nl), None) == B.OK
     assert nl.value == 0 and lp0[0] == 0
-    assert L.pksell_trsv_levels(None, None, -1, None, ctypes.cast(lp0, ctypes.c_void_p),
+    assert L.pksell_trsv_levels(None, None, -1, 1, None, ctypes.cast(lp0, ctypes.c_void_p),
                                 ctypes.byref(nl), None) == B.ERANGE

@@ -1,5 +1,5 @@
-"""GPU parity for the level-scheduled lower-triangular solve on CSR-packed
-words (and its plain-CSR comparator).
+"""GPU parity for the level-scheduled triangular solves (lower and upper) on
+CSR-packed words (and their plain-CSR comparator).
 
 The level schedule (row order and level pointer) must equal the oracle's
 bit for bit.  Forward substitution in float32 is componentwise backward
@@ -19,7 +19,7 @@ from oracle import packcsr as PC
 from oracle import trsv as TR
 from paper_2604_13433_amd import binding as B
 from paper_2604_13433_amd import workloads as W
-from test_oracle_trsv import random_lower, tril_of
+from test_oracle_trsv import random_lower, transpose_of, tril_of
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -38,9 +38,9 @@ def bound(a):
     return k * U / (1 - k * U)
 
 
-def check_solve(a, fmt, D, seed=0, check_oracle=True):
-    S = B.TriangularSolve(a.rowptr, a.col, a.val, a.n, fmt, D, DEV)
-    order, ptr = TR.level_schedule(TR.levels(a.rowptr, a.col, a.n))
+def check_solve(a, fmt, D, seed=0, check_oracle=True, upper=False):
+    S = B.TriangularSolve(a.rowptr, a.col, a.val, a.n, fmt, D, DEV, upper=upper)
+    order, ptr = TR.level_schedule(TR.levels(a.rowptr, a.col, a.n, upper))
     assert S.n_levels == ptr.size - 1
     assert np.array_equal(S.level_ptr[: ptr.size], ptr)
     assert np.array_equal(S.order.cpu().numpy()[: a.n].astype(np.int64), order)
@@ -53,7 +53,7 @@ def check_solve(a, fmt, D, seed=0, check_oracle=True):
     assert backward_error(a, q, y, b.astype(np.float64)) <= bound(a)
     if check_oracle and fmt is not None:
         E = PC.encode(a.rowptr, a.col, a.val, a.n, a.n, FMTS[fmt], D)
-        ref = TR.solve(E, b.astype(np.float64))
+        ref = TR.solve(E, b.astype(np.float64), upper)
         assert np.max(np.abs(y - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
     return S, y
 
@@ -97,3 +97,25 @@ def test_edges():
     up = W.csr_from_triplets(2, 2, [0, 0, 1], [0, 1, 1], [1.0, 1.0, 1.0])  # upper entry
     with pytest.raises(B.PackSELLError):
         B.TriangularSolve(up.rowptr, up.col, up.val, 2, "fp16", 15, DEV)
+
+
+@pytest.mark.parametrize("fmt,D", [("fp16", 15), ("e8my", 5), ("fix", 18), (None, 0)])
+def test_random_upper(fmt, D):
+    for seed, (n, per_row) in enumerate([(300, 6), (5000, 12)]):
+        check_solve(transpose_of(random_lower(30 + seed, n, per_row)), fmt, D, seed, upper=True)
+
+
+def test_grid_laplacian_64_upper():
+    """Upper triangle of a 64^3 stencil: 190 levels, the grid walked from the
+    far corner."""
+    import scipy.sparse as sp
+
+    a = W.stencil((64, 64, 64), "star", 3, 0.5, "lap64")
+    M = sp.triu(sp.csr_matrix((a.val, a.col, a.rowptr), shape=(a.n, a.m))).tocsr()
+    M.sort_indices()
+    u = W.csr_from_triplets(a.n, a.n, np.repeat(np.arange(a.n), np.diff(M.indptr)), M.indices,
+                            M.data)
+    S, _ = check_solve(u, "e8my", 12, check_oracle=False, upper=True)
+    assert S.n_levels == 3 * 63 + 1
+    with pytest.raises(B.PackSELLError):  # the diagonal is first, not last
+        B.TriangularSolve(u.rowptr, u.col, u.val, u.n, "e8my", 12, DEV, upper=False)
