@@ -187,6 +187,10 @@ def main():
         if only and name not in only:
             continue
         built.append(add_packsell(name, fmt, D, mode))
+    if not only or "packed_csr_fp16" in only:
+        # the same words row after row (no slices): what SELL's slicing buys on a stencil
+        built.append(("packed_csr_fp16",
+                      B.encode_packed_csr(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 512, dev)))
     sells = []
     for name, dt in [("sell_fp32", torch.float32), ("sell_fp16", torch.float16),
                      ("sell_fp64", torch.float64)]:
@@ -756,6 +760,16 @@ def cpu_leg(args, a, x_np, results, H, torch):
                               x_np)[E.stored_rows]
             else:
                 full = L.spmv(a.rowptr, a.col, a.val.astype(np.float32).astype(np.float64), x_np)
+            den = L.inf_norm(a.rowptr, q) * np.abs(x_np).max()
+            den_a = L.inf_norm(a.rowptr, a.val) * np.abs(x_np).max()
+            errors[name] = {"vs_oracle_same_q": float(np.abs(y - ref).max() / den),
+                            "backward_error_eq5": float(np.abs(y - full).max() / den_a)}
+        elif name.startswith("packed_csr"):  # rows in their own order
+            A = r["A"]
+            fmt = F.FMT_FP16 if A.fmt == 0 else F.FMT_E8MY
+            q = P.quantized_values(a.rowptr, a.col, a.val, a.n, fmt, A.D)
+            ref = L.spmv(a.rowptr, a.col, q, x_np)
+            full = L.spmv(a.rowptr, a.col, a.val.astype(np.float32).astype(np.float64), x_np)
             den = L.inf_norm(a.rowptr, q) * np.abs(x_np).max()
             den_a = L.inf_norm(a.rowptr, a.val) * np.abs(x_np).max()
             errors[name] = {"vs_oracle_same_q": float(np.abs(y - ref).max() / den),
