@@ -125,20 +125,21 @@ def test_chunk_parameters_rejected():
                      split_words=chunk)
 
 
-def test_powerlaw_full_size_sampled_rows():
-    """The 1M-row power-law matrix (row lengths 1..5000) with FP16 words in
-    512-word chunks, as the benchmark runs it: plan against the oracle on
-    the whole matrix, products on 3000 sampled rows."""
+@pytest.mark.parametrize("fmt,D", [("fp16", 15), ("e8my", 12)])
+def test_powerlaw_full_size_sampled_rows(fmt, D):
+    """The 1M-row power-law matrix (row lengths 1..5000) with FP16 or E8M10
+    words in 512-word chunks, as the benchmark runs it: words and plan
+    against the oracle on the whole matrix, products on 3000 sampled rows."""
     a = W.m3_powerlaw()
-    A = B.encode_packed_csr(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 512, DEV)
-    E = PC.encode(a.rowptr, a.col, a.val, a.n, a.m, FMTS["fp16"], 15)
+    A = B.encode_packed_csr(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 512, DEV)
+    E = PC.encode(a.rowptr, a.col, a.val, a.n, a.m, FMTS[fmt], D)
     check_layout(A, E, 512)
     x = W.uniform_vector(a.m, 9).astype(np.float64)
     y = B.spmv(A, torch.from_numpy(x.astype(np.float32)).to(DEV)).cpu().numpy()
     rng = np.random.default_rng(10)
     lens = np.diff(a.rowptr)
     rows = np.unique(np.concatenate([rng.integers(0, a.n, 2000), np.argsort(lens)[-1000:]]))
-    q = P.quantized_values(a.rowptr, a.col, a.val, a.n, FMTS["fp16"], 15)
+    q = P.quantized_values(a.rowptr, a.col, a.val, a.n, FMTS[fmt], D)
     den = L.inf_norm(a.rowptr, q) * float(np.abs(x).max())
     for r in rows:
         s, e = a.rowptr[r], a.rowptr[r + 1]
