@@ -118,7 +118,8 @@ extern "C" {
  * padding, and offset is a word row pointer: delta-value packing in a
  * CSR-based layout, which the paper leaves to future work (sec. 6).  Set
  * split_words = T (256, 512 or 1024) after pksell_encode_query to give
- * pksell_spmv (k = 1) a product balanced over words: the word stream is
+ * pksell_spmv (k = 1, 2 or 4; k = 4 needs 16-byte aligned x) a product
+ * balanced over words: the word stream is
  * cut into n_units = ceil(n_words / T) chunks of T words, one per wave,
  * whatever rows they fall in.  The analyse phase sets n_units
  * (n_split_units = n_split_slices = 0); the caller then allocates
@@ -126,13 +127,14 @@ extern "C" {
  *                                 word c*T (units[n_units] = n)
  *   ckpt     uint32[n_units]      column reached before word c*T (the row's
  *                                 eq. 4 left offset when a row starts there)
- *   partial  float[3 * n_units]   scratch of pksell_spmv (one product at a
+ *   partial  float[9 * n_units]   scratch of pksell_spmv (one product at a
  *                                 time per matrix): pieces of the rows that
- *                                 cross chunk edges and those rows' indices
+ *                                 cross chunk edges (k per chunk and side)
+ *                                 and those rows' indices
  * and the fill phase writes units and ckpt.  pack must be 16-byte aligned
  * for these products.  Rows crossing chunk edges are summed piece by piece
  * in chunk order by a second kernel: results are deterministic.  Products
- * with k > 1 and the other entry points ignore the plan.
+ * with other k and the other entry points ignore the plan.
  */
 typedef struct pksell_matrix {
   int64_t n, m, nnz;

@@ -213,7 +213,7 @@ class PackSELLMatrix:
             return int(b)
         wb = 2 if d.fmt in W16 else 4  # bytes per word
         b = wb * d.n_words + 8 * (d.n_slices + 1) + 4 * d.m * k + 4 * d.n * k
-        chunked = d.C == 1 and d.split_words > 0 and k == 1
+        chunked = d.C == 1 and d.split_words > 0 and k in (1, 2, 4)
         if d.perm_mode == IMPLICIT and not chunked:  # rows stay in order: no perm read
             b += d.perm_bytes * d.n
         if d.fmt in (FIX, FIX16):
@@ -331,7 +331,7 @@ def encode(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, C: int = 6
     if desc.C == 1 and desc.split_words > 0 and desc.n_units > 0:  # CSR-packed chunk plan
         t["units"] = torch.empty(desc.n_units + 1, dtype=torch.int32, device=device)
         t["ckpt"] = torch.empty(desc.n_units, dtype=torch.int32, device=device)
-        t["partial"] = torch.empty(3 * desc.n_units, dtype=torch.float32, device=device)
+        t["partial"] = torch.empty(9 * desc.n_units, dtype=torch.float32, device=device)
     if desc.n_split_units > 0:
         t["units"] = torch.empty(4 * desc.n_units, dtype=torch.int32, device=device)
         t["splits"] = torch.empty(4 * desc.n_split_slices, dtype=torch.int32, device=device)

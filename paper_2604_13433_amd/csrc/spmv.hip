@@ -716,7 +716,7 @@ void launch_sell_pair(const pksell_sell *S, const void *x, void *y, const void *
 
 // 16-bit words (spmv16.hip).
 int spmv16(const pksell_matrix *A, const float *x, float *y, int64_t k, hipStream_t st);
-int spmv_chunks(const pksell_matrix *A, const float *x, float *y, hipStream_t st);
+int spmv_chunks(const pksell_matrix *A, const float *x, float *y, int64_t k, hipStream_t st);
 
 }  // namespace pksell
 
@@ -735,7 +735,8 @@ int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, voi
   if (A->n == 0) return PKSELL_OK;
   if (A->m == 0) return zero_f32(y, A->n * k, st);
   PKS_CHECK(x, PKSELL_EINVAL, "null x");
-  if (k == 1 && A->C == 1 && A->split_words > 0) return spmv_chunks(A, x, y, st);
+  if ((k == 1 || k == 2 || k == 4) && A->C == 1 && A->split_words > 0)
+    return spmv_chunks(A, x, y, k, st);
   SpmvArgs a = make_args(A, x, y, k);
   if (k == 1 && A->C == kWave && A->split_words > 0 && A->n_split_units > 0) {
     PKS_CHECK(A->units && A->splits && A->ckpt && A->partial, PKSELL_EINVAL,

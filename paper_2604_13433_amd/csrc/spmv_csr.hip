@@ -31,6 +31,7 @@
 //    chunk order.  Every sum has a fixed order: results are deterministic.
 #include "codec.hpp"
 #include "common.hpp"
+#include "rowdot.hpp"
 
 namespace pksell {
 
@@ -54,6 +55,7 @@ struct CsrArgs {
   int32_t *tail_row;  // n_chunks: that row, or -1
   int64_t n_words;
   uint32_t n, m, n_chunks, k_left;
+  uint32_t nr;  // right-hand sides (1, 2 or 4): x is m x nr, y n x nr, row-major
   int32_t D;
   Codec cd;
 };
@@ -99,7 +101,7 @@ __device__ inline void seg_scan_sum(bool f, float &s, uint32_t lane) {
   }
 }
 
-template <int FMT, int K>
+template <int FMT, int K, int NR>
 __global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
   constexpr uint32_t T = K * kWave;
   __shared__ uint32_t s_heads[kCsrWaves][kWave];  // bit j of word l: position l K + j is a head
@@ -125,7 +127,8 @@ __global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
     const int64_t s = a.rowptr[r], e = a.rowptr[r + 1];
     const uint64_t p = (uint64_t)(s - p0);
     if (s == e) {
-      a.y[r] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) a.y[(int64_t)r * NR + q] = 0.0f;
     } else if (p < T) {  // always, for a plan built by the encoder
       hrow[p] = r;
       atomicOr(&heads[p / K], 1u << (p % K));
@@ -183,55 +186,88 @@ __global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
   uint32_t col = ef ? ev : anchor + ev;
 
   // pass 2: columns, gathers, per-row sums in word order
-  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 4u);
-  const uint32_t oob = a.m * 4u;
-  float xv[K], val[K];
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * 4u * NR);
+  const uint32_t oob = a.m * 4u * NR;
+  float xv[K][NR], val[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const Unpacked u = unpack(w[j], a.cd);
     if ((hb >> j) & 1u) col = row_base(hrow[lane * K + j], a.k_left) + u.delta;
     else col += u.delta;
     val[j] = decode_value<FMT>(u.vbits);
-    xv[j] = buffer_load_f32(rx, (w[j] & 1u) ? col * 4u : oob);
+    const uint32_t off = (w[j] & 1u) ? col * 4u * NR : oob;
+    if constexpr (NR == 4) {
+      const f32x4 v4 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rx, off, 0, 0));
+      xv[j][0] = v4.x;
+      xv[j][1] = v4.y;
+      xv[j][2] = v4.z;
+      xv[j][3] = v4.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) xv[j][q] = buffer_load_f32(rx, off + 4u * q);
+    }
   }
-  float acc = 0.0f, lead = 0.0f;
+  // stores row r's NR sums
+  auto put = [&](uint32_t r, const float (&v)[NR]) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) a.y[(int64_t)r * NR + q] = row_scaled<FMT>(v[q], a, r);
+  };
+  float acc[NR], lead[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) acc[q] = lead[q] = 0.0f;
   bool open = false;
   uint32_t cur = 0;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     if ((hb >> j) & 1u) {
-      if (open) a.y[cur] = row_scaled<FMT>(acc, a, cur);  // a row inside the lane
-      else lead = acc;
-      acc = 0.0f;
+      if (open) put(cur, acc);  // a row inside the lane
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        if (!open) lead[q] = acc[q];
+        acc[q] = 0.0f;
+      }
       open = true;
       cur = hrow[lane * K + j];
     }
-    acc = fmaf(val[j], xv[j], acc);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = fmaf(val[j], xv[j][q], acc[q]);
   }
-  if (!open) lead = acc;
+  if (!open) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) lead[q] = acc[q];
+  }
 
   // the lanes' open sums: segmented by the same heads as the columns
-  float s = has_head ? acc : lead;
-  seg_scan_sum(has_head, s, lane);
-  float es = __shfl_up(s, 1, kWave);
-  if (lane == 0) es = 0.0f;
+  float s[NR], es[NR], total[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    s[q] = has_head ? acc[q] : lead[q];
+    seg_scan_sum(has_head, s[q], lane);
+    es[q] = __shfl_up(s[q], 1, kWave);
+    if (lane == 0) es[q] = 0.0f;
+    total[q] = es[q] + lead[q];
+  }
   if (has_head) {
     // the row that ends just before this lane's first head
-    const float total = es + lead;
-    if (ef) a.y[er] = row_scaled<FMT>(total, a, er);
-    else a.head_part[c] = total;  // continued from earlier chunks
+    if (ef) {
+      put(er, total);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) a.head_part[(int64_t)c * NR + q] = total[q];  // continued
+    }
   }
   if (lane == kWave - 1) {
     // f, s, rr: the chunk's last segment
-    if (closed) {
-      if (f) a.y[rr] = row_scaled<FMT>(s, a, rr);
-      else a.head_part[c] = s;
+    if (closed && f) {
+      put(rr, s);
       a.tail_row[c] = -1;
     } else if (f) {
-      a.tail_part[c] = s;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) a.tail_part[(int64_t)c * NR + q] = s[q];
       a.tail_row[c] = (int32_t)rr;
     } else {
-      a.head_part[c] = s;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) a.head_part[(int64_t)c * NR + q] = s[q];
       a.tail_row[c] = -1;
     }
   }
@@ -240,7 +276,7 @@ __global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
 // Rows that continue past the chunk where they start: the open piece of
 // that chunk plus the leading pieces of the following chunks, in chunk
 // order.
-template <int FMT>
+template <int FMT, int NR>
 __global__ void k_csr_rows_across(CsrArgs a, uint32_t T) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n_chunks) return;
@@ -248,35 +284,47 @@ __global__ void k_csr_rows_across(CsrArgs a, uint32_t T) {
   if (r < 0) return;
   const int64_t end = a.rowptr[r + 1];
   const uint32_t c_end = (uint32_t)min<int64_t>((end - 1) / T, a.n_chunks - 1);
-  float s = a.tail_part[c];
-  for (uint32_t k = c + 1; k <= c_end; ++k) s += a.head_part[k];
-  a.y[r] = row_scaled<FMT>(s, a, (uint32_t)r);
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    float s = a.tail_part[(int64_t)c * NR + q];
+    for (uint32_t k = c + 1; k <= c_end; ++k) s += a.head_part[(int64_t)k * NR + q];
+    a.y[(int64_t)r * NR + q] = row_scaled<FMT>(s, a, (uint32_t)r);
+  }
 }
 
-__global__ void k_csr_zero(float *y, int64_t n) {
+__global__ void k_csr_zero(float *y, int64_t n) {  // n = rows * right-hand sides
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = 0.0f;
 }
 
-template <int FMT>
-int launch_chunks(const CsrArgs &a, int K, hipStream_t st) {
+template <int FMT, int NR>
+int launch_chunks_nr(const CsrArgs &a, int K, hipStream_t st) {
   const uint32_t blocks = (uint32_t)cdiv(a.n_chunks, kCsrWaves);
   switch (K) {
-    case 4: k_csr_chunks<FMT, 4><<<blocks, kCsrBlock, 0, st>>>(a); break;
-    case 8: k_csr_chunks<FMT, 8><<<blocks, kCsrBlock, 0, st>>>(a); break;
-    default: k_csr_chunks<FMT, 16><<<blocks, kCsrBlock, 0, st>>>(a); break;
+    case 4: k_csr_chunks<FMT, 4, NR><<<blocks, kCsrBlock, 0, st>>>(a); break;
+    case 8: k_csr_chunks<FMT, 8, NR><<<blocks, kCsrBlock, 0, st>>>(a); break;
+    default: k_csr_chunks<FMT, 16, NR><<<blocks, kCsrBlock, 0, st>>>(a); break;
   }
   PKS_LAUNCHED();
-  k_csr_rows_across<FMT><<<cdiv(a.n_chunks, 256), 256, 0, st>>>(a, (uint32_t)(K * kWave));
+  k_csr_rows_across<FMT, NR><<<cdiv(a.n_chunks, 256), 256, 0, st>>>(a, (uint32_t)(K * kWave));
   PKS_LAUNCHED();
   return PKSELL_OK;
+}
+
+template <int FMT>
+int launch_chunks(const CsrArgs &a, int K, hipStream_t st) {
+  switch (a.nr) {
+    case 1: return launch_chunks_nr<FMT, 1>(a, K, st);
+    case 2: return launch_chunks_nr<FMT, 2>(a, K, st);
+    default: return launch_chunks_nr<FMT, 4>(a, K, st);
+  }
 }
 
 }  // namespace
 
 // y = A_q x for a CSR-packed matrix with a chunk plan (C = 1, sigma = 1,
-// split_words = T); called by pksell_spmv for k = 1.
-int spmv_chunks(const pksell_matrix *A, const float *x, float *y, hipStream_t st) {
+// split_words = T); called by pksell_spmv for k = 1, 2 or 4.
+int spmv_chunks(const pksell_matrix *A, const float *x, float *y, int64_t k, hipStream_t st) {
   const int64_t T = A->split_words;
   PKS_CHECK(A->C == 1 && A->sigma == 1 && (T == 256 || T == 512 || T == 1024), PKSELL_EINVAL,
             "chunked products need C = 1, sigma = 1 and split_words 256, 512 or 1024");
@@ -286,8 +334,11 @@ int spmv_chunks(const pksell_matrix *A, const float *x, float *y, hipStream_t st
             "chunked products need units, ckpt and partial");
   PKS_CHECK(((uintptr_t)A->pack & 15) == 0, PKSELL_EINVAL,
             "chunked products need 16-byte aligned words");
+  PKS_CHECK(k == 1 || k == 2 || k == 4, PKSELL_EINVAL, "chunked products take k = 1, 2 or 4");
+  PKS_CHECK(k != 4 || ((uintptr_t)x & 15) == 0, PKSELL_EINVAL,
+            "chunked products with k = 4 need 16-byte aligned x");
   if (A->n_units == 0) {  // no words: every row is empty
-    k_csr_zero<<<cdiv(A->n, 256), 256, 0, st>>>(y, A->n);
+    k_csr_zero<<<cdiv(A->n * k, 256), 256, 0, st>>>(y, A->n * k);
     PKS_LAUNCHED();
     return PKSELL_OK;
   }
@@ -300,8 +351,9 @@ int spmv_chunks(const pksell_matrix *A, const float *x, float *y, hipStream_t st
   a.x = x;
   a.y = y;
   a.head_part = A->partial;
-  a.tail_part = A->partial + A->n_units;
-  a.tail_row = reinterpret_cast<int32_t *>(A->partial + 2 * A->n_units);
+  a.tail_part = A->partial + k * A->n_units;
+  a.tail_row = reinterpret_cast<int32_t *>(A->partial + 2 * k * A->n_units);
+  a.nr = (uint32_t)k;
   a.n_words = A->n_words;
   a.n = (uint32_t)A->n;
   a.m = (uint32_t)A->m;

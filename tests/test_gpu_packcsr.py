@@ -105,7 +105,7 @@ def test_edges():
         assert A.n_words == 0 and A.desc.n_units == 0
         y = B.spmv(A, torch.ones(m, device=DEV), torch.full((n,), 7.0, device=DEV))
         assert not y.any()
-    # k > 1 takes the one-row-slice product (no chunk plan): same values
+    # k = 3 takes the one-row-slice product (no chunk plan): same values
     a = hollow(8)
     A, E = both(a, "e8my", 9, 512)
     x = np.random.default_rng(4).uniform(-1, 1, (a.m, 3))
@@ -167,3 +167,23 @@ def test_adjoint_and_value_gradients_on_packed_csr():
     gv = B.grad_values(A, rp, torch.from_numpy(g).to(DEV), torch.from_numpy(x).to(DEV))
     want = (g[a.rows()] * x[a.col]).astype(np.float32)
     assert np.array_equal(gv.cpu().numpy()[: a.nnz], want)
+
+
+@pytest.mark.parametrize("k", [2, 4])
+@pytest.mark.parametrize("fmt,D", [("fp16", 15), ("fix", 20)])
+def test_several_right_hand_sides(fmt, D, k):
+    """k = 2 and 4 run the chunk product on k columns at once (x m x k, y
+    n x k, row-major): each column equals the oracle's product, and the
+    result repeats bit for bit."""
+    for si, a in enumerate([hollow(13), W.powerlaw(20_000, seed=2)]):
+        A, E = both(a, fmt, D, 256)
+        x = np.random.default_rng(20 + si).uniform(-1, 1, (a.m, k)).astype(np.float32)
+        xt = torch.from_numpy(x).to(DEV)
+        y = B.spmv(A, xt)
+        assert torch.equal(y, B.spmv(A, xt))
+        y = y.cpu().numpy().astype(np.float64)
+        q = P.quantized_values(a.rowptr, a.col, a.val, a.n, FMTS[fmt], D)
+        for j in range(k):
+            ref = PC.spmv(E, x[:, j].astype(np.float64))
+            den = L.inf_norm(a.rowptr, q) * float(np.abs(x[:, j]).max())
+            assert float(np.max(np.abs(y[:, j] - ref))) / den <= SPMV_TOL, (si, j)
