@@ -416,6 +416,20 @@ def powerlaw_leg(args, torch, B, W):
             res[name].update(split_words=J, units=A.n_units, split_units=A.n_split_units)
         log(f"[bench] powerlaw {name}: {res[name]}")
         del A
+    # four right-hand sides through the chunk product: one 16-byte gather per word
+    A = B.encode_packed_csr(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 512, dev)
+    per = A.bytes_per_spmv(4)
+    R = max(2, int(math.ceil(args.replica_bytes / per)))
+    reps = [A] + [A.replicate() for _ in range(R - 1)]
+    xs = [torch.rand((a.m, 4), device=dev) * 2 - 1 for _ in range(R)]
+    ys = [torch.empty((a.n, 4), device=dev) for _ in range(R)]
+    ms = Timed(torch, lambda i: B.spmv(reps[i], xs[i], ys[i]), R, min(args.steps, 200),
+               min(args.warmup, 20)).run()
+    res["packed_csr_fp16_chunk512_k4"] = {"us": round(ms * 1e3, 2),
+                                          "us_per_rhs": round(ms * 1e3 / 4, 2),
+                                          "GB/s": round(per / (ms * 1e-3) / 1e9, 1)}
+    log(f"[bench] powerlaw packed_csr_fp16_chunk512_k4: {res['packed_csr_fp16_chunk512_k4']}")
+    del reps, xs, ys, A
     S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 65536, B.EXPLICIT, dev)
     ms, per, R = time_variant(args, torch, B, S, a.m, a.n)
     res["sell_fp32"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
