@@ -8,8 +8,8 @@ Precision-Agnostic High-Performance SpMV, Suzuki & Iwashita):
   word codec (sec. 4.2, the packing/unpacking listing and its two examples).
 * ``packsell`` -- the encoder (delta encoding eq. 2 with the block-uniform
   left offset eq. 4, dummy insertion and SELL-C-sigma alignment, sec. 4.1 and
-  4.3), the decoder, and the PackSELL SpMV algorithm of sec. 4.4 executed as
-  written, in float64.
+  4.3), the decoder, and the product of sec. 4.4 as a row-by-row decode
+  followed by a float64 dot product.
 * ``linalg``   -- float64 CSR SpMV / transposed SpMV / value gradients (the
   plain definitions y = A_q x), textbook CG and the inner-outer CG of
   sec. 5.2.2.

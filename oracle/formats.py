@@ -82,46 +82,47 @@ def fp16_value_bits_scalar(v: float) -> int:
 # E8MY (sec. 4.2.2, second example)
 # ---------------------------------------------------------------------------
 
-def e8my_value_bits(v32: np.ndarray, D: int) -> np.ndarray:
-    """FP32 -> E8MY value field following the paper's conversion: take the
-    binary exponent e of v (v = f * 2^e, 1/2 <= |f| < 1), set
-    scale = 2^(e - 24 + D + 1), round v / scale to the nearest integer with
-    ties away from zero, multiply back by scale, and clear the low D + 1 bits
-    of the FP32 pattern.  Every step is exact in float64 for normal float32
-    inputs, so the float64 evaluation equals the float32 one; a result of
-    2^128 or more becomes +-inf as the float32 product would.
+def e8my_grid_neighbours(v32: np.ndarray, D: int):
+    """The two E8MY values that enclose each float32 v (sec. 4.2.2): E8MY
+    holds the float32 values whose low D + 1 pattern bits are zero, so the
+    neighbour toward zero has those bits cleared and the one away from zero
+    is the next such pattern (possibly the infinity pattern)."""
+    b = np.asarray(v32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    low = np.uint64((1 << (D + 1)) - 1)
+    toward = b & ~low & np.uint64(0xFFFFFFFF)
+    sign = toward & np.uint64(0x80000000)
+    mag = (toward & np.uint64(0x7FFFFFFF)) + np.uint64(1 << (D + 1))
+    away = sign | np.minimum(mag, np.uint64(0x7F800000))
+    return toward.astype(np.uint32), away.astype(np.uint32)
 
-    Readings where the paper's conversion is not usable as written:
-    subnormal inputs (|v| < 2^-126) round to the nearest multiple of
-    2^(D + 1 - 149) with ties away from zero (the same rule on the subnormal
-    grid); +-0 and +-inf are kept; NaN becomes 0x7FC00000.
+
+def e8my_value_bits(v32: np.ndarray, D: int) -> np.ndarray:
+    """float32 -> E8MY value field (Y = 22 - D, sec. 4.2.2): the nearest
+    E8MY value, ties away from zero (the conversion rounds with C's round).
+
+    Distances to the two neighbours are exact in float64; the infinity
+    pattern stands for 2^128, the first value past the float32 range, so a
+    value at or past the midpoint above the largest finite E8MY value
+    becomes infinity.  Readings: the same rule on the subnormal grid; +-0
+    and +-inf kept; NaN -> 0x7FC00000.
     """
     if not (1 <= D <= 22):
         raise ValueError("E8MY needs 1 <= D <= 22")
     v32 = np.asarray(v32, dtype=np.float32)
-    v = v32.astype(np.float64)
-    out = np.zeros(v.shape, dtype=np.float32)
-    finite = np.isfinite(v)
-    normal = finite & (np.abs(v) >= 2.0 ** -126)
-    sub = finite & ~normal & (v != 0)
-    if normal.any():
-        _, e = np.frexp(v[normal])
-        scale = np.ldexp(1.0, e - 24 + D + 1)
-        r = _round_half_away(v[normal] / scale) * scale
-        with np.errstate(over="ignore"):
-            out[normal] = r.astype(np.float32)
-    if sub.any():
-        grid = 2.0 ** (D + 1 - 149)
-        out[sub] = (_round_half_away(v[sub] / grid) * grid).astype(np.float32)
-    zero = v == 0
-    out[zero] = v32[zero]
-    inf = np.isinf(v)
-    out[inf] = v32[inf]
-    bits = out.view(np.uint32).copy()
-    keep = np.uint32((0xFFFFFFFF >> (D + 1)) << (D + 1))
-    bits &= keep
-    bits[np.isnan(v)] = 0x7FC00000
-    return bits
+    toward, away = e8my_grid_neighbours(v32, D)
+
+    def magnitude(bits):
+        m = np.abs(bits.view(np.float32).astype(np.float64))
+        return np.where((bits & np.uint32(0x7FFFFFFF)) == 0x7F800000, 2.0 ** 128, m)
+
+    a = np.abs(v32.astype(np.float64))
+    with np.errstate(invalid="ignore"):
+        d_toward = a - magnitude(toward)
+        d_away = magnitude(away) - a
+        out = np.where(d_away <= d_toward, away, toward).astype(np.uint32)
+    out[np.isinf(v32)] = v32.view(np.uint32)[np.isinf(v32)]
+    out[np.isnan(v32)] = 0x7FC00000
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -176,16 +177,14 @@ def pack_delta_word(delta: np.ndarray) -> np.ndarray:
 
 
 def unpack_word(p: np.ndarray, D: int):
-    """Branch-free unpacking as in sec. 4.2.1: flag = p & 1;
-    shift = (31 - D) * flag; delta = (p << shift) >> (shift + 1) in 32-bit
-    unsigned arithmetic; value field = p AND (NOT(2^(D+1) - 1) times flag),
-    i.e. zero for flag-0 words.  Returns (flag, delta, value_bits)."""
-    p = np.asarray(p, dtype=np.uint32).astype(np.uint64)
-    flag = p & np.uint64(1)
-    shift = (np.uint64(31 - D)) * flag
-    delta = ((p << shift) & np.uint64(0xFFFFFFFF)) >> (shift + np.uint64(1))
-    mask = np.uint64((~((1 << (D + 1)) - 1)) & 0xFFFFFFFF)
-    value_bits = p & ((mask * flag) & np.uint64(0xFFFFFFFF))
+    """(flag, delta, value_bits) of 32-bit words (sec. 4.2.1): bit 0 is the
+    flag; a flag-1 word has its delta in bits 1..D and its value field in
+    bits D+1..31, a flag-0 word its delta in bits 1..31 and no value."""
+    p = np.asarray(p, dtype=np.uint32)
+    flag = p & np.uint32(1)
+    one = flag == 1
+    delta = np.where(one, (p >> np.uint32(1)) & np.uint32((1 << D) - 1), p >> np.uint32(1))
+    value_bits = np.where(one, p & np.uint32((0xFFFFFFFF << (D + 1)) & 0xFFFFFFFF), np.uint32(0))
     return flag.astype(np.uint32), delta.astype(np.uint32), value_bits.astype(np.uint32)
 
 

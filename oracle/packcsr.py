@@ -1,5 +1,5 @@
-"""CSR-based delta-value packing and its chunk plan (oracle; test
-infrastructure only, never called by the product path).
+"""CSR-based delta-value packing (oracle; test infrastructure only, never
+called by the product path).
 
 The paper names extending its delta-value packing to CSR-based formats as
 future work (sec. 6), for matrices whose row lengths vary so much that
@@ -9,16 +9,6 @@ one dummy before a delta that does not fit, sec. 4.3), stored row after row
 with no padding and no row sort, and a word row pointer in place of slice
 offsets.  Every row's first delta is taken from its eq. 4 left offset with
 a window of one row (row i - k_left when k_left < i, else 0).
-
-A product balanced over words cuts the word stream into chunks of T
-consecutive words, whatever rows they fall in.  Its plan per chunk c:
-
-  lo[c]      the first row whose words start at or after word c*T, for
-             c < n_chunks; lo[n_chunks] = n (the last chunk also owns the
-             empty rows that start at the end of the stream);
-  anchor[c]  the running column before word c*T: the left offset of the
-             row when a row starts there, else the column its row has
-             reached after the words before c*T.
 """
 from __future__ import annotations
 
@@ -115,23 +105,6 @@ def columns_after(E: PackedCSR) -> np.ndarray:
     total = np.cumsum(d.astype(np.int64))
     before_row = np.concatenate([[0], total])[E.wrowptr[:-1]]  # deltas of earlier rows
     return left_offset(r, E.k_left) + total - before_row[r]
-
-
-def chunk_plan(E: PackedCSR, T: int):
-    """(lo, anchor) for chunks of T words (see the module docstring)."""
-    n_chunks = -(-E.n_words // T)
-    starts = np.arange(n_chunks, dtype=np.int64) * T
-    lo = np.empty(n_chunks + 1, dtype=np.int64)
-    lo[:n_chunks] = np.searchsorted(E.wrowptr[:-1], starts, side="left")
-    lo[n_chunks] = E.n
-    anchor = np.zeros(n_chunks, dtype=np.int64)
-    if n_chunks:
-        after = columns_after(E)
-        r = word_rows(E)[starts]
-        head = E.wrowptr[r] == starts
-        anchor[head] = left_offset(r[head], E.k_left)
-        anchor[~head] = after[starts[~head] - 1]
-    return lo, anchor
 
 
 def spmv(E: PackedCSR, x: np.ndarray) -> np.ndarray:

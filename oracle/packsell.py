@@ -171,103 +171,97 @@ def encode(rowptr, col, val, n: int, m: int, fmt: int, D: int, C: int,
                    cnt=cnt, row_exp=row_exp)
 
 
-def spmv_algorithm(E: Encoded, x: np.ndarray, return_trace: bool = False):
-    """The PackSELL SpMV of sec. 4.4, executed as written in float64.
-
-    For every stored row i: c = dfrak_i (eq. 4); i' = floor(i/sigma)*sigma +
-    perm_i; k = floor(i/C); l = i mod C; s = offset_k;
-    w = (offset_{k+1} - s)/C; t = 0; for j < w: unpack pack[s + j*C + l] to
-    (v, d); c += d; t += v * x_c.  Then y_{i'} = t (implicit mode) or
-    y_i = t (explicit mode).  All rows advance together, one j at a time.
-
-    Readings: flag-0 words carry value 0 and their product is skipped, so a
-    padding word never reads x (its column can lie past m for empty rows);
-    FIX rows multiply t by 2^e_row at the end.
-
-    With ``return_trace`` also returns the column reconstructed at every word
-    position (int64[n_words]) and every decoded value (float64[n_words]).
-    """
-    n, C, sigma = E.n, E.C, E.sigma
-    x = np.asarray(x, dtype=np.float64)
+def row_words(offset, n: int, C: int):
+    """Word positions of every stored row, row after row (sec. 3): stored
+    row i is lane l = i mod C of slice k = floor(i/C), and its word j < w_k
+    sits at offset_k + j*C + l.  Returns (row, position, row start) with
+    row start[i] the index of row i's first word in that listing."""
     i = np.arange(n, dtype=np.int64)
-    c = left_offsets(n, sigma, E.k_left)  # block-uniform, same for i and i'
-    k = i // C
-    l = i % C
-    s = E.offset[k]
-    w = (E.offset[k + 1] - s) // C
-    t = np.zeros(n, dtype=np.float64)
-    cols = np.zeros(E.n_words, dtype=np.int64) if return_trace else None
-    vals = np.zeros(E.n_words, dtype=np.float64) if return_trace else None
-    active = np.nonzero(w > 0)[0]
-    j = 0
-    while active.size:
-        p_idx = s[active] + j * C + l[active]
-        flag, d, vb = F.unpack_word(E.pack[p_idx], E.D)
-        v = F.value_from_bits(vb, E.fmt, E.D)
-        c[active] += d.astype(np.int64)
-        has = flag == 1
-        prod = np.zeros(active.size)
-        prod[has] = v[has] * x[c[active][has]]
-        t[active] += prod
-        if return_trace:
-            cols[p_idx] = c[active]
-            vals[p_idx] = v
-        j += 1
-        active = active[w[active] > j]
+    k, l = i // C, i % C
+    w = (offset[k + 1] - offset[k]) // C
+    start = np.zeros(n + 1, dtype=np.int64)
+    start[1:] = np.cumsum(w)
+    row = np.repeat(i, w)
+    j = np.arange(int(start[-1]), dtype=np.int64) - start[row]
+    return row, offset[k[row]] + j * C + l[row], start
+
+
+def row_columns(delta, row, start, left):
+    """Column at every word: the row's left offset (eq. 4) plus the running
+    sum of its deltas up to and including the word (sec. 4.4)."""
+    run = np.cumsum(np.asarray(delta, dtype=np.int64))
+    before = np.concatenate([[0], run])[start[:-1]]  # deltas of the rows before
+    return left[row] + run - before[row]
+
+
+def decode_rows(E: Encoded):
+    """Every stored row's words, decoded (sec. 4.2.1, sec. 4.4).
+
+    Stored row i sits in slice k = floor(i/C) at lane l = i mod C; its word
+    j < w_k is pack[offset_k + j*C + l] (sec. 3).  Its columns are the left
+    offset of eq. 4 plus the running sum of the row's deltas; a flag-1 word
+    is an entry (decoded value, times 2^e_row for FIX), a flag-0 word only
+    moves the column.  Returns, per word in row-major order (stored row,
+    then j): stored row, word position, flag, column, value.
+    """
+    n = E.n
+    row, pos, start = row_words(E.offset, n, E.C)
+    flag, delta, vbits = F.unpack_word(E.pack[pos], E.D)
+    col = row_columns(delta, row, start, left_offsets(n, E.sigma, E.k_left))
+    val = np.where(flag == 1, F.value_from_bits(vbits, E.fmt, E.D), 0.0)
     if E.fmt == F.FMT_FIX:
-        t = np.ldexp(t, E.row_exp)
+        val = np.ldexp(val, E.row_exp[row])
+    return row, pos, flag, col, val
+
+
+def spmv_algorithm(E: Encoded, x: np.ndarray, return_trace: bool = False):
+    """y = A_q x through the format (sec. 4.4): decode each stored row, then
+    take its dot product with x over its flag-1 words, in float64.  The
+    result goes to row floor(i/sigma)*sigma + perm_i (implicit mode) or to
+    stored row i (explicit mode).  Flag-0 words read no x (a padding word's
+    column may lie past m).
+
+    With ``return_trace`` also returns the column and the value decoded at
+    every word position (int64[n_words], float64[n_words]; phantom rows past
+    n stay 0).
+    """
+    n = E.n
+    x = np.asarray(x, dtype=np.float64)
+    row, pos, flag, col, val = decode_rows(E)
+    has = flag == 1
+    prod = np.zeros(row.size)
+    prod[has] = val[has] * x[col[has]]
+    t = np.bincount(row, weights=prod, minlength=n)[:n] if n else np.zeros(0)
     y = np.zeros(n, dtype=np.float64)
     if E.perm_mode == PERM_IMPLICIT:
-        y[(i // sigma) * sigma + E.perm.astype(np.int64)] = t
+        i = np.arange(n, dtype=np.int64)
+        y[(i // E.sigma) * E.sigma + E.perm.astype(np.int64)] = t
     else:
         y[:] = t
     if return_trace:
-        # padding words of slices' phantom rows (>= n) decode as delta 0
+        cols = np.zeros(E.n_words, dtype=np.int64)
+        vals = np.zeros(E.n_words, dtype=np.float64)
+        cols[pos] = col
+        if E.fmt == F.FMT_FIX:  # the trace holds the field value, unscaled
+            vals[pos] = np.ldexp(val, -E.row_exp[row])
+        else:
+            vals[pos] = val
         return y, cols, vals
     return y
 
 
 def decode_csr(E: Encoded):
-    """Decoder: recover (rowptr, col, value) of A_q in the original row order
-    from the encoded arrays only, by replaying the word stream of every
-    stored row (flag-1 words are entries, flag-0 words only move c)."""
-    n, C, sigma = E.n, E.C, E.sigma
+    """Decoder: (rowptr, col, value) of A_q in the original row order from
+    the encoded arrays only (the flag-1 words of each row, in word order)."""
+    n = E.n
+    row, _, flag, col, val = decode_rows(E)
+    has = flag == 1
     i = np.arange(n, dtype=np.int64)
-    orig = (i // sigma) * sigma + E.perm.astype(np.int64)
-    c = left_offsets(n, sigma, E.k_left)
-    k = i // C
-    l = i % C
-    s = E.offset[k]
-    w = (E.offset[k + 1] - s) // C
-    ent_r, ent_j, ent_c, ent_v = [], [], [], []
-    active = np.nonzero(w > 0)[0]
-    j = 0
-    while active.size:
-        flag, d, vb = F.unpack_word(E.pack[s[active] + j * C + l[active]], E.D)
-        c[active] += d.astype(np.int64)
-        has = flag == 1
-        ent_r.append(orig[active][has])
-        ent_j.append(np.full(int(has.sum()), j))
-        ent_c.append(c[active][has])
-        v = F.value_from_bits(vb[has], E.fmt, E.D)
-        if E.fmt == F.FMT_FIX:
-            v = np.ldexp(v, E.row_exp[active][has])
-        ent_v.append(v)
-        j += 1
-        active = active[w[active] > j]
-    if ent_r:
-        r = np.concatenate(ent_r)
-        jj = np.concatenate(ent_j)
-        cc = np.concatenate(ent_c)
-        vv = np.concatenate(ent_v)
-    else:
-        r = jj = cc = np.zeros(0, np.int64)
-        vv = np.zeros(0)
-    order = np.lexsort((jj, r))
-    r, cc, vv = r[order], cc[order], vv[order]
+    orig = ((i // E.sigma) * E.sigma + E.perm.astype(np.int64))[row[has]]
+    order = np.argsort(orig, kind="stable")  # keeps word order inside a row
     rowptr = np.zeros(n + 1, dtype=np.int64)
-    np.add.at(rowptr, r + 1, 1)
-    return np.cumsum(rowptr), cc, vv
+    np.add.at(rowptr, orig + 1, 1)
+    return np.cumsum(rowptr), col[has][order], val[has][order]
 
 
 def quantized_values(rowptr, col, val, n: int, fmt: int, D: int) -> np.ndarray:

@@ -36,6 +36,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from .packsell import row_columns, row_words
+
 W = 16
 FMT_E5MY = 4
 FMT_FIX16 = 5
@@ -261,33 +263,24 @@ def encode(rowptr, col, val, n: int, m: int, fmt: int, D: int, C: int, sigma: in
 
 
 def spmv(E: Encoded16, x: np.ndarray) -> np.ndarray:
-    """sec. 4.4 in float64: every stored row walks its words from its left
-    offset, adds the deltas and accumulates value * x[column] for flag-1
-    words; FIX16 rows are scaled by 2^e_row at the end; y is written in the
+    """y = A_q x through the format (sec. 4.4), in float64: decode each
+    stored row's words (columns from the eq. 4 left offset plus the running
+    deltas), then take the dot product of its flag-1 values with x; y in the
     original order (implicit) or in stored order (explicit)."""
     x = np.asarray(x, np.float64)
-    n, C = E.n, E.C
-    i = np.arange(n, dtype=np.int64)
-    c = left_offsets(n, E.sigma, E.k_left)
-    k, l = i // C, i % C
-    s = E.offset[k]
-    w = (E.offset[k + 1] - s) // C
-    t = np.zeros(n)
-    active = np.nonzero(w > 0)[0]
-    j = 0
-    while active.size:
-        flag, d, vb = unpack_word(E.pack[s[active] + j * C + l[active]], E.D)
-        c[active] += d
-        has = flag == 1
-        prod = np.zeros(active.size)
-        prod[has] = value_from_bits(vb[has], E.fmt, E.D) * x[c[active][has]]
-        t[active] += prod
-        j += 1
-        active = active[w[active] > j]
+    n = E.n
+    row, pos, start = row_words(E.offset, n, E.C)
+    flag, delta, vb = unpack_word(E.pack[pos], E.D)
+    col = row_columns(delta, row, start, left_offsets(n, E.sigma, E.k_left))
+    has = flag == 1
+    prod = np.zeros(row.size)
+    prod[has] = value_from_bits(vb[has], E.fmt, E.D) * x[col[has]]
+    t = np.bincount(row, weights=prod, minlength=n)[:n] if n else np.zeros(0)
     if E.fmt == FMT_FIX16:
         t = np.ldexp(t, E.row_exp)
     y = np.zeros(n)
     if E.perm_mode == PERM_IMPLICIT:
+        i = np.arange(n, dtype=np.int64)
         y[(i // E.sigma) * E.sigma + E.perm] = t
     else:
         y[:] = t

@@ -9,13 +9,10 @@ builds its E8MY format by giving the low D + 1 bits of the FP32 pattern to
 the delta and the flag.  Here the same construction is applied to FP64
 (our reading, since the paper spells it out for W = 32 only): with W = 64
 the value is an E11MY float, the FP64 pattern with Y = 51 - D mantissa bits,
-so 1 <= D <= 51.  Conversion follows the E8MY steps with the FP64 constants:
-v = f * 2^e (1/2 <= |f| < 1), scale = 2^(e - 53 + D + 1), round v / scale to
-the nearest integer with ties away from zero, multiply back.  Every step is
-exact in float64 for normal doubles.  Readings as for E8MY: subnormals
-(|v| < 2^-1022) round on the grid 2^(D + 1 - 1074), ties away from zero;
-+-0 and +-inf are kept; NaN becomes the canonical quiet NaN
-0x7FF8000000000000; a result past the largest finite double becomes +-inf.
+so 1 <= D <= 51, rounded to nearest with ties away from zero as E8MY is.
+Readings as for E8MY: the same rule on the subnormal grid; +-0 and +-inf
+are kept; NaN becomes the canonical quiet NaN 0x7FF8000000000000; a value
+past the midpoint above the largest finite E11MY value becomes +-inf.
 
 The encoder follows the same steps E0 - E8 as the 32-bit oracle
 (oracle/packsell.py), written again here for 64-bit words: lower bandwidth
@@ -29,36 +26,46 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from .packsell import row_columns, row_words
+
 W = 64
 PERM_EXPLICIT = 0
 PERM_IMPLICIT = 1
 
 
 def e11my_value_bits(v: np.ndarray, D: int) -> np.ndarray:
-    """float64 -> E11MY value field (uint64, low D + 1 bits zero)."""
+    """float64 -> E11MY value field (uint64, low D + 1 bits zero): the
+    nearest float64 value whose low D + 1 pattern bits are zero, ties away
+    from zero, as E8MY rounds float32 (sec. 4.2.2).
+
+    The two candidates are the pattern with those bits cleared (toward zero)
+    and the next such pattern (away from zero; the infinity pattern past the
+    largest finite value, standing for 2^1024).  Both distances are exact in
+    float64 (Sterbenz); next to 2^1024 they are compared halved.  +-0 and
+    +-inf are kept; NaN becomes 0x7FF8000000000000.
+    """
     if not (1 <= D <= 51):
         raise ValueError("E11MY needs 1 <= D <= 51")
     v = np.asarray(v, dtype=np.float64)
-    out = np.zeros(v.shape, dtype=np.float64)
-    finite = np.isfinite(v)
-    normal = finite & (np.abs(v) >= 2.0 ** -1022)
-    sub = finite & ~normal & (v != 0)
-    if normal.any():
-        _, e = np.frexp(v[normal])
-        scale = np.ldexp(1.0, e - 53 + D + 1)
-        with np.errstate(over="ignore"):
-            out[normal] = np.sign(v[normal]) * np.floor(np.abs(v[normal] / scale) + 0.5) * scale
-    if sub.any():
-        grid = 2.0 ** (D + 1 - 1074)
-        out[sub] = np.sign(v[sub]) * np.floor(np.abs(v[sub] / grid) + 0.5) * grid
-    zero = v == 0
-    out[zero] = v[zero]
-    inf = np.isinf(v)
-    out[inf] = v[inf]
-    bits = out.view(np.uint64).copy()
-    bits &= np.uint64(((1 << 64) - 1) >> (D + 1) << (D + 1))
-    bits[np.isnan(v)] = np.uint64(0x7FF8000000000000)
-    return bits
+    b = v.view(np.uint64)
+    low = np.uint64((1 << (D + 1)) - 1)
+    sign_bit = np.uint64(1 << 63)
+    inf_pat = np.uint64(0x7FF0000000000000)
+    toward = b & ~low
+    sign = toward & sign_bit
+    tmag = toward & ~sign_bit
+    amag = np.minimum(tmag + np.uint64(1 << (D + 1)), inf_pat)
+    away = sign | amag
+    a = np.abs(v)
+    t = tmag.view(np.float64)
+    over = amag == inf_pat
+    with np.errstate(invalid="ignore", over="ignore"):
+        d_toward = np.where(over, 0.5 * a - 0.5 * t, a - t)
+        d_away = np.where(over, 2.0 ** 1023 - 0.5 * a, amag.view(np.float64) - a)
+        out = np.where(d_away <= d_toward, away, toward)
+    out = np.where(np.isinf(v), b, out)
+    out = np.where(np.isnan(v), np.uint64(0x7FF8000000000000), out)
+    return out.astype(np.uint64)
 
 
 def quantized(v: np.ndarray, D: int) -> np.ndarray:
@@ -168,31 +175,22 @@ def encode(rowptr, col, val, n: int, m: int, D: int, C: int, sigma: int,
 
 
 def spmv(E: Encoded64, x: np.ndarray) -> np.ndarray:
-    """sec. 4.4 in float64: every stored row walks its words from its left
-    offset, adds the deltas and accumulates value * x[column] for flag-1
-    words (all rows advance one word at a time); y is written in the
+    """y = A_q x through the format (sec. 4.4), in float64: decode each
+    stored row's words (columns from the eq. 4 left offset plus the running
+    deltas), then take the dot product of its flag-1 values with x; y in the
     original order (implicit) or in stored order (explicit)."""
     x = np.asarray(x, np.float64)
-    n, C = E.n, E.C
-    i = np.arange(n, dtype=np.int64)
-    c = left_offsets(n, E.sigma, E.k_left)
-    k, l = i // C, i % C
-    s = E.offset[k]
-    w = (E.offset[k + 1] - s) // C
-    t = np.zeros(n)
-    active = np.nonzero(w > 0)[0]
-    j = 0
-    while active.size:
-        flag, d, vb = unpack_word(E.pack[s[active] + j * C + l[active]], E.D)
-        c[active] += d.astype(np.int64)
-        has = flag == 1
-        prod = np.zeros(active.size)
-        prod[has] = vb[has].view(np.float64) * x[c[active][has]]
-        t[active] += prod
-        j += 1
-        active = active[w[active] > j]
+    n = E.n
+    row, pos, start = row_words(E.offset, n, E.C)
+    flag, delta, vb = unpack_word(E.pack[pos], E.D)
+    col = row_columns(delta, row, start, left_offsets(n, E.sigma, E.k_left))
+    has = flag == 1
+    prod = np.zeros(row.size)
+    prod[has] = vb[has].view(np.float64) * x[col[has]]
+    t = np.bincount(row, weights=prod, minlength=n)[:n] if n else np.zeros(0)
     y = np.zeros(n)
     if E.perm_mode == PERM_IMPLICIT:
+        i = np.arange(n, dtype=np.int64)
         y[(i // E.sigma) * E.sigma + E.perm] = t
     else:
         y[:] = t

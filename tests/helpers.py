@@ -3,6 +3,7 @@ import numpy as np
 
 from oracle import formats as F
 from oracle import linalg as L
+from oracle import packcsr as PC
 from oracle import packsell as P
 from paper_2604_13433_amd import workloads as W
 
@@ -48,3 +49,24 @@ def normalised_error(y, ref, a, q, x):
     den = L.inf_norm(a.rowptr, q) * float(np.max(np.abs(x))) if np.size(x) else 0.0
     err = float(np.max(np.abs(np.asarray(y, np.float64) - ref))) if np.size(y) else 0.0
     return err / den if den else err
+
+
+def chunk_plan_from_words(E, T):
+    """The expected plan of a product balanced over chunks of T words of a
+    CSR-packed matrix E (the oracle's encoding), read off the word stream:
+    lo[c] = the first row whose words start at or after word c*T
+    (lo[n_chunks] = n), anchor[c] = the running column just before word c*T
+    (the row's left offset when a row starts there)."""
+    n_chunks = -(-E.n_words // T)
+    starts = np.arange(n_chunks, dtype=np.int64) * T
+    lo = np.empty(n_chunks + 1, dtype=np.int64)
+    lo[:n_chunks] = np.searchsorted(E.wrowptr[:-1], starts, side="left")
+    lo[n_chunks] = E.n
+    anchor = np.zeros(n_chunks, dtype=np.int64)
+    if n_chunks:
+        after = PC.columns_after(E)
+        r = PC.word_rows(E)[starts]
+        head = E.wrowptr[r] == starts
+        anchor[head] = PC.left_offset(r[head], E.k_left)
+        anchor[~head] = after[starts[~head] - 1]
+    return lo, anchor

@@ -1,8 +1,9 @@
 """GPU parity for CSR-packed matrices (PackSELL words stored row after row:
 C = 1, sigma = 1) and their product balanced over chunks of words.
 
-Words, word row pointer and the chunk plan (first owned row and anchor
-column per chunk) must equal the CSR-packing oracle's bit for bit.  Products
+Words and the word row pointer must equal the CSR-packing oracle's bit for
+bit, and the chunk plan (first owned row and anchor column per chunk) the
+plan read off the oracle's word stream.  Products
 must equal the oracle's float64 product on the same quantised values
 within 1e-6, normalised by ||A_q||_inf ||x||_inf, and repeat bit for bit
 (every sum has a fixed order).  At the power-law matrix's full size the
@@ -13,7 +14,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import FMTS, SPMV_TOL, random_csr
+from helpers import FMTS, SPMV_TOL, chunk_plan_from_words, random_csr
 from oracle import linalg as L
 from oracle import packcsr as PC
 from oracle import packsell as P
@@ -52,7 +53,7 @@ def check_layout(A, E, chunk):
     assert np.array_equal(A.pack.cpu().numpy().view(np.uint32)[: E.n_words], E.pack)
     if E.row_exp is not None:
         assert np.array_equal(A.row_exp.cpu().numpy()[: E.n].astype(np.int64), E.row_exp)
-    lo, anchor = PC.chunk_plan(E, chunk)
+    lo, anchor = chunk_plan_from_words(E, chunk)
     assert A.desc.n_units == anchor.size
     if anchor.size:
         assert np.array_equal(A.t["units"].cpu().numpy().astype(np.int64), lo)

@@ -2,7 +2,9 @@
 
 Each test checks the oracle against something other than itself: words packed
 by hand (tests/golden/words.json), Python's own binary16 packing, an integer
-closed form of the E8MY rounding, and error bounds.
+closed form of the E8MY rounding, the paper's scaling form of the same
+rounding, an exhaustive nearest-value search over small E8MY grids, closed-form
+half-way cases of the FIX rounding, and error bounds.
 """
 import json
 import os
@@ -158,3 +160,63 @@ def test_fix_exact_grid_values():
     e = F.fix_row_exponent(np.array([1024.0]), D)[0]
     q = F.value_from_bits(F.fix_value_bits(v, np.full(v.size, e), D), F.FMT_FIX, D)
     assert np.array_equal(np.ldexp(q, int(e)), v.astype(np.float64))
+
+
+def _e8my_by_scaling(v32, D):
+    """The conversion of sec. 4.2.2 as the paper states it, for normal
+    inputs: with |v| = f 2^e (1/2 <= f < 1), round v to a multiple of
+    2^(e - 24 + D + 1), ties away from zero (C's round), then clear the low
+    D + 1 bits.  A different route from the oracle's neighbour search."""
+    v = np.asarray(v32, np.float32).astype(np.float64)
+    _, e = np.frexp(v)
+    scale = np.ldexp(1.0, e - 24 + D + 1)
+    t = v / scale
+    r = np.sign(t) * np.floor(np.abs(t) + 0.5) * scale
+    with np.errstate(over="ignore"):
+        b = r.astype(np.float32).view(np.uint32)
+    return b & np.uint32((0xFFFFFFFF << (D + 1)) & 0xFFFFFFFF)
+
+
+@pytest.mark.parametrize("D", [1, 2, 5, 9, 12, 13, 15, 20, 22])
+def test_e8my_equals_paper_scaling_steps(D):
+    rng = np.random.default_rng(300 + D)
+    bits = rng.integers(0x00800000, 0x7F800000, 20000, dtype=np.uint64).astype(np.uint32)
+    bits |= (rng.integers(0, 2, bits.size).astype(np.uint32) << np.uint32(31))
+    ties = (bits & np.uint32((0xFFFFFFFF << (D + 1)) & 0xFFFFFFFF)) | np.uint32(1 << D)
+    v = np.concatenate([bits, ties, ties + np.uint32(1)]).view(np.float32)
+    assert np.array_equal(F.e8my_value_bits(v, D), _e8my_by_scaling(v, D))
+
+
+@pytest.mark.parametrize("D", [18, 20, 21, 22])
+def test_e8my_brute_force_nearest(D):
+    """Y = 22 - D <= 4: list every positive E8MY value with exponent in
+    [-6, 6] (2^Y per binade), and take the nearest one by exhaustive search,
+    ties to the larger magnitude."""
+    Y = 22 - D
+    grid = sorted({(1 + k / 2 ** Y) * 2.0 ** e for e in range(-6, 7) for k in range(2 ** Y)})
+    grid = np.array(grid)
+    rng = np.random.default_rng(D)
+    v = (2.0 ** rng.uniform(-6, 6.9, 3000)).astype(np.float32)
+    mids = ((grid[1:] + grid[:-1]) / 2).astype(np.float32)  # exact ties (Y small)
+    v = np.concatenate([v, mids, grid.astype(np.float32)])
+    v = v[(v >= 2.0 ** -6) & (v <= grid[-1])]
+    a = v.astype(np.float64)
+    dist = np.abs(a[:, None] - grid[None, :])
+    best = dist.min(axis=1, keepdims=True)
+    want = np.where(dist == best, grid[None, :], -np.inf).max(axis=1)  # tie: larger
+    got = F.e8my_value_bits(v, D).view(np.float32).astype(np.float64)
+    assert np.array_equal(got, want)
+    got_neg = F.e8my_value_bits(-v, D).view(np.float32).astype(np.float64)
+    assert np.array_equal(got_neg, -want)
+
+
+@pytest.mark.parametrize("D,M", [(25, 20.0), (15, 20000.0), (25, 20.0 * 2.0 ** -10)])
+def test_fix_ties_round_away_from_zero(D, M):
+    """Half-way cases: with the row maximum M the row exponent makes
+    v / 2^e_row land exactly on +-0.5, +-1.5, +-2.5, +-3.5; ties go away
+    from zero (round-half-even would give 0, 2, 2, 4)."""
+    e = int(F.fix_row_exponent(np.array([M]), D)[0])
+    t = np.array([0.5, -0.5, 1.5, -1.5, 2.5, -2.5, 3.5, -3.5])
+    v = np.ldexp(t, e).astype(np.float32)
+    q = F.value_from_bits(F.fix_value_bits(v, np.full(v.size, e), D), F.FMT_FIX, D)
+    assert list(q) == [1, -1, 2, -2, 3, -3, 4, -4]

@@ -1,12 +1,14 @@
-"""Pins of the CSR-based packing oracle and its chunk plan, each against
-something other than the oracle itself: the PackSELL oracle at C = 1 and
-sigma = 1 (one-row slices hold a row's words contiguously with no padding),
-a loop-by-loop encoder, dense products, and a chunk plan found by walking
-rows word by word."""
+"""Pins of the CSR-based packing oracle, each against something other than
+the oracle itself: the PackSELL oracle at C = 1 and sigma = 1 (one-row
+slices hold a row's words contiguously with no padding), a loop-by-loop
+encoder and dense products.  The expected chunk plan of the GPU tests
+(tests/helpers.py, read off the oracle's word stream) is checked here
+against a plan found by walking rows word by word, and on closed-form
+cases."""
 import numpy as np
 import pytest
 
-from helpers import FMTS, random_csr
+from helpers import FMTS, chunk_plan_from_words, random_csr
 from oracle import formats as F
 from oracle import packcsr as PC
 from oracle import packsell as P
@@ -124,7 +126,7 @@ def plan_by_walking(E, T):
 def test_chunk_plan_against_walking(T, case):
     a = CASES[case]()
     E = PC.encode(a.rowptr, a.col, a.val, a.n, a.m, F.FMT_E8MY, 9)
-    lo, anchor = PC.chunk_plan(E, T)
+    lo, anchor = chunk_plan_from_words(E, T)
     wlo, wanchor = plan_by_walking(E, T)
     assert np.array_equal(lo, wlo) and np.array_equal(anchor, wanchor)
     # every row is owned by exactly one chunk: rows lo[c]..lo[c+1]-1 start in
@@ -143,17 +145,17 @@ def test_chunk_plan_special_cases():
     cols = np.tile(np.arange(64), n)
     a = W.csr_from_triplets(n, 64, rows, cols, np.ones(rows.size))
     E = PC.encode(a.rowptr, a.col, a.val, n, 64, F.FMT_FP16, 15)
-    lo, anchor = PC.chunk_plan(E, 128)
+    lo, anchor = chunk_plan_from_words(E, 128)
     assert list(lo) == [0, 2, 4, 6, 8, 10]
     assert list(anchor) == [0, 0, 0, 0, 0]  # k_left = 9: left offsets 0 up to row 9
     # one row across many chunks: anchors are that row's running column
     a = W.csr_from_triplets(3, 5000, [1] * 1000, np.arange(0, 5000, 5), np.ones(1000))
     E = PC.encode(a.rowptr, a.col, a.val, 3, 5000, F.FMT_FP16, 15)
-    lo, anchor = PC.chunk_plan(E, 64)
+    lo, anchor = chunk_plan_from_words(E, 64)
     assert list(lo) == [0] + [2] * 15 + [3]
     assert list(anchor) == [0] + [5 * 64 * c - 5 for c in range(1, 16)]
     # no words at all: no chunks, lo = [n]
     a = W.csr_from_triplets(4, 9, [], [], [])
     E = PC.encode(a.rowptr, a.col, a.val, 4, 9, F.FMT_FP16, 15)
-    lo, anchor = PC.chunk_plan(E, 64)
+    lo, anchor = chunk_plan_from_words(E, 64)
     assert list(lo) == [4] and anchor.size == 0

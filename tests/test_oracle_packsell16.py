@@ -98,6 +98,18 @@ def test_fix16_reduces_to_fix_with_the_same_field_width(D):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("D,M", [(7, 100.0), (7, 100.0 * 2.0 ** -12), (3, 1000.0)])
+def test_fix16_ties_round_away_from_zero(D, M):
+    """Half-way cases: v / 2^e_row = +-0.5, +-1.5, +-2.5, +-3.5 must give
+    +-1, +-2, +-3, +-4 (round-half-even would give 0, 2, 2, 4); D = 7 is the
+    int8 field."""
+    e = int(P16.fix16_row_exponent(np.array([M]), D)[0])
+    t = np.array([0.5, -0.5, 1.5, -1.5, 2.5, -2.5, 3.5, -3.5])
+    v = np.ldexp(t, e).astype(np.float32)
+    q = P16.value_from_bits(P16.fix16_value_bits(v, np.full(v.size, e), D), P16.FMT_FIX16, D)
+    assert list(q) == [1, -1, 2, -2, 3, -3, 4, -4]
+
+
 def test_hand_packed_words():
     """Sec. 4.2.1 layout with W = 16, written out by hand."""
     # E5M2 value 1.5 (binary16 0x3E00), D = 7, delta 5: 0x3E00 | 5 << 1 | 1
