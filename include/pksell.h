@@ -118,7 +118,8 @@ extern "C" {
  * padding, and offset is a word row pointer: delta-value packing in a
  * CSR-based layout, which the paper leaves to future work (sec. 6).  Set
  * split_words = T (256, 512 or 1024) after pksell_encode_query to give
- * pksell_spmv (k = 1, 2 or 4; k = 4 needs 16-byte aligned x) a product
+ * pksell_spmv (k = 1, 2, or 4 with 16-byte aligned x; a k = 4 product with
+ * misaligned x runs the one-row-slice product instead) a product
  * balanced over words: the word stream is
  * cut into n_units = ceil(n_words / T) chunks of T words, one per wave,
  * whatever rows they fall in.  The analyse phase sets n_units

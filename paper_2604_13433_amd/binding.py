@@ -147,6 +147,26 @@ def _stream(device=None):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _require(cond: bool, msg: str):
+    """Argument check that survives ``python -O`` (unlike assert)."""
+    if not cond:
+        raise ValueError(msg)
+
+
+def _block(t, dtype, rows: int, k: int | None, name: str):
+    """Checks a dense vector or row-major block argument: dtype, contiguity,
+    a GPU tensor, ``rows`` rows and (when given) ``k`` columns."""
+    _require(isinstance(t, torch.Tensor), f"{name} must be a torch tensor")
+    _require(t.dtype == dtype, f"{name} must be {dtype}, got {t.dtype}")
+    _require(t.dim() in (1, 2) and t.shape[0] == rows,
+             f"{name} must have {rows} rows, got shape {tuple(t.shape)}")
+    if k is not None:
+        kk = 1 if t.dim() == 1 else t.shape[1]
+        _require(kk == k, f"{name} must have {k} columns, got {kk}")
+    _require(t.is_contiguous(), f"{name} must be contiguous")
+    _require(t.is_cuda, f"{name} must be a GPU tensor")
+
+
 def _dev(t, dtype, device):
     if isinstance(t, np.ndarray):
         t = torch.from_numpy(np.ascontiguousarray(t))
@@ -389,10 +409,12 @@ class TriangularSolve:
         return int(stored + 8 * (self.n + 1) + 4 * self.n + 8 * self.n + 4 * (nnz - self.n))
 
     def __call__(self, b: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
-        assert b.dtype == torch.float32 and b.is_contiguous() and b.shape == (self.n,)
+        _block(b, torch.float32, self.n, 1, "b")
+        _require(b.dim() == 1, "b must be a vector")
         if y is None:
             y = torch.empty(self.n, dtype=torch.float32, device=b.device)
-        assert y.data_ptr() != b.data_ptr() or self.n == 0
+        _block(y, torch.float32, self.n, 1, "y")
+        _require(y.data_ptr() != b.data_ptr() or self.n == 0, "y must not alias b")
         lp = self.level_ptr.ctypes.data_as(vp)
         if self.L is None:
             _check(lib().pksell_trsv_csr(_ptr(self.rp), _ptr(self.cl), _ptr(self.val), self.n,
@@ -411,7 +433,8 @@ class StreamRead:
     per wave."""
 
     def __init__(self, buf: torch.Tensor, width: int = 4, chunks: int = 7):
-        assert buf.is_contiguous() and buf.data_ptr() % 16 == 0
+        _require(buf.is_cuda and buf.is_contiguous() and buf.data_ptr() % 16 == 0,
+                 "buf must be a contiguous, 16-byte aligned GPU tensor")
         self.buf = buf
         self.bytes = buf.numel() * buf.element_size()
         self.width, self.chunks = width, chunks
@@ -461,11 +484,11 @@ def encode_transpose(rowptr, col, val, n: int, m: int, fmt="fp16", D: int = 15, 
 
 def spmv(A: PackSELLMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
     """y = A_q x (x: m or m x k float32 on the device)."""
+    _block(x, torch.float32, A.m, None, "x")
     k = 1 if x.dim() == 1 else x.shape[1]
     if y is None:
         y = torch.empty((A.n,) if x.dim() == 1 else (A.n, k), dtype=torch.float32, device=x.device)
-    assert x.dtype == torch.float32 and x.is_contiguous() and x.shape[0] == A.m
-    assert y.dtype == torch.float32 and y.is_contiguous() and y.shape[0] == A.n
+    _block(y, torch.float32, A.n, k, "y")
     _check(lib().pksell_spmv(ctypes.byref(A.desc), _ptr(x), _ptr(y), k, _stream(x.device)))
     return y
 
@@ -474,8 +497,8 @@ def spmv_f64(A: PackSELLMatrix, x: torch.Tensor, y: torch.Tensor | None = None) 
     """y = A_q x in float64 for a 64-bit-word (E11MY) matrix (x: m float64)."""
     if y is None:
         y = torch.empty(A.n, dtype=torch.float64, device=x.device)
-    assert x.dtype == torch.float64 and x.is_contiguous() and x.shape[0] == A.m
-    assert y.dtype == torch.float64 and y.is_contiguous() and y.shape[0] == A.n
+    _block(x, torch.float64, A.m, 1, "x")
+    _block(y, torch.float64, A.n, 1, "y")
     _check(lib().pksell_spmv_f64(ctypes.byref(A.desc), _ptr(x), _ptr(y), _stream(x.device)))
     return y
 
@@ -483,9 +506,10 @@ def spmv_f64(A: PackSELLMatrix, x: torch.Tensor, y: torch.Tensor | None = None) 
 def spmv_t(A: PackSELLMatrix, g: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
     """y = A_q^T g (g: n or n x k float32)."""
     k = 1 if g.dim() == 1 else g.shape[1]
+    _block(g, torch.float32, A.n, None, "g")
     if y is None:
         y = torch.empty((A.m,) if g.dim() == 1 else (A.m, k), dtype=torch.float32, device=g.device)
-    assert g.dtype == torch.float32 and g.is_contiguous() and g.shape[0] == A.n
+    _block(y, torch.float32, A.m, k, "y")
     _check(lib().pksell_spmv_t(ctypes.byref(A.desc), _ptr(g), _ptr(y), k, _stream(g.device)))
     return y
 
@@ -495,7 +519,8 @@ def grad_values(A: PackSELLMatrix, rowptr: torch.Tensor, g: torch.Tensor,
     """sum_s g[i, s] x[j, s] at every stored nonzero, in the CSR order of
     ``rowptr`` (g: n or n x k, x: m or m x k)."""
     k = 1 if g.dim() == 1 else g.shape[1]
-    assert g.is_contiguous() and x.is_contiguous() and x.shape[0] == A.m
+    _block(g, torch.float32, A.n, None, "g")
+    _block(x, torch.float32, A.m, k, "x")
     out = torch.empty(max(1, A.nnz), dtype=torch.float32, device=g.device)
     rp = _dev(rowptr, torch.int64, g.device)
     _check(lib().pksell_grad_values(ctypes.byref(A.desc), _ptr(rp), _ptr(g), _ptr(x),
@@ -592,7 +617,8 @@ def sell_encode(rowptr, col, val, n: int, m: int, dtype=torch.float32, C: int = 
 def sell_spmv(S: SellMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
     if y is None:
         y = torch.empty(S.n, dtype=S.dtype, device=x.device)
-    assert x.dtype == S.dtype and y.dtype == S.dtype and x.numel() == S.m
+    _block(x, S.dtype, S.m, 1, "x")
+    _block(y, S.dtype, S.n, 1, "y")
     _check(lib().pksell_sell_spmv(ctypes.byref(S.desc), _ptr(x), _ptr(y), _stream(x.device)))
     return y
 
@@ -608,7 +634,9 @@ def pcg(A_lo: PackSELLMatrix | None, A_hi, b: torch.Tensor,
     float64 CG when ``A_lo`` is None.  ``A_hi`` (the float64 operator) is a
     float64 SellMatrix or a 64-bit-word (E11MY) PackSELLMatrix.
     Returns (x, info)."""
-    assert b.dtype == torch.float64 and b.numel() == A_hi.n
+    _block(b, torch.float64, A_hi.n, 1, "b")
+    if x0 is not None:
+        _block(x0, torch.float64, A_hi.n, 1, "x0")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     ws_bytes = ctypes.c_size_t()
     lo = ctypes.byref(A_lo.desc) if A_lo is not None else None
@@ -635,16 +663,16 @@ class BatchedSpMV:
     a HIP graph that ``replay()`` re-runs with the same buffers."""
 
     def __init__(self, mats: list, inputs: list, outputs: list, transpose: bool = False):
-        assert len(mats) == len(inputs) == len(outputs) and mats
+        _require(len(mats) == len(inputs) == len(outputs) and len(mats) > 0,
+                 "mats, inputs and outputs must be non-empty lists of one length")
         self.mats, self.inputs, self.outputs = mats, inputs, outputs
         k = 1 if inputs[0].dim() == 1 else inputs[0].shape[1]
         dev = inputs[0].device
         arr = (CBatchItem * len(mats))()
         for i, (A, x, y) in enumerate(zip(mats, inputs, outputs)):
-            assert x.dtype == torch.float32 and y.dtype == torch.float32
-            assert x.is_contiguous() and y.is_contiguous()
-            kk = 1 if x.dim() == 1 else x.shape[1]
-            assert kk == k, "every item needs the same k"
+            rows_in, rows_out = (A.n, A.m) if transpose else (A.m, A.n)
+            _block(x, torch.float32, rows_in, k, f"inputs[{i}]")
+            _block(y, torch.float32, rows_out, k, f"outputs[{i}]")
             arr[i].A = ctypes.pointer(A.desc)
             arr[i].inp = x.data_ptr()
             arr[i].out = y.data_ptr()

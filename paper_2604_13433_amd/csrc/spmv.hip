@@ -735,7 +735,10 @@ int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, voi
   if (A->n == 0) return PKSELL_OK;
   if (A->m == 0) return zero_f32(y, A->n * k, st);
   PKS_CHECK(x, PKSELL_EINVAL, "null x");
-  if ((k == 1 || k == 2 || k == 4) && A->C == 1 && A->split_words > 0)
+  // The chunk plan serves k = 1, 2 and 4; its k = 4 form gathers 16-byte x
+  // rows, so a misaligned x takes the one-row-slice product below instead.
+  const bool x16 = ((uintptr_t)x & 15) == 0;
+  if ((k == 1 || k == 2 || (k == 4 && x16)) && A->C == 1 && A->split_words > 0)
     return spmv_chunks(A, x, y, k, st);
   SpmvArgs a = make_args(A, x, y, k);
   if (k == 1 && A->C == kWave && A->split_words > 0 && A->n_split_units > 0) {

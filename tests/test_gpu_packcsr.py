@@ -188,3 +188,22 @@ def test_several_right_hand_sides(fmt, D, k):
             ref = PC.spmv(E, x[:, j].astype(np.float64))
             den = L.inf_norm(a.rowptr, q) * float(np.abs(x[:, j]).max())
             assert float(np.max(np.abs(y[:, j] - ref))) / den <= SPMV_TOL, (si, j)
+
+
+def test_four_columns_from_a_misaligned_view():
+    """A k = 4 product whose x is a contiguous view starting 4 bytes into its
+    storage cannot take the chunk kernel's 16-byte gathers: it runs the
+    one-row-slice product instead, and still equals the oracle per column."""
+    a = hollow(17)
+    A, E = both(a, "fp16", 15, 512)
+    x = np.random.default_rng(21).uniform(-1, 1, (a.m, 4)).astype(np.float32)
+    store = torch.zeros(a.m * 4 + 1, dtype=torch.float32, device=DEV)
+    store[1:] = torch.from_numpy(x.reshape(-1)).to(DEV)
+    xv = store[1:].view(a.m, 4)
+    assert xv.is_contiguous() and xv.data_ptr() % 16 != 0
+    y = B.spmv(A, xv).cpu().numpy().astype(np.float64)
+    q = P.quantized_values(a.rowptr, a.col, a.val, a.n, FMTS["fp16"], 15)
+    for j in range(4):
+        ref = PC.spmv(E, x[:, j].astype(np.float64))
+        den = L.inf_norm(a.rowptr, q) * float(np.abs(x[:, j]).max())
+        assert np.max(np.abs(y[:, j] - ref)) / den <= SPMV_TOL

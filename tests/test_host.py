@@ -33,3 +33,40 @@ def test_batch_generator_sizes():
     assert len(mats) == 6
     assert all(m.n == m.m for m in mats)
     assert mats[0].name.startswith("b0_5pt") and mats[1].name.startswith("b1_7pt")
+
+
+_ARG_CHECKS = r"""
+import torch, pytest
+from paper_2604_13433_amd import binding as B
+d = B.CMatrix(); d.n, d.m = 5, 10
+A = B.PackSELLMatrix(d, {}, torch.device("cpu"))
+cases = [
+    (lambda: B.spmv(A, torch.zeros(9)), "10 rows"),
+    (lambda: B.spmv(A, torch.zeros(10, dtype=torch.float64)), "torch.float32"),
+    (lambda: B.spmv(A, torch.zeros(10)), "GPU tensor"),
+    (lambda: B.spmv_t(A, torch.zeros(4)), "5 rows"),
+    (lambda: B.spmv_f64(A, torch.zeros(10)), "torch.float64"),
+]
+for fn, msg in cases:
+    try:
+        fn()
+    except ValueError as e:
+        assert msg in str(e), (msg, str(e))
+    else:
+        raise SystemExit("no error for " + msg)
+print("ok")
+"""
+
+
+@pytest.mark.parametrize("opt", [[], ["-O"]])
+def test_binding_argument_errors_survive_optimised_python(opt):
+    """Shape, dtype and device errors are raised before any library call,
+    also under ``python -O`` (which strips asserts)."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, *opt, "-c", _ARG_CHECKS], cwd=root,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr[-2000:]
