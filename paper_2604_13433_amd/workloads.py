@@ -20,6 +20,9 @@ stand in for them with the same structural traits:
   law, 90% of each row inside a +/-512 band and 10% uniform far columns
   (the high-RSD regime of sec. 5.1.1), values N(0,1) then row-sum scaled.
 * ``batch``          -- many stencils of uneven size.
+* ``convdiff3d``     -- a nonsymmetric convection-diffusion stencil, for the
+  nested solver of sec. 5.2.1 (whose test set mixes SPD and nonsymmetric
+  matrices).
 
 Diagonal scalings used by the paper as workload preparation
 (row-sum scaling G^-1 A of sec. 5.1.2, symmetric scaling of sec. 5.2) are
@@ -188,6 +191,29 @@ def stencil(dims, kind: str, seed: int | None, ln_sigma: float = 0.5,
     rowptr = np.zeros(n + 1, dtype=np.int64)
     rowptr[1:] = np.cumsum(counts)
     return CSR(n, n, rowptr, cols[mask].astype(np.int32), vals[mask], name)
+
+
+def convdiff3d(g: int, seed: int, wind=(1.0, 0.5, 0.25), ln_sigma: float = 0.5,
+               name: str = "") -> CSR:
+    """Nonsymmetric 3D convection-diffusion on a g^3 grid: the 7-point
+    variable-coefficient diffusion of ``stencil`` (lognormal(0, ln_sigma)
+    edge coefficients, seed ``seed``) plus first-order upwind convection
+    with the constant velocity ``wind`` (one component per axis, >= 0, in
+    units of the mean edge coefficient): each point adds wind[ax] to its
+    diagonal and -wind[ax] to its lower neighbour along axis ax (dropped at
+    the boundary).  A diagonally dominant M-matrix with a nonsymmetric
+    pattern of values, a stand-in for the nonsymmetric problems the paper
+    solves with F3R (sec. 5.2.1)."""
+    a = stencil((g, g, g), "star", seed, ln_sigma)
+    rows = a.rows()
+    colv = a.col.astype(np.int64)
+    val = a.val.copy()
+    diag = rows == colv
+    val[diag] += float(sum(wind))
+    for ax, v in enumerate(wind):
+        lower = rows - colv == g ** ax
+        val[lower] -= v
+    return CSR(a.n, a.m, a.rowptr, a.col, val, name or f"convdiff7_{g}")
 
 
 def block_stencil(dims, dof: int, seed: int, name: str = "") -> CSR:
