@@ -31,7 +31,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-EXTRA_CHECKS = []  # (name, matrix, x, {variant: y}) checked by the CPU leg
+# label -> (matrix, x, {variant: (y in original row order, fmt, D)}): products
+# of the extra legs whose errors the CPU leg computes against the oracle
+# (fmt None: only the eq. 5 backward error against the unquantised values)
+EXTRA_CHECKS = {}
+
+
+def record(label, mat, x, variant, y, fmt=None, D=0):
+    """Keeps a product for the CPU leg's error check."""
+    entry = EXTRA_CHECKS.setdefault(label, (mat, np.asarray(x), {}))
+    entry[2][variant] = (np.asarray(y), fmt, D)
+
+
+def original_order(B, A, y):
+    """A product in stored row order (explicit mode) put back in the
+    original row order with the matrix's perm."""
+    y = y.cpu().numpy() if hasattr(y, "cpu") else np.asarray(y)
+    if A.perm_mode == B.IMPLICIT or A.perm is None or A.sigma == 1:
+        return y
+    i = np.arange(A.n)
+    orig = (i // A.sigma) * A.sigma + A.perm.cpu().numpy()[: A.n].astype(np.int64)
+    out = np.empty_like(y)
+    out[orig] = y
+    return out
 METRIC = "PackSELL SpMV GB/s and % HBM roofline vs FP32 SELL at stated err; PCG time-to-1e-10"
 
 
@@ -87,7 +109,7 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the power-law and block-stencil legs")
-    p.add_argument("--leg", default="", choices=["", "powerlaw", "trsv"],
+    p.add_argument("--leg", default="", choices=["", "powerlaw", "trsv", "f3r", "pcg"],
                    help="run only this leg and print its JSON (for profiling one kernel)")
     p.add_argument("--calib-copy-mb", type=int, default=0,
                    help="first run one plain device copy of this many MiB (a known-size "
@@ -96,14 +118,18 @@ def parse():
 
 
 class Timed:
-    """K launches of ``launch(i)`` replayed from HIP graphs on one stream."""
+    """Windows of exactly K launches of ``launch(i)`` replayed from HIP graphs
+    on one stream; ``run`` returns the median window's ms per launch and
+    keeps every window's figure in ``windows_ms``."""
 
-    def __init__(self, torch, launch, n_rep: int, steps: int, warmup: int):
+    def __init__(self, torch, launch, n_rep: int, steps: int, warmup: int, windows: int = 5):
         self.torch = torch
         self.launch = launch
         self.n_rep = n_rep
         self.steps = steps
         self.warmup = warmup
+        self.windows = windows
+        self.windows_ms = []
 
     def _graph(self, count: int, start: int):
         torch = self.torch
@@ -126,18 +152,21 @@ class Timed:
             g_full.replay()
         torch.cuda.synchronize()
         st = torch.cuda.current_stream()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(st)
-        for _ in range(self.steps // full):
-            g_full.replay()
-        if g_rem is not None:
-            g_rem.replay()
-        e1.record(st)
-        e1.synchronize()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / self.steps  # ms per launch
+        self.windows_ms = []
+        for _ in range(self.windows):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(st)
+            for _ in range(self.steps // full):
+                g_full.replay()
+            if g_rem is not None:
+                g_rem.replay()
+            e1.record(st)
+            e1.synchronize()
+            torch.cuda.synchronize()
+            self.windows_ms.append(e0.elapsed_time(e1) / self.steps)  # ms per launch
+        return sorted(self.windows_ms)[len(self.windows_ms) // 2]
 
 
 def main():
@@ -163,7 +192,8 @@ def main():
         log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
     if args.leg:
-        leg = {"powerlaw": powerlaw_leg, "trsv": trsv_leg}[args.leg]
+        leg = {"powerlaw": powerlaw_leg, "trsv": trsv_leg, "f3r": f3r_leg,
+               "pcg": pcg_leg}[args.leg]
         print(json.dumps({args.leg: leg(args, torch, B, W)}), flush=True)
         return
     g = args.grid
@@ -183,6 +213,9 @@ def main():
     specs = [("packsell_fp16", "fp16", 15, B.EXPLICIT),
              ("packsell_e8m13", "e8my", 9, B.EXPLICIT),
              ("packsell_fp16_implicit", "fp16", 15, B.IMPLICIT)]
+    # the E8MY delta/value split: D = 1, 2 (FP32-level values, a dummy at
+    # nearly every plane jump) and 12 beside the D = 9 above
+    specs += [(f"packsell_e8m{22 - D}", "e8my", D, B.EXPLICIT) for D in (1, 2, 12)]
     for name, fmt, D, mode in specs:
         if only and name not in only:
             continue
@@ -208,12 +241,13 @@ def main():
         reps = [A] + [A.replicate() for _ in range(R - 1)]
         xs = [x0.clone() for _ in range(R)]
         ys = [torch.empty(a.n, dtype=torch.float32, device=dev) for _ in range(R)]
-        ms = Timed(torch, lambda i: B.spmv(reps[i], xs[i], ys[i]), R, args.steps,
-                   args.warmup).run()
+        tm = Timed(torch, lambda i: B.spmv(reps[i], xs[i], ys[i]), R, args.steps, args.warmup)
+        ms = tm.run()
         gbs = per / (ms * 1e-3) / 1e9
         results[name] = dict(ms=ms, gbs=gbs, bytes=per, replicas=R, words=A.n_words,
                              dummies=A.n_dummies, gflops=2 * a.nnz / (ms * 1e-3) / 1e9,
-                             y=ys[0], A=A, useful=per - 4 * (A.n_words - a.nnz))
+                             y=ys[0], A=A, useful=per - 4 * (A.n_words - a.nnz),
+                             windows_us=[round(w * 1e3, 3) for w in tm.windows_ms])
         log(f"[bench] {name}: {ms * 1e3:.2f} us  {gbs:.0f} GB/s  ({R} replicas, "
             f"{per / 1e6:.1f} MB/product)")
         del reps, xs
@@ -223,13 +257,15 @@ def main():
         reps = [S] + [S.replicate() for _ in range(R - 1)]
         xs = [x0.to(S.dtype).clone() for _ in range(R)]
         ys = [torch.empty(a.n, dtype=S.dtype, device=dev) for _ in range(R)]
-        ms = Timed(torch, lambda i: B.sell_spmv(reps[i], xs[i], ys[i]), R, args.steps,
-                   args.warmup).run()
+        tm = Timed(torch, lambda i: B.sell_spmv(reps[i], xs[i], ys[i]), R, args.steps,
+                   args.warmup)
+        ms = tm.run()
         gbs = per / (ms * 1e-3) / 1e9
         vb = S.value_dtype.itemsize
         results[name] = dict(ms=ms, gbs=gbs, bytes=per, replicas=R, slots=S.n_slots,
                              gflops=2 * a.nnz / (ms * 1e-3) / 1e9, y=ys[0], S=S,
-                             useful=per - (4 + vb) * (S.n_slots - a.nnz))
+                             useful=per - (4 + vb) * (S.n_slots - a.nnz),
+                             windows_us=[round(w * 1e3, 3) for w in tm.windows_ms])
         log(f"[bench] {name}: {ms * 1e3:.2f} us  {gbs:.0f} GB/s  ({R} replicas)")
         del reps, xs
 
@@ -244,6 +280,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": H["ms"],
+        "timing": f"median of 5 windows of exactly {args.steps} launches each (graph replays "
+                  f"bracketed by HIP events on the launch stream); per-window figures in "
+                  f"variants.*.windows_us",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -268,7 +307,8 @@ def main():
         v = {"us": round(r["ms"] * 1e3, 2), "GB/s": round(r["gbs"], 1),
              "GFLOP/s": round(r["gflops"], 1), "hbm_frac": round(r["gbs"] / PEAK_HBM_GBS, 4),
              "bytes": r["bytes"], "replicas": r["replicas"],
-             "useful_GB/s": round(r["useful"] / (r["ms"] * 1e-3) / 1e9, 1)}
+             "useful_GB/s": round(r["useful"] / (r["ms"] * 1e-3) / 1e9, 1),
+             "windows_us": r["windows_us"]}
         if base32 is not None:
             v["speedup_vs_sell_fp32"] = round(base32["ms"] / r["ms"], 3)
         if base16 is not None and name.startswith("packsell_fp16"):
@@ -292,6 +332,7 @@ def main():
         out["batched"] = batched_leg(args, torch, B, W)
     if not args.no_pcg:
         out["pcg"] = pcg_leg(args, torch, B, W)
+        out["f3r"] = f3r_leg(args, torch, B, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_leg(args, a, x_np, results, H, torch)
     print(json.dumps(out), flush=True)
@@ -397,6 +438,11 @@ def powerlaw_leg(args, torch, B, W):
     variants += [("packsell_e8m10_split256", "e8my", 12, 256)]
     variants += [(f"packed_csr_fp16_chunk{J}", "fp16", 15, J) for J in (256, 512, 1024)]
     variants += [("packed_csr_e8m10_chunk512", "e8my", 12, 512)]
+    # the E8MY delta/value split (D = 1, 2, 9; D = 12 above) and 16-bit fixed
+    # point with a per-row scale (FIX, D = 15) on the best layout
+    variants += [(f"packed_csr_e8m{22 - D}_chunk512", "e8my", D, 512) for D in (1, 2, 9)]
+    variants += [("packed_csr_fix16_chunk512", "fix", 15, 512)]
+    x_chk = torch.from_numpy(W.uniform_vector(a.m, 41)).to(dev)
     for name, fmt, D, J in variants:
         csr = name.startswith("packed_csr")
         if csr:
@@ -414,6 +460,8 @@ def powerlaw_leg(args, torch, B, W):
             res[name]["sigma"] = 65536
         if J and not csr:
             res[name].update(split_words=J, units=A.n_units, split_units=A.n_split_units)
+        record("powerlaw", a, x_chk.cpu().numpy(), name, original_order(B, A, B.spmv(A, x_chk)),
+               fmt, D)
         log(f"[bench] powerlaw {name}: {res[name]}")
         del A
     # four right-hand sides through the chunk product: one 16-byte gather per word
@@ -428,12 +476,19 @@ def powerlaw_leg(args, torch, B, W):
     res["packed_csr_fp16_chunk512_k4"] = {"us": round(ms * 1e3, 2),
                                           "us_per_rhs": round(ms * 1e3 / 4, 2),
                                           "GB/s": round(per / (ms * 1e-3) / 1e9, 1)}
+    x4 = torch.from_numpy(W.uniform_vector(a.m, 42, k=4)).to(dev)
+    y4 = B.spmv(A, x4).cpu().numpy()
+    for c in (0, 3):
+        record(f"powerlaw_k4_col{c}", a, x4[:, c].cpu().numpy(), "packed_csr_fp16_chunk512_k4",
+               y4[:, c], "fp16", 15)
     log(f"[bench] powerlaw packed_csr_fp16_chunk512_k4: {res['packed_csr_fp16_chunk512_k4']}")
     del reps, xs, ys, A
     S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 65536, B.EXPLICIT, dev)
     ms, per, R = time_variant(args, torch, B, S, a.m, a.n)
     res["sell_fp32"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
                         "slots_per_nnz": round(S.n_slots / a.nnz, 3)}
+    record("powerlaw", a, x_chk.cpu().numpy(), "sell_fp32",
+           original_order(B, S, B.sell_spmv(S, x_chk)), "f32")
     log(f"[bench] powerlaw sell_fp32: {res['sell_fp32']}")
     for name, *_ in variants:
         res[name]["speedup_vs_sell_fp32"] = round(res["sell_fp32"]["us"] / res[name]["us"], 3)
@@ -506,8 +561,12 @@ def fp64_leg(args, a, torch, B, W):
             if label == "packsell64":
                 yp = ys[0].clone()
                 x0 = xs[0]
+                record(f"fp64_words_{name}", mat, x0.cpu().numpy(), "packsell64",
+                       original_order(B, M, fn(M, x0)), "e11my", D)
             else:
                 ys_ref = fn(M, x0)  # same x, unquantised FP64 values
+                record(f"fp64_words_{name}", mat, x0.cpu().numpy(), "sell_fp64",
+                       original_order(B, M, ys_ref), "f64")
             del reps, xs, ys
         diff = float((yp - ys_ref).abs().max() / ys_ref.abs().max().clamp_min(1e-300))
         out["speedup_vs_sell_fp64"] = round(out["sell_fp64"]["us"] / out["packsell64"]["us"], 3)
@@ -567,8 +626,8 @@ def block_leg(args, torch, B, W):
     res["speedup_vs_sell_fp32"] = round(ms_s / ms_p, 3)
     # errors against the float64 oracle are computed in the CPU leg
     x_np = x.cpu().numpy()
-    EXTRA_CHECKS.append(("block3_27pt", a, x_np, {"packsell_e8m20": B.spmv(A, x).cpu().numpy(),
-                                                  "sell_fp32": B.sell_spmv(S, x).cpu().numpy()}))
+    record("block3_27pt", a, x_np, "packsell_e8m20", B.spmv(A, x).cpu().numpy(), "e8my", 2)
+    record("block3_27pt", a, x_np, "sell_fp32", B.sell_spmv(S, x).cpu().numpy(), "f32")
     log(f"[bench] block3_27pt: {res}")
     return res
 
@@ -585,7 +644,6 @@ def w16_leg(args, torch, B, W):
                              ("poisson2d_2048_fix16_int4", W.poisson2d(2048), "fix16", 11)):
         res = {"n": a.n, "nnz": a.nnz}
         x = torch.from_numpy(W.uniform_vector(a.m, 13)).to(dev)
-        ys = {}
         for name, mk in ((f"packsell16_{fmt}", lambda: B.encode(a.rowptr, a.col, a.val, a.n, a.m,
                                                                   fmt, D, 64, 256, B.EXPLICIT,
                                                                   dev)),
@@ -602,18 +660,15 @@ def w16_leg(args, torch, B, W):
             if isinstance(M, B.PackSELLMatrix):
                 r["words"], r["dummies"] = M.n_words, M.n_dummies
                 # product in the original row order for the error check
-                y = B.spmv(M, x).cpu().numpy()
-                orig = (np.arange(a.n) // 256) * 256 + M.perm.cpu().numpy()[: a.n]
-                yo = np.empty_like(y)
-                yo[orig] = y
-                ys[name] = yo
+                record(label, a, x.cpu().numpy(), name, original_order(B, M, B.spmv(M, x)),
+                       fmt if name.startswith("packsell16") else "fp16",
+                       D if name.startswith("packsell16") else 15)
             res[name] = r
             del M
         for name in list(res):
             if name.startswith("packsell16"):
                 res["speedup_vs_packsell_fp16"] = round(res["packsell_fp16"]["us"] / res[name]["us"], 3)
                 res["speedup_vs_sell_fp16"] = round(res["sell_fp16"]["us"] / res[name]["us"], 3)
-        EXTRA_CHECKS.append((label, a, x.cpu().numpy(), ys))
         log(f"[bench] 16-bit words {label}: {res}")
         out[label] = res
     return out
@@ -636,6 +691,10 @@ def multirhs_leg(args, a, A, torch, B, W):
         res[f"k{k}"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
                         "GFLOP/s": round(2 * a.nnz * k / (ms * 1e-3) / 1e9, 1), "bytes": per,
                         "replicas": R}
+        yk = original_order(B, A, B.spmv(A, xs[0]))
+        for c in (0, k - 1):
+            record(f"multi_rhs_k{k}_col{c}", a, xs[0][:, c].cpu().numpy(), "packsell_fp16",
+                   yk[:, c], "fp16", 15)
         log(f"[bench] single-matrix k={k}: {res[f'k{k}']}")
         del reps, xs, ys
     return res
@@ -665,6 +724,13 @@ def batched_leg(args, torch, B, W):
         res[f"k{k}"] = {"us": round(ms * 1e3, 1), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
                         "GFLOP/s": round(2 * nnz * k / (ms * 1e-3) / 1e9, 1),
                         "bytes": per, "replicas": R}
+        bats[0]()
+        torch.cuda.synchronize()
+        for i in (0, len(mats) // 2, len(mats) - 1):  # implicit order: original rows
+            xi, yi = bats[0].inputs[i].cpu().numpy(), bats[0].outputs[i].cpu().numpy()
+            c = k - 1
+            record(f"batched_k{k}_m{i}", mats[i], xi if k == 1 else xi[:, c], "packsell_e8m13",
+                   yi if k == 1 else yi[:, c], "e8my", 9)
         log(f"[bench] batched k={k}: {ms * 1e3:.1f} us {per / (ms * 1e-3) / 1e9:.0f} GB/s")
         del bats, sets
     return res
@@ -697,7 +763,7 @@ def pcg_leg(args, torch, B, W):
     best = None
     for D in (9, 12, 14):
         lo = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e8my", D, 64, 256, B.IMPLICIT, dev)
-        for m_in in (20, 50):
+        for m_in in (20, 50, 80):
             r = run(lo, m_in)
             r["speedup_vs_fp64_cg"] = round(res["fp64_cg"]["ms"] / r["ms"], 3)
             res[f"iocg_e8m{22 - D}_min{m_in}"] = r
@@ -729,6 +795,56 @@ def pcg_leg(args, torch, B, W):
     return res
 
 
+def f3r_leg(args, torch, B, W):
+    """Time to a 1e-10 relative residual with the F3R nested solver (sec.
+    5.2.1; outer FGMRES(100), FGMRES(8), FGMRES(4), Richardson(2)) in its
+    three forms: every layer float64 (FP64-F3R); float32 SELL in layer 2 and
+    half-value SELL in layers 3-4 (FP16-F3R); the same with FP16 PackSELL
+    words in layers 3-4 (PackSELL-F3R).  On the SPD 27-point 100^3 system
+    (b = A 1) and a nonsymmetric 7-point convection-diffusion 128^3 system
+    (b ~ U[0, 1)), both symmetrically scaled."""
+    dev = torch.device("cuda:0")
+    out = {}
+    for label, a, bvec in (
+            ("stencil27_100", W.symmetric_diag_scale(W.m4_stencil27()), None),
+            ("convdiff7_128", W.symmetric_diag_scale(W.convdiff3d(128, 11)), "uniform")):
+        b_np = W.ones_rhs(a) if bvec is None else np.random.default_rng(12).uniform(0, 1, a.n)
+        b = torch.from_numpy(b_np).to(dev)
+        enc = lambda dt: B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, dt, 64, 256, B.IMPLICIT,
+                                       dev)
+        A1, A2, A3s = enc(torch.float64), enc(torch.float32), enc(torch.float16)
+        A3p = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 64, 256, B.IMPLICIT, dev)
+        res = {"n": a.n, "nnz": a.nnz, "params": "m1=100 m2=8 m3=4 m4=2 omega=1"}
+        xs = {}
+        for name, kw in (("fp64_f3r", {}), ("fp16_f3r", dict(A2=A2, A3=A3s)),
+                         ("packsell_f3r", dict(A2=A2, A3=A3p))):
+            times, info, x = [], None, None
+            for _ in range(3):
+                x, info = B.f3r(A1, b, tol=1e-10, **kw)
+                times.append(info["seconds"])
+            xs[name] = x
+            true = float(np.linalg.norm(b_np - csr_apply(a, x.cpu().numpy())) /
+                         np.linalg.norm(b_np))
+            res[name] = dict(ms=round(1e3 * sorted(times)[1], 2),
+                             outer_steps=info["outer_iterations"], rel_residual=info["rel_residual"],
+                             true_rel_residual_host=true)
+            log(f"[bench] F3R {label} {name}: {res[name]}")
+        for name in ("fp16_f3r", "packsell_f3r"):
+            res[name]["speedup_vs_fp64_f3r"] = round(res["fp64_f3r"]["ms"] / res[name]["ms"], 3)
+        res["packsell_over_fp16_speedup"] = round(res["fp16_f3r"]["ms"] / res["packsell_f3r"]["ms"], 3)
+        res["fp16_and_packsell_iterates_identical"] = bool(torch.equal(xs["fp16_f3r"],
+                                                                      xs["packsell_f3r"]))
+        out[label] = res
+        del A1, A2, A3s, A3p
+    return out
+
+
+def csr_apply(a, x):
+    """A x in float64 on the host with scipy (a residual check, not timed)."""
+    import scipy.sparse as sp
+    return sp.csr_matrix((a.val, a.col, a.rowptr), shape=(a.n, a.m)) @ x
+
+
 def run_with(hi, lo, m_in, run_fn, b, reps=3):
     """Median time of ``reps`` solves to 1e-10 (x0 = 0)."""
     times, info, x = [], None, None
@@ -741,6 +857,29 @@ def run_with(hi, lo, m_in, run_fn, b, reps=3):
                 max_abs_err_vs_ones=float((x - 1.0).abs().max()))
 
 
+def quantised(m, fmt, D):
+    """The oracle's values of the matrix as a product of format ``fmt``
+    holds them (None: no format, only the backward error is reported)."""
+    from oracle import formats as F
+    from oracle import packsell as P
+    from oracle import packsell16 as P16
+    from oracle import packsell64 as P64
+
+    if fmt is None:
+        return None
+    if fmt == "f32":
+        return m.val.astype(np.float32).astype(np.float64)
+    if fmt == "f64":
+        return m.val
+    if fmt == "e11my":
+        return P64.quantized(m.val, D)
+    if fmt in ("e5my", "fix16"):
+        return P16.quantized(m.rowptr, m.val, m.n, {"e5my": P16.FMT_E5MY,
+                                                    "fix16": P16.FMT_FIX16}[fmt], D)
+    code = {"fp16": F.FMT_FP16, "e8my": F.FMT_E8MY, "fix": F.FMT_FIX}[fmt]
+    return P.quantized_values(m.rowptr, m.col, m.val, m.n, code, D)
+
+
 def cpu_leg(args, a, x_np, results, H, torch):
     """The float64 CSR oracle timed on the host cores (and the error of every
     GPU result against it, which needs the oracle anyway)."""
@@ -750,15 +889,23 @@ def cpu_leg(args, a, x_np, results, H, torch):
     from oracle import packsell as P
 
     q16 = P.quantized_values(a.rowptr, a.col, a.val, a.n, F.FMT_FP16, 15)
-    reps = 0
-    t0 = time.time()
-    while True:
-        y_ref = L.spmv(a.rowptr, a.col, q16, x_np)
-        reps += 1
-        if time.time() - t0 >= args.cpu_seconds:
-            break
-    dt = (time.time() - t0) / reps
+    # the oracle's own bytes: float64 CSR (8 B value + 4 B column per entry,
+    # the int64 row pointer, float64 x and y once)
+    csr_bytes = 12 * a.nnz + 8 * (a.n + 1) + 8 * a.m + 8 * a.n
+
+    def timed(seconds):
+        reps, t0 = 0, time.time()
+        while True:
+            L.spmv(a.rowptr, a.col, q16, x_np)
+            reps += 1
+            if time.time() - t0 >= seconds:
+                return (time.time() - t0) / reps, reps
+
     cores = native.num_threads()
+    dt, reps = timed(args.cpu_seconds / 2)
+    native.set_num_threads(1)
+    dt1, reps1 = timed(args.cpu_seconds / 2)
+    native.set_num_threads(cores)
     errors = {}
     for name, r in results.items():
         y = r["y"].double().cpu().numpy()
@@ -799,18 +946,30 @@ def cpu_leg(args, a, x_np, results, H, torch):
             den = L.inf_norm(a.rowptr, vals) * np.abs(x_np).max()
             errors[name] = {"vs_oracle_same_values": float(np.abs(y - ref).max() / den),
                             "backward_error_eq5": float(np.abs(y - full).max() / den)}
-    for name, m, xx, ys in EXTRA_CHECKS:
+    for name, (m, xx, ys) in EXTRA_CHECKS.items():
         xd = xx.astype(np.float64)
         full = L.spmv(m.rowptr, m.col, m.val, xd)
         den = L.inf_norm(m.rowptr, m.val) * np.abs(xd).max()
-        for var, y in ys.items():
-            errors[f"{name}.{var}"] = {"backward_error_eq5": float(np.abs(y - full).max() / den)}
-    return {"value": round(H["bytes"] / dt / 1e9, 2), "unit": "GB/s", "cores": cores,
+        for var, (y, fmt, D) in ys.items():
+            y = y.astype(np.float64)
+            e = {"backward_error_eq5": float(np.abs(y - full).max() / den)}
+            q = quantised(m, fmt, D)
+            if q is not None:
+                ref = L.spmv(m.rowptr, m.col, q, xd)
+                e["vs_oracle_same_q"] = float(np.abs(y - ref).max() /
+                                              (L.inf_norm(m.rowptr, q) * np.abs(xd).max()))
+            errors[f"{name}.{var}"] = e
+    return {"value": round(csr_bytes / dt / 1e9, 2), "unit": "GB/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{reps} full float64 CSR SpMVs of the same matrix on the host "
-                      f"({dt * 1e3:.1f} ms each); rate = the PackSELL product's bytes per "
-                      f"oracle product time",
+            "sample": f"{reps} float64 CSR SpMVs of the 7-point {round(a.n ** (1 / 3))}^3 "
+                      f"Laplacian (FP16-quantised values) on {cores} host threads, "
+                      f"{dt * 1e3:.1f} ms each, and {reps1} on one thread, {dt1 * 1e3:.1f} ms "
+                      f"each; rate = the oracle's own CSR bytes ({csr_bytes} per product) "
+                      f"per product time",
             "ms_per_spmv": round(dt * 1e3, 3),
+            "single_thread": {"value": round(csr_bytes / dt1 / 1e9, 3), "unit": "GB/s",
+                              "ms_per_spmv": round(dt1 * 1e3, 3), "cores": 1},
+            "oracle_ms_over_gpu_ms": round(dt / H["ms"], 1),
             "errors": errors}
 
 

@@ -77,6 +77,11 @@ extern "C" {
  * float32 x and y, float32 accumulation: the plain-SELL counterpart of the
  * FP16 PackSELL words (int32 column + 2-byte value per slot). */
 #define PKSELL_F16 2
+/* SELL values only: float32 values with their int32 columns side by side,
+ * one 8-byte slot per entry (column in the low 4 bytes, value bits in the
+ * high 4), float32 vectors: one load per slot instead of two.  S->val
+ * points to the uint64 slots; S->col is not used (may be NULL). */
+#define PKSELL_F32_PAIRED 12
 
 /* A PackSELL matrix.  pksell_encode_query() fills the shape and parameter
  * fields; the analyse phase of pksell_encode() fills n_words, n_dummies and
@@ -344,20 +349,23 @@ int pksell_trsv_csr(const int64_t *rowptr, const int32_t *col,
  * Plain SELL-C-sigma (sec. 3), the comparator and the float64 operator.
  * ---------------------------------------------------------------------- */
 
-/* As pksell_encode_query for SELL; dtype is PKSELL_F32, PKSELL_F64 or
- * PKSELL_F16 (the value type; vectors are float32 for F16). */
+/* As pksell_encode_query for SELL; dtype is PKSELL_F32, PKSELL_F64,
+ * PKSELL_F16 or PKSELL_F32_PAIRED (the value type and slot layout; vectors
+ * are float32 for F16 and F32_PAIRED). */
 int pksell_sell_query(int64_t n, int64_t m, int64_t nnz, int32_t C,
                       int32_t sigma, int32_t dtype, int32_t perm_mode,
                       pksell_sell *S, size_t *ws_bytes);
 
 /* As pksell_encode: analyse when S->val == NULL (needs S->offset, S->perm;
- * synchronises; fills S->n_slots), fill otherwise (needs S->col, S->val). */
+ * synchronises; fills S->n_slots), fill otherwise (needs S->val, and S->col
+ * unless the slots are paired). */
 int pksell_sell_encode(const int64_t *rowptr, const int32_t *col,
                        const void *val, int32_t val_dtype, pksell_sell *S,
                        void *ws, size_t ws_bytes, void *stream);
 
-/* y = S x in S->dtype (x: m, y: n, of S->dtype), accumulated in S->dtype;
- * for PKSELL_F16, x and y are float32 and the sums float32. */
+/* y = S x in S->dtype (x: m, y: n, of S->dtype), accumulated in S->dtype
+ * with one fused multiply-add per slot in slot order; for PKSELL_F16 and
+ * PKSELL_F32_PAIRED, x and y are float32 and the sums float32. */
 int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y,
                      void *stream);
 
@@ -460,6 +468,69 @@ int pksell_pcg64(const pksell_matrix *A_lo, const pksell_matrix *A_hi,
                  const double *b, double *x, double tol, int32_t m_in,
                  int32_t max_outer, pksell_pcg_info *info, void *ws,
                  size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * F3R nested Krylov solver (sec. 5.2.1): A x = b with
+ * ||b - A x||_2 / ||b||_2 < tol (eq. 6), for square (not necessarily
+ * symmetric) A.
+ * ---------------------------------------------------------------------- */
+
+/* Layer parameters.  The paper takes them from the solver's own defaults
+ * and names no values; ours are the caller's choice (the Python binding
+ * uses m1 = 100, m2 = 8, m3 = 4, m4 = 2, omega = 1). */
+typedef struct pksell_f3r_params {
+  int32_t m1;         /* outer FGMRES steps per restart cycle, 1..200 */
+  int32_t m2;         /* second-layer FGMRES steps (one cycle from zero), 1..32 */
+  int32_t m3;         /* third-layer FGMRES steps (one cycle from zero), 1..32 */
+  int32_t m4;         /* Richardson iterations from zero, 1..32 */
+  double omega;       /* Richardson weight (> 0); its preconditioner is the identity */
+  int32_t max_cycles; /* outer restart cycles before PKSELL_ENOTCONV, >= 1 */
+  int32_t reserved;
+} pksell_f3r_params;
+
+/* Workspace bytes of pksell_f3r for n rows; mixed != 0 for the
+ * mixed-precision form (float32 inner vectors), 0 for the all-float64 form.
+ * About (2 m1 + 3) n float64 values plus (2 m2 + 2 m3 + 3) n inner values. */
+int pksell_f3r_workspace(int64_t n, int32_t mixed, const pksell_f3r_params *prm,
+                         size_t *ws_bytes);
+
+/* F3R: an outer flexible GMRES(m1) in float64 on A1 (float64 SELL),
+ * restarted until the true relative residual passes tol, preconditioned by
+ * one FGMRES(m2) cycle, preconditioned by one FGMRES(m3) cycle,
+ * preconditioned by m4 Richardson iterations.  The inner layers run a fixed
+ * number of steps from zero, with no convergence test.
+ *
+ *  - A2 == NULL: every layer uses A1 with float64 vectors (FP64-F3R); A3_sell
+ *    and A3_pack must be NULL.
+ *  - A2 != NULL (float32 SELL, plain or paired slots): layers 2-4 keep
+ *    float32 vectors; layer 2
+ *    multiplies with A2, layers 3 and 4 with exactly one of A3_sell (SELL
+ *    with half or float32 values) and A3_pack (32-bit PackSELL words: FP16,
+ *    E8MY or FIX, no split).  Half-value SELL and FP16 PackSELL words of the
+ *    same matrix give bit-identical products, so the two forms give
+ *    bit-identical iterates (the paper's FP16-F3R and PackSELL-F3R).
+ *
+ * All matrices are n x n in implicit (original) row order.  Gram-Schmidt is
+ * classical with one reorthogonalisation; dot products, the Hessenberg
+ * matrices, rotations and the small triangular solves are float64, each
+ * reduction in one fixed order (results repeat bit for bit).  No
+ * preconditioner is applied inside the Richardson layer: scale the system
+ * (Gbar^-1 A Gbar^-1, sec. 5.2) beforehand.  x (float64, n) holds the
+ * initial guess on entry and the solution on return.  The outer layer
+ * checks its residual estimate after every step and the true residual
+ * b - A1 x (float64) at the end of each cycle, restarting from it.
+ * ``info``: outer_iterations = outer steps over all cycles,
+ * inner_iterations = second-layer steps (outer steps x m2), the final true
+ * relative residual and the wall time.  The call SYNCHRONISES: it waits for
+ * ``stream``, runs on a private stream (each outer step replayed from one
+ * captured HIP graph, the host polling the residual estimate) and returns
+ * when done.  PKSELL_ENOTCONV after max_cycles cycles (x holds the last
+ * iterate), PKSELL_EBREAKDOWN when a residual is not finite,
+ * PKSELL_EWORKSPACE when ws_bytes is below pksell_f3r_workspace's size. */
+int pksell_f3r(const pksell_sell *A1, const pksell_sell *A2, const pksell_sell *A3_sell,
+               const pksell_matrix *A3_pack, const double *b, double *x, double tol,
+               const pksell_f3r_params *prm, pksell_pcg_info *info, void *ws, size_t ws_bytes,
+               void *stream);
 
 #ifdef __cplusplus
 }

@@ -27,6 +27,8 @@ void oracle_csr_spmv_t(int64_t n, int64_t m, const int64_t *rowptr,
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) y[col[e]] += val[e] * g[i];
 }
 
+void oracle_set_num_threads(int t) { omp_set_num_threads(t); }
+
 int oracle_num_threads(void) {
   int t = 1;
 #pragma omp parallel

@@ -36,6 +36,8 @@ def lib():
         L.oracle_csr_spmv_t.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -68,3 +70,9 @@ def csr_spmv_t(rowptr, col, val, g, m: int) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads of the following parallel loops (the CPU baseline times one
+    thread and all of them)."""
+    lib().oracle_set_num_threads(int(t))

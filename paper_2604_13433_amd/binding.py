@@ -20,6 +20,7 @@ OK, EINVAL, ERANGE, EWORKSPACE, EHIP, ENOTCONV, EBREAKDOWN = 0, -1, -2, -3, -4, 
 FP16, E8MY, FIX, E11MY, E5MY, FIX16 = 0, 1, 2, 3, 4, 5  # E5MY, FIX16: 16-bit words
 EXPLICIT, IMPLICIT = 0, 1
 F32, F64, F16 = 4, 8, 2  # F16: SELL half values (float32 vectors)
+F32_PAIRED = 12  # SELL float32 values and int32 columns in one 8-byte slot
 FMT_BY_NAME = {"fp16": FP16, "e8my": E8MY, "fix": FIX, "e11my": E11MY, "e5my": E5MY,
                "fix16": FIX16}
 W16 = (E5MY, FIX16)
@@ -63,6 +64,11 @@ class CBatch(ctypes.Structure):
                 ("items", vp), ("unit_start", vp)]
 
 
+class CF3RParams(ctypes.Structure):
+    _fields_ = [("m1", i32), ("m2", i32), ("m3", i32), ("m4", i32), ("omega", ctypes.c_double),
+                ("max_cycles", i32), ("reserved", i32)]
+
+
 class CPcgInfo(ctypes.Structure):
     _fields_ = [("outer_iterations", i32), ("inner_iterations", i32),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
@@ -104,6 +110,11 @@ _PROTOS.update({
                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_pcg": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CSell), vp, vp, ctypes.c_double,
                     i32, i32, ctypes.POINTER(CPcgInfo), vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "pksell_f3r_workspace": ([i64, i32, ctypes.POINTER(CF3RParams),
+                              ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pksell_f3r": ([ctypes.POINTER(CSell), ctypes.POINTER(CSell), ctypes.POINTER(CSell),
+                    ctypes.POINTER(CMatrix), vp, vp, ctypes.c_double, ctypes.POINTER(CF3RParams),
+                    ctypes.POINTER(CPcgInfo), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "pksell_pcg64_workspace": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CMatrix),
                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_pcg64": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CMatrix), vp, vp, ctypes.c_double,
@@ -558,6 +569,11 @@ class SellMatrix:
     def value_dtype(self):
         return {F64: torch.float64, F16: torch.float16}.get(self.desc.dtype, torch.float32)
 
+    @property
+    def paired(self) -> bool:
+        """Column and value side by side in one 8-byte slot."""
+        return self.desc.dtype == F32_PAIRED
+
     def bytes_per_spmv(self) -> int:
         d = self.desc
         vb = {F64: 8, F16: 2}.get(d.dtype, 4)  # value bytes per slot
@@ -583,7 +599,11 @@ class SellMatrix:
 
 
 def sell_encode(rowptr, col, val, n: int, m: int, dtype=torch.float32, C: int = 64,
-                sigma: int = 256, perm_mode: int = IMPLICIT, device="cuda") -> SellMatrix:
+                sigma: int = 256, perm_mode: int = IMPLICIT, device="cuda",
+                paired: bool = False) -> SellMatrix:
+    """Plain SELL-C-sigma with ``dtype`` values (float32, float64 or half).
+    ``paired`` (float32 only) stores each float32 value beside its int32
+    column in one 8-byte slot, read with one load per slot."""
     device = torch.device(device)
     rp = _dev(rowptr, torch.int64, device)
     cl = _dev(col, torch.int32, device)
@@ -591,6 +611,9 @@ def sell_encode(rowptr, col, val, n: int, m: int, dtype=torch.float32, C: int = 
         (isinstance(val, torch.Tensor) and val.dtype == torch.float64) else torch.float32
     vl = _dev(val, vdt, device)
     code = {torch.float64: F64, torch.float16: F16}.get(dtype, F32)
+    _require(not paired or code == F32, "paired slots hold float32 values")
+    if paired:
+        code = F32_PAIRED
     desc = CSell()
     ws_bytes = ctypes.c_size_t()
     L = lib()
@@ -606,8 +629,11 @@ def sell_encode(rowptr, col, val, n: int, m: int, dtype=torch.float32, C: int = 
     vcode = F64 if vdt == torch.float64 else F32
     _check(L.pksell_sell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
                                 _ptr(ws), ws_bytes.value, st))
-    t["col"] = torch.empty(max(1, desc.n_slots), dtype=torch.int32, device=device)
-    t["val"] = torch.empty(max(1, desc.n_slots), dtype=dtype, device=device)
+    if paired:
+        t["val"] = torch.empty(max(1, desc.n_slots), dtype=torch.int64, device=device)
+    else:
+        t["col"] = torch.empty(max(1, desc.n_slots), dtype=torch.int32, device=device)
+        t["val"] = torch.empty(max(1, desc.n_slots), dtype=dtype, device=device)
     S._bind()
     _check(L.pksell_sell_encode(_ptr(rp), _ptr(cl), _ptr(vl), vcode, ctypes.byref(desc),
                                 _ptr(ws), ws_bytes.value, st))
@@ -653,6 +679,42 @@ def pcg(A_lo: PackSELLMatrix | None, A_hi, b: torch.Tensor,
                     inner_iterations=info.inner_iterations,
                     rel_residual=info.rel_residual, seconds=info.seconds, status=st)
     if check and st not in (OK,):
+        raise PackSELLError(st, L.pksell_last_error().decode())
+    return x, out
+
+
+def f3r(A1: "SellMatrix", b: torch.Tensor, A2: "SellMatrix | None" = None, A3=None,
+        x0: torch.Tensor | None = None, tol: float = 1e-10, m1: int = 100, m2: int = 8,
+        m3: int = 4, m4: int = 2, omega: float = 1.0, max_cycles: int = 100,
+        check: bool = True):
+    """Solve A x = b with the F3R nested solver (sec. 5.2.1).  ``A1`` is the
+    float64 SELL operator of the outer layer.  With ``A2`` None every layer
+    runs on A1 in float64 (FP64-F3R); otherwise ``A2`` (float32 SELL) is the
+    second layer's operator and ``A3`` (half-value SELL, or a PackSELL matrix
+    with 32-bit words) that of layers 3 and 4, with float32 vectors.
+    Returns (x, info)."""
+    _block(b, torch.float64, A1.n, 1, "b")
+    _require(A2 is not None or A3 is None, "A3 needs A2 (the mixed-precision form)")
+    _require(A2 is None or A3 is not None, "the mixed-precision form needs A3")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    _block(x, torch.float64, A1.n, 1, "x0")
+    prm = CF3RParams(m1, m2, m3, m4, float(omega), max_cycles, 0)
+    L = lib()
+    ws_bytes = ctypes.c_size_t()
+    _check(L.pksell_f3r_workspace(A1.n, int(A2 is not None), ctypes.byref(prm),
+                                  ctypes.byref(ws_bytes)))
+    ws = torch.empty(max(1, ws_bytes.value), dtype=torch.uint8, device=b.device)
+    a2 = ctypes.byref(A2.desc) if A2 is not None else None
+    a3s = ctypes.byref(A3.desc) if isinstance(A3, SellMatrix) else None
+    a3p = ctypes.byref(A3.desc) if isinstance(A3, PackSELLMatrix) else None
+    info = CPcgInfo()
+    st = L.pksell_f3r(ctypes.byref(A1.desc), a2, a3s, a3p, _ptr(b), _ptr(x), tol,
+                      ctypes.byref(prm), ctypes.byref(info), _ptr(ws), ws_bytes.value,
+                      _stream(b.device))
+    out = SolveInfo(outer_iterations=info.outer_iterations,
+                    inner_iterations=info.inner_iterations,
+                    rel_residual=info.rel_residual, seconds=info.seconds, status=st)
+    if check and st != OK:
         raise PackSELLError(st, L.pksell_last_error().decode())
     return x, out
 

@@ -456,6 +456,37 @@ __device__ inline OT sell_value(const VT *v, int64_t e) {
   else return (OT)v[e];
 }
 
+// One paired slot: the column in the low 4 bytes, the float32 value bits in
+// the high 4 (float64 input rounded to float32 first).
+template <typename VT>
+__device__ inline uint64_t sell_slot(const VT *v, int64_t e, int32_t c) {
+  const float f = (float)load_value(v, e);
+  return (uint64_t)(uint32_t)c | ((uint64_t)__float_as_uint(f) << 32);
+}
+
+template <typename VT>
+__global__ void k_fill_sell_paired(const int64_t *__restrict__ rowptr,
+                                   const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                   int64_t n, int32_t C, int64_t n_slices,
+                                   const int32_t *__restrict__ stored_rows,
+                                   const int64_t *__restrict__ offset, uint64_t *__restrict__ slot) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slices * C) return;
+  int64_t k = i / C, l = i - k * C;
+  int64_t s = offset[k];
+  int64_t w = (offset[k + 1] - s) / C;
+  int64_t j = 0;
+  int32_t last = 0;
+  if (i < n) {
+    int64_t r = stored_rows[i];
+    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e, ++j) {
+      last = col[e];
+      slot[s + j * C + l] = sell_slot(val, e, last);
+    }
+  }
+  for (; j < w; ++j) slot[s + j * C + l] = (uint64_t)(uint32_t)last;  // value 0
+}
+
 template <typename VT, typename OT>
 __global__ void k_fill_sell(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                             const VT *__restrict__ val, int64_t n, int32_t C, int64_t n_slices,
@@ -798,8 +829,9 @@ int pksell_sell_query(int64_t n, int64_t m, int64_t nnz, int32_t C, int32_t sigm
   PKS_CHECK(S && ws_bytes, PKSELL_EINVAL, "null argument");
   int rc = check_common(n, m, nnz, C, sigma, perm_mode);
   if (rc) return rc;
-  PKS_CHECK(dtype == PKSELL_F32 || dtype == PKSELL_F64 || dtype == PKSELL_F16, PKSELL_EINVAL,
-            "bad dtype");
+  PKS_CHECK(dtype == PKSELL_F32 || dtype == PKSELL_F64 || dtype == PKSELL_F16 ||
+                dtype == PKSELL_F32_PAIRED,
+            PKSELL_EINVAL, "bad dtype");
   std::memset(S, 0, sizeof(*S));
   S->n = n;
   S->m = m;
@@ -833,10 +865,24 @@ int pksell_sell_encode(const int64_t *rowptr, const int32_t *col, const void *va
     S->n_slots = h.n_words;
     return PKSELL_OK;
   }
-  PKS_CHECK(S->col, PKSELL_EINVAL, "null S->col");
+  const bool paired = S->dtype == PKSELL_F32_PAIRED;
+  PKS_CHECK(paired || S->col, PKSELL_EINVAL, "null S->col");
   const int64_t rows = S->n_slices * S->C;
   if (rows == 0) return PKSELL_OK;
   const int64_t g = cdiv(rows, kBlock);
+  if (paired) {
+    if (val_dtype == PKSELL_F32)
+      k_fill_sell_paired<float><<<g, kBlock, 0, st>>>(rowptr, col, static_cast<const float *>(val),
+                                                      S->n, S->C, S->n_slices, p.stored_rows,
+                                                      S->offset, static_cast<uint64_t *>(S->val));
+    else
+      k_fill_sell_paired<double><<<g, kBlock, 0, st>>>(rowptr, col,
+                                                       static_cast<const double *>(val), S->n,
+                                                       S->C, S->n_slices, p.stored_rows,
+                                                       S->offset, static_cast<uint64_t *>(S->val));
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
 #define PKS_SFILL(VT, OT)                                                                   \
   k_fill_sell<VT, OT><<<g, kBlock, 0, st>>>(rowptr, col, static_cast<const VT *>(val), S->n, \
                                             S->C, S->n_slices, p.stored_rows, S->offset,     \

@@ -11,6 +11,7 @@
 // float32, in word order.  Workgroups are remapped so each XCD walks one
 // contiguous range of slices and its L2 serves the x window they share.
 #include <algorithm>
+#include <type_traits>
 
 #include "rowdot.hpp"
 
@@ -324,6 +325,20 @@ __global__ void k_fill_zero(T *p, int64_t len) {
   if (i < len) p[i] = T(0);
 }
 
+// Value type tag of paired SELL slots: one uint64 per slot, the column in
+// the low 4 bytes and the float32 value bits in the high 4.
+struct Paired {
+  uint64_t u;
+};
+template <typename VT>
+constexpr bool kPairedVT = std::is_same<VT, Paired>::value;
+
+// One fused multiply-add in the vector type: SELL sums products exactly as
+// the PackSELL kernels do (fmaf in slot order), so half-value SELL and FP16
+// words give bit-identical results on the same values.
+__device__ inline float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fma_t(double a, double b, double c) { return fma(a, b, c); }
+
 // Plain SELL-C-sigma SpMV (sec. 3): the float32 / float64 / half-value
 // comparator, with the same lane mapping and batched loads as the PackSELL
 // kernel.  Values are VT (T, or half with T = float), vectors and sums T.
@@ -342,10 +357,11 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
   const RowOut dst = row_out(perm, perm_bytes, t, n, g);
   const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)C;
   T acc = 0;
-  const int32_t *pc = scol + ln.s + ln.l;
+  const int32_t *pc = kPairedVT<VT> ? nullptr : scol + ln.s + ln.l;
   const VT *pv = sval + ln.s + ln.l;
   // (BUF implies C = 64, where ln.s is wave-uniform)
-  const __amdgpu_buffer_rsrc_t rc = BUF ? make_rsrc(scol + ln.s, w * 256u) : make_rsrc(scol, 0u);
+  const __amdgpu_buffer_rsrc_t rc =
+      BUF && !kPairedVT<VT> ? make_rsrc(scol + ln.s, w * 256u) : make_rsrc(scol, 0u);
   const __amdgpu_buffer_rsrc_t rv =
       BUF ? make_rsrc(sval + ln.s, w * kWave * (uint32_t)sizeof(VT)) : make_rsrc(sval, 0u);
   for (uint32_t j = 0; j < w; j += G) {
@@ -354,7 +370,14 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
 #pragma unroll
     for (int q = 0; q < G; ++q) {
       const bool in = j + q < w;
-      if constexpr (BUF) {
+      if constexpr (kPairedVT<VT>) {  // one 8-byte load per slot
+        uint64_t u = 0;
+        if (in)
+          u = BUF ? stream_elem<uint64_t>(rv, ln.l, j + q)
+                  : __builtin_nontemporal_load(&pv[(j + q) * stride].u);
+        cc[q] = (int32_t)(uint32_t)u;
+        vv[q] = __uint_as_float((uint32_t)(u >> 32));
+      } else if constexpr (BUF) {
         cc[q] = in ? stream_elem<int32_t>(rc, ln.l, j + q) : 0;
         vv[q] = in ? (T)stream_elem<VT>(rv, ln.l, j + q) : T(0);
       } else {
@@ -364,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
     }
 #pragma unroll
     for (int q = 0; q < G; ++q)
-      if (j + q < w) acc += vv[q] * x[cc[q]];
+      if (j + q < w) acc = fma_t(vv[q], x[cc[q]], acc);
   }
   if (t >= n) return;
   y[dst.row()] = acc;
@@ -402,7 +425,7 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
   for (int i = 0; i < S; ++i) {
     w[i] = (uint32_t)((off[i + 1] - off[i]) >> 6);
     wm = max(wm, w[i]);
-    rc[i] = make_rsrc(scol + off[i], w[i] * 256u);
+    rc[i] = kPairedVT<VT> ? make_rsrc(scol, 0u) : make_rsrc(scol + off[i], w[i] * 256u);
     rv[i] = make_rsrc(sval + off[i], w[i] * kWave * (uint32_t)sizeof(VT));
     acc[i] = T(0);
   }
@@ -414,8 +437,14 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
 #pragma unroll
       for (int q = 0; q < G; ++q) {
         const bool in = j + q < w[i];
-        cc[i][q] = in ? stream_elem<int32_t>(rc[i], lane, j + q) : 0;
-        vv[i][q] = in ? (T)stream_elem<VT>(rv[i], lane, j + q) : T(0);
+        if constexpr (kPairedVT<VT>) {  // one 8-byte load per slot
+          const uint64_t u = in ? stream_elem<uint64_t>(rv[i], lane, j + q) : 0ull;
+          cc[i][q] = (int32_t)(uint32_t)u;
+          vv[i][q] = __uint_as_float((uint32_t)(u >> 32));
+        } else {
+          cc[i][q] = in ? stream_elem<int32_t>(rc[i], lane, j + q) : 0;
+          vv[i][q] = in ? (T)stream_elem<VT>(rv[i], lane, j + q) : T(0);
+        }
       }
     T xv[S][G];
 #pragma unroll
@@ -426,7 +455,7 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
     for (int i = 0; i < S; ++i)
 #pragma unroll
       for (int q = 0; q < G; ++q)
-        if (j + q < w[i]) acc[i] += vv[i][q] * xv[i][q];
+        if (j + q < w[i]) acc[i] = fma_t(vv[i][q], xv[i][q], acc[i]);
   }
 #pragma unroll
   for (int i = 0; i < S; ++i) {
@@ -718,6 +747,19 @@ void launch_sell_pair(const pksell_sell *S, const void *x, void *y, const void *
 int spmv16(const pksell_matrix *A, const float *x, float *y, int64_t k, hipStream_t st);
 int spmv_chunks(const pksell_matrix *A, const float *x, float *y, int64_t k, hipStream_t st);
 
+// The chunk plan of a CSR-packed matrix serves k = 1, 2 and 4; its k = 4
+// form gathers 16-byte x rows, so a misaligned x takes the one-row-slice
+// product instead.
+bool chunk_path(const pksell_matrix *A, const float *x, int64_t k) {
+  const bool x16 = ((uintptr_t)x & 15) == 0;
+  return (k == 1 || k == 2 || (k == 4 && x16)) && A->C == 1 && A->split_words > 0;
+}
+
+// Split wide slices run one work unit per wave for single-vector products.
+bool split_path(const pksell_matrix *A, int64_t k) {
+  return k == 1 && A->C == kWave && A->split_words > 0 && A->n_split_units > 0;
+}
+
 }  // namespace pksell
 
 using namespace pksell;
@@ -735,13 +777,9 @@ int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, voi
   if (A->n == 0) return PKSELL_OK;
   if (A->m == 0) return zero_f32(y, A->n * k, st);
   PKS_CHECK(x, PKSELL_EINVAL, "null x");
-  // The chunk plan serves k = 1, 2 and 4; its k = 4 form gathers 16-byte x
-  // rows, so a misaligned x takes the one-row-slice product below instead.
-  const bool x16 = ((uintptr_t)x & 15) == 0;
-  if ((k == 1 || k == 2 || (k == 4 && x16)) && A->C == 1 && A->split_words > 0)
-    return spmv_chunks(A, x, y, k, st);
+  if (chunk_path(A, x, k)) return spmv_chunks(A, x, y, k, st);
   SpmvArgs a = make_args(A, x, y, k);
-  if (k == 1 && A->C == kWave && A->split_words > 0 && A->n_split_units > 0) {
+  if (split_path(A, k)) {
     PKS_CHECK(A->units && A->splits && A->ckpt && A->partial, PKSELL_EINVAL,
               "split slices need units, splits, ckpt and partial");
     PKS_CHECK(A->n_units < (int64_t(1) << 31) && A->n_split_units * kWave < (int64_t(1) << 32),
@@ -827,7 +865,8 @@ int pksell_decode(const pksell_matrix *A, int32_t *cols, float *vals, void *stre
 int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream) {
   PKS_CHECK(S, PKSELL_EINVAL, "null matrix");
   PKS_CHECK(S->n == 0 || (S->offset && y), PKSELL_EINVAL, "arrays not set");
-  PKS_CHECK(S->n_slots == 0 || (S->col && S->val), PKSELL_EINVAL, "arrays not set");
+  PKS_CHECK(S->n_slots == 0 || ((S->col || S->dtype == PKSELL_F32_PAIRED) && S->val),
+            PKSELL_EINVAL, "arrays not set");
   PKS_CHECK(S->perm_mode != PKSELL_IMPLICIT || S->n == 0 || S->perm, PKSELL_EINVAL,
             "implicit mode needs perm");
   hipStream_t st = as_stream(stream);
@@ -855,10 +894,17 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
     if (S->dtype == PKSELL_F16) {
       if (perm) launch_sell_pair<true, _Float16>(S, x, y, perm, G, pg, st);
       else launch_sell_pair<false, _Float16>(S, x, y, perm, G, pg, st);
+    } else if (S->dtype == PKSELL_F32_PAIRED) {
+      if (perm) launch_sell_pair<true, Paired>(S, x, y, perm, G, pg, st);
+      else launch_sell_pair<false, Paired>(S, x, y, perm, G, pg, st);
     } else {
       if (perm) launch_sell_pair<true, float>(S, x, y, perm, G, pg, st);
       else launch_sell_pair<false, float>(S, x, y, perm, G, pg, st);
     }
+  } else if (S->dtype == PKSELL_F32_PAIRED) {
+    if (buf) PKS_SELL(float, true, true, Paired);
+    else if (S->C == kWave) PKS_SELL(float, true, false, Paired);
+    else PKS_SELL(float, false, false, Paired);
   } else if (S->dtype == PKSELL_F16) {
     if (buf) PKS_SELL(float, true, true, _Float16);
     else if (S->C == kWave) PKS_SELL(float, true, false, _Float16);

@@ -167,3 +167,58 @@ def test_iocg_with_16_bit_inner_operator(fmt, D):
     assert ref.converged
     assert np.max(np.abs(x - ref.x)) < 1e-7
     assert abs(info["outer_iterations"] - ref.iterations) <= max(2, ref.iterations // 3)
+
+
+@pytest.fixture(scope="module")
+def m4():
+    """The 27-point 100^3 system (n = 10^6, 26.5 M nonzeros), symmetrically
+    scaled, b = A 1, and the oracle's float64 CG on it."""
+    a = W.symmetric_diag_scale(W.m4_stencil27())
+    b = W.ones_rhs(a)
+    return a, b, L.cg(a.rowptr, a.col, a.val, b, tol=1e-10)
+
+
+def _true_residual(a, val, b, x):
+    return np.linalg.norm(b - L.spmv(a.rowptr, a.col, val, x)) / np.linalg.norm(b)
+
+
+def test_m4_full_size_fp64_cg(m4):
+    a, b, ref = m4
+    assert ref.converged
+    _, hi = operators(a)
+    x, info = B.pcg(None, hi, torch.from_numpy(b).to(DEV), tol=1e-10, max_outer=5000)
+    x = x.cpu().numpy()
+    assert info["rel_residual"] < 1e-10 and _true_residual(a, a.val, b, x) < 1e-10
+    assert np.max(np.abs(x - ref.x)) < 1e-7 and np.max(np.abs(x - 1.0)) < 1e-7
+    assert abs(info["outer_iterations"] - ref.iterations) <= max(3, ref.iterations // 50)
+
+
+@pytest.mark.parametrize("outer", ["sell", "e11my"])
+def test_m4_full_size_iocg_e8m8(m4, outer):
+    """IO-CG with an E8M8 inner operator (D = 14, no dummies on this
+    matrix) and m_in = 20; the float64 operator is FP64 SELL or 64-bit
+    E11M37 words.  x, the outer and inner iteration counts and the true
+    residual follow the oracle's inner-outer CG on the same quantised
+    values."""
+    from oracle import packsell64 as P64
+
+    a, b, _ = m4
+    lo = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e8my", 14, 64, 256, B.IMPLICIT, DEV)
+    if outer == "sell":
+        hi = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float64, 64, 256, B.IMPLICIT,
+                           DEV)
+        q_hi = a.val
+    else:
+        hi = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e11my", 14, 64, 256, B.IMPLICIT, DEV)
+        q_hi = P64.quantized(a.val, 14)
+    x, info = B.pcg(lo, hi, torch.from_numpy(b).to(DEV), tol=1e-10, m_in=20, max_outer=500)
+    x = x.cpu().numpy()
+    q_lo = P.quantized_values(a.rowptr, a.col, a.val, a.n, F.FMT_E8MY, 14)
+    ref = L.iocg(a.rowptr, a.col, q_hi, q_lo, b, m_in=20, tol=1e-10)
+    assert ref.converged
+    assert info["rel_residual"] < 1e-10 and _true_residual(a, q_hi, b, x) < 1e-10
+    assert np.max(np.abs(x - ref.x)) < 1e-7
+    assert abs(info["outer_iterations"] - ref.iterations) <= max(2, ref.iterations // 3)
+    # no inner breakdown on this matrix: every outer step runs its m_in inner steps
+    assert info["inner_iterations"] == info["outer_iterations"] * 20
+    assert ref.inner_iterations == ref.iterations * 20

@@ -190,10 +190,12 @@ def test_sell_fp32_fp64_fp16(C):
 
 def test_sell_fp16_matches_packsell_fp16_laplace3d_128():
     """SELL with half values holds the same values as the FP16 PackSELL
-    words (both round float32 to binary16, ties to even) and sums them in
-    the same order, so on the 128^3 Laplacian at the benchmark's launch
-    configuration (C = 64, sigma = 256, explicit order) the two products
-    agree to float32 rounding; both are checked against the oracle."""
+    words (both round float32 to binary16, ties to even) and sums them with
+    the same fused multiply-adds in the same order, so on the 128^3
+    Laplacian at the benchmark's launch configuration (C = 64, sigma = 256,
+    explicit order) the two products are bit-identical (the equivalence
+    behind the paper's identical convergence of its FP16 SELL and PackSELL
+    solvers, sec. 5.2.1); both are checked against the oracle."""
     a = W.m2_laplace3d()
     x = W.uniform_vector(a.m, 3)
     xd = torch.from_numpy(x).to(DEV)
@@ -206,8 +208,15 @@ def test_sell_fp16_matches_packsell_fp16_laplace3d_128():
     ref = L.spmv(a.rowptr, a.col, vals, x)[E.stored_rows]
     assert normalised_error(ys, ref, a, vals, x) <= SPMV_TOL
     assert normalised_error(yp, ref, a, vals, x) <= SPMV_TOL
-    den = L.inf_norm(a.rowptr, vals) * float(np.abs(x).max())
-    assert float(np.max(np.abs(ys - yp))) / den <= 2 * SPMV_TOL
+    assert np.array_equal(ys, yp)
+    # implicit order (the solvers' layout) and the one-slice-per-wave kernels
+    # (27 words per lane on the 27-point stencil) give identical results too
+    for g, mode in ((W.m2_laplace3d(), B.IMPLICIT), (W.m4_stencil27(48), B.IMPLICIT),
+                    (W.m4_stencil27(48), B.EXPLICIT)):
+        xg = torch.from_numpy(W.uniform_vector(g.m, 4)).to(DEV)
+        Sg = B.sell_encode(g.rowptr, g.col, g.val, g.n, g.m, torch.float16, 64, 256, mode, DEV)
+        Ag = B.encode(g.rowptr, g.col, g.val, g.n, g.m, "fp16", 15, 64, 256, mode, DEV)
+        assert torch.equal(B.sell_spmv(Sg, xg), B.spmv(Ag, xg)), (g.n, mode)
     # bytes: 6 per SELL slot (int32 column + half) against 4 per word
     assert S.n_slots == A.n_words
 
@@ -349,3 +358,25 @@ def test_save_and_load_roundtrip(tmp_path):
         assert A2.n_words == A.n_words and A2.k_left == A.k_left and A2.D == A.D
         assert torch.equal(A2.pack, A.pack)
         assert torch.equal(B.spmv(A2, x), B.spmv(A, x))
+
+
+@pytest.mark.parametrize("C", [64, 16])
+def test_sell_paired_slots_equal_plain_sell(C):
+    """SELL with the float32 value beside its column in one 8-byte slot holds
+    the same values in the same order as plain float32 SELL, so products are
+    bit-identical; also against the oracle, on random rows and on the 128^3
+    Laplacian (two slices per wave), both row orders."""
+    for a in (random_csr(13, 3000, 2500, per_row=12), W.m2_laplace3d(64)):
+        x = torch.from_numpy(W.uniform_vector(a.m, 14)).to(DEV)
+        for mode in (B.IMPLICIT, B.EXPLICIT):
+            S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, C, 256, mode, DEV)
+            Sp = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, C, 256, mode, DEV,
+                               paired=True)
+            assert Sp.paired and Sp.n_slots == S.n_slots
+            assert Sp.bytes_per_spmv() == S.bytes_per_spmv()
+            yp = B.sell_spmv(Sp, x)
+            assert torch.equal(yp, B.sell_spmv(S, x))
+            if mode == B.IMPLICIT:
+                vals = sell_values(a.val, torch.float32)
+                ref = L.spmv(a.rowptr, a.col, vals, x.cpu().numpy())
+                assert normalised_error(yp.cpu().numpy(), ref, a, vals, x.cpu().numpy()) <= SPMV_TOL
