@@ -242,6 +242,25 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val,
 int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k,
                 void *stream);
 
+/* pksell_spmv for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same product and the same result, bit for bit, but the scratch that
+ * products of CSR-packed matrices with a chunk plan (k = 1, 2, or 4 with
+ * 16-byte aligned x) and of split wide slices (k = 1) need comes from one
+ * 16 MiB float32 array that the library holds on each GPU until the process
+ * ends, instead of A->partial (which may then be NULL).  Such a product
+ * needs (2k + 1) * n_units floats (chunk plan) or 64 * n_split_units
+ * (split slices); beyond 2^22 floats the call returns PKSELL_ERANGE before
+ * any device work.  Other products need no scratch and run as pksell_spmv.
+ * The call allocates nothing.  Its first call on a device looks up that
+ * device's array (the stream must belong to the current device, else
+ * PKSELL_EINVAL).  Every call on one GPU shares that GPU's array, and each
+ * product writes all the scratch it reads: calls that overlap on one GPU
+ * (on different streams, or on one stream with a concurrent graph replay)
+ * race, so serialise them. */
+int pksell_spmv_static(const pksell_matrix *A, const float *x, float *y, int64_t k,
+                       void *stream);
+
 /* y = A_q^T g (the adjoint: grad_x of <g, A x>).  g is n x k in the row
  * order pksell_spmv produces; y (m x k) is zeroed on the stream and then
  * accumulated with float32 atomics, so the summation order is not fixed. */

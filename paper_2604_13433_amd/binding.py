@@ -84,6 +84,7 @@ _PROTOS = {
                              ctypes.POINTER(CMatrix), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_encode": ([vp, vp, vp, i32, ctypes.POINTER(CMatrix), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "pksell_spmv": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
+    "pksell_spmv_static": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
     "pksell_spmv_f64": ([ctypes.POINTER(CMatrix), vp, vp, vp], ctypes.c_int),
     "pksell_spmv_t": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
     "pksell_grad_values": ([ctypes.POINTER(CMatrix), vp, vp, vp, vp, i64, vp], ctypes.c_int),
@@ -501,6 +502,21 @@ def spmv(A: PackSELLMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> t
         y = torch.empty((A.n,) if x.dim() == 1 else (A.n, k), dtype=torch.float32, device=x.device)
     _block(y, torch.float32, A.n, k, "y")
     _check(lib().pksell_spmv(ctypes.byref(A.desc), _ptr(x), _ptr(y), k, _stream(x.device)))
+    return y
+
+
+def spmv_static(A: PackSELLMatrix, x: torch.Tensor,
+                y: torch.Tensor | None = None) -> torch.Tensor:
+    """``spmv`` through pksell_spmv_static: products that need scratch take
+    it from the library's per-GPU array, so the call allocates nothing
+    (given y).  Concurrent calls on one GPU race on that array."""
+    _block(x, torch.float32, A.m, None, "x")
+    k = 1 if x.dim() == 1 else x.shape[1]
+    if y is None:
+        y = torch.empty((A.n,) if x.dim() == 1 else (A.n, k), dtype=torch.float32, device=x.device)
+    _block(y, torch.float32, A.n, k, "y")
+    _check(lib().pksell_spmv_static(ctypes.byref(A.desc), _ptr(x), _ptr(y), k,
+                                    _stream(x.device)))
     return y
 
 

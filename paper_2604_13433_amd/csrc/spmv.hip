@@ -760,6 +760,16 @@ bool split_path(const pksell_matrix *A, int64_t k) {
   return k == 1 && A->C == kWave && A->split_words > 0 && A->n_split_units > 0;
 }
 
+// Floats of A->partial that pksell_spmv(A, x, ., k) uses as scratch: the
+// pieces of rows that cross chunk edges (chunk plan) or the per-chunk sums
+// of split slices; 0 when the product needs none.
+int64_t spmv_partial_floats(const pksell_matrix *A, const float *x, int64_t k) {
+  if (!A || is_w16(A->fmt) || A->n == 0 || A->m == 0) return 0;
+  if (chunk_path(A, x, k)) return (2 * k + 1) * A->n_units;
+  if (split_path(A, k)) return kWave * A->n_split_units;
+  return 0;
+}
+
 }  // namespace pksell
 
 using namespace pksell;
