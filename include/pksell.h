@@ -56,9 +56,9 @@ extern "C" {
 /* 16-bit words (sec. 4.2.1 with W = 16): a value word has its delta in bits
  * 1..D and 15 - D value bits; a dummy carries at most 2^15 - 1, so a larger
  * delta takes a chain of dummies (all but the last carrying 2^15 - 1)
- * before its value word.  C must be 64.  Products through pksell_spmv with
- * k = 1, and the solvers' inner operator (pksell_pcg, pksell_pcg64); every
- * other entry point rejects these formats. */
+ * before its value word.  C must be 64.  Products through pksell_spmv
+ * (any k), and the solvers' inner operator (pksell_pcg, pksell_pcg64);
+ * every other entry point rejects these formats. */
 #define PKSELL_E5MY 4  /* binary16-compatible float, Y = 9 - D mantissa bits
                           (the E8MY construction applied to binary16; D = 7 is
                           8-bit E5M2); 1 <= D <= 8 */
@@ -238,7 +238,8 @@ int pksell_encode(const int64_t *rowptr, const int32_t *col, const void *val,
  * implicit mode y is in the original row order, in explicit mode in stored
  * order.  1 <= k <= 64.  With k a multiple of 4 and x, y 16-byte aligned, x
  * is gathered and y stored four columns at a time.  16-bit words (E5MY,
- * FIX16): k = 1 only. */
+ * FIX16) take any such k too: k > 1 runs in passes of up to eight columns
+ * over the words. */
 int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k,
                 void *stream);
 
@@ -309,13 +310,16 @@ int pksell_csr_transpose(const int64_t *rowptr, const int32_t *col,
 int pksell_stream_read(const void *src, size_t bytes, int32_t width,
                        int32_t chunks, float *out, void *stream);
 
-/* y = A_q x in float64 for 64-bit-word matrices (fmt E11MY): x float64[m],
- * y float64[n] (original order in implicit mode, stored order in explicit
- * mode), accumulated in float64 in word order.  One right-hand side.  Not
- * in the paper as such: its W = 64 word with the E8MY value construction
- * applied to FP64, for FP64 operators at 8 bytes per stored word.  Other
- * product, adjoint, batched and solver entry points reject E11MY. */
-int pksell_spmv_f64(const pksell_matrix *A, const double *x, double *y, void *stream);
+/* y = A_q x in float64 for 64-bit-word matrices (fmt E11MY): x float64[m x k]
+ * and y float64[n x k], row-major, k in [1, 64] right-hand sides (rows of y
+ * in original order in implicit mode, stored order in explicit mode), each
+ * column accumulated in float64 in word order.  m * k < 2^29, else ERANGE.
+ * Not in the paper as such: its W = 64 word with the E8MY value
+ * construction applied to FP64, for FP64 operators at 8 bytes per stored
+ * word.  Other product, adjoint, batched and solver entry points reject
+ * E11MY. */
+int pksell_spmv_f64(const pksell_matrix *A, const double *x, double *y, int64_t k,
+                    void *stream);
 
 /* Decodes every word position: cols[p] = column reconstructed at word p
  * (running sum of deltas from the left offset), vals[p] = decoded value
@@ -452,7 +456,9 @@ int pksell_pcg_workspace(const pksell_matrix *A_lo, const pksell_sell *A_hi,
  *    encoding of the same matrix (implicit row order; FP16, E8MY or FIX
  *    words, or 16-bit E5MY or FIX16 words with C = 64), started from zero on
  *    the right-hand side r / ||r||.  Inner dot products, alpha and beta are
- *    accumulated in float64.  max_outer bounds outer iterations.
+ *    accumulated in float64.  max_outer bounds outer iterations.  The
+ *    inner vectors keep r and p as interleaved float32 pairs, so this form
+ *    takes n < 2^29 (their byte offsets fit 32 bits); larger n: EINVAL.
  *  - A_lo == NULL: plain float64 CG on A_hi (the baseline); max_outer bounds
  *    iterations, m_in is ignored.
  *

@@ -85,7 +85,7 @@ _PROTOS = {
     "pksell_encode": ([vp, vp, vp, i32, ctypes.POINTER(CMatrix), vp, ctypes.c_size_t, vp], ctypes.c_int),
     "pksell_spmv": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
     "pksell_spmv_static": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
-    "pksell_spmv_f64": ([ctypes.POINTER(CMatrix), vp, vp, vp], ctypes.c_int),
+    "pksell_spmv_f64": ([ctypes.POINTER(CMatrix), vp, vp, ctypes.c_int64, vp], ctypes.c_int),
     "pksell_spmv_t": ([ctypes.POINTER(CMatrix), vp, vp, i64, vp], ctypes.c_int),
     "pksell_grad_values": ([ctypes.POINTER(CMatrix), vp, vp, vp, vp, i64, vp], ctypes.c_int),
     "pksell_decode": ([ctypes.POINTER(CMatrix), vp, vp, vp], ctypes.c_int),
@@ -521,12 +521,14 @@ def spmv_static(A: PackSELLMatrix, x: torch.Tensor,
 
 
 def spmv_f64(A: PackSELLMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
-    """y = A_q x in float64 for a 64-bit-word (E11MY) matrix (x: m float64)."""
+    """y = A_q x in float64 for a 64-bit-word (E11MY) matrix (x: m or m x k
+    float64)."""
+    _block(x, torch.float64, A.m, None, "x")
+    k = 1 if x.dim() == 1 else x.shape[1]
     if y is None:
-        y = torch.empty(A.n, dtype=torch.float64, device=x.device)
-    _block(x, torch.float64, A.m, 1, "x")
-    _block(y, torch.float64, A.n, 1, "y")
-    _check(lib().pksell_spmv_f64(ctypes.byref(A.desc), _ptr(x), _ptr(y), _stream(x.device)))
+        y = torch.empty((A.n,) if x.dim() == 1 else (A.n, k), dtype=torch.float64, device=x.device)
+    _block(y, torch.float64, A.n, k, "y")
+    _check(lib().pksell_spmv_f64(ctypes.byref(A.desc), _ptr(x), _ptr(y), k, _stream(x.device)))
     return y
 
 

@@ -82,6 +82,17 @@ __device__ inline float buffer_load_f32(__amdgpu_buffer_rsrc_t r, uint32_t byte_
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
 }
 
+// Two consecutive floats (8-byte aligned) in one load; 0 past the resource.
+// The halves are taken from the 64-bit value by shifts: with this compiler,
+// a bit cast of one element of the builtin's vector result (or of a vector
+// copied from it) read element 0 for both halves.
+__device__ inline float2 buffer_load_f32x2(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  const uint64_t v =
+      __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  return make_float2(__builtin_bit_cast(float, lo), __builtin_bit_cast(float, hi));
+}
+
 // Left offset of eq. 4: uniform over each sigma-block of rows.
 __device__ __host__ inline uint32_t left_offset(int64_t row, int32_t sigma, int64_t k_left) {
   int64_t blk = (row / sigma) * sigma;

@@ -532,6 +532,54 @@ __global__ __launch_bounds__(kBlock) void k_spmv64(Spmv64Args a) {
   a.y[dst.row()] = acc;
 }
 
+// k right-hand sides in float64 (x m x k and y n x k, row-major): columns
+// r0 .. r0 + KB - 1 per launch, four words per group, each column's
+// products summed in word order as for k = 1.
+template <bool CWAVE, int KB>
+__global__ __launch_bounds__(kBlock) void k_spmv64k(Spmv64Args a, uint32_t k, uint32_t r0) {
+  constexpr int G = 4;
+  Lane ln;
+  if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
+  const uint32_t t = ln.t, w = ln.w;
+  const RowOut dst = row_out(a.perm, a.perm_bytes, t, a.n, a.geo);
+  const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)a.C;
+  const uint32_t kx = k * 8u, x0 = r0 * 8u;
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x, a.m * kx);
+  const uint32_t oob = a.m * kx;  // past the resource: 0, no request
+  const uint64_t *P = a.pack + ln.s + ln.l;
+  uint32_t c = left_offset32(t, a.geo);
+  double acc[KB];
+#pragma unroll
+  for (int r = 0; r < KB; ++r) acc[r] = 0.0;
+  for (uint32_t j = 0; j < w; j += G) {
+    uint64_t p[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) p[q] = j + q < w ? __builtin_nontemporal_load(P + (j + q) * stride) : 0ull;
+    uint32_t off[G];
+    double val[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const uint32_t lo = (uint32_t)p[q];
+      const bool flag = lo & 1u;
+      c += flag ? ((lo >> 1) & a.dmask) : (uint32_t)(p[q] >> 1);
+      off[q] = flag ? c * kx + x0 : oob;
+      val[q] = flag ? __builtin_bit_cast(double, p[q] & a.vmask) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+#pragma unroll
+      for (int r = 0; r < KB; ++r)
+        acc[r] = fma(val[q],
+                     __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                    rx, off[q] == oob ? oob : off[q] + 8u * r, 0, 0)),
+                     acc[r]);
+  }
+  if (t >= a.n) return;
+  double *yo = a.y + (int64_t)dst.row() * k + r0;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) yo[r] = acc[r];
+}
+
 SpmvArgs make_args(const pksell_matrix *A, const float *x, float *y, int64_t k) {
   SpmvArgs a;
   a.pack = A->pack;
@@ -813,19 +861,21 @@ int pksell_spmv(const pksell_matrix *A, const float *x, float *y, int64_t k, voi
   }
 }
 
-int pksell_spmv_f64(const pksell_matrix *A, const double *x, double *y, void *stream) {
+int pksell_spmv_f64(const pksell_matrix *A, const double *x, double *y, int64_t k,
+                    void *stream) {
   PKS_CHECK(A, PKSELL_EINVAL, "null matrix");
   PKS_CHECK(A->fmt == PKSELL_E11MY, PKSELL_EINVAL, "pksell_spmv_f64 needs fmt E11MY");
   PKS_CHECK(A->n == 0 || (A->offset && (A->n_words == 0 || A->pack)), PKSELL_EINVAL,
             "matrix arrays not set");
   PKS_CHECK(A->perm_mode != PKSELL_IMPLICIT || A->n == 0 || A->perm, PKSELL_EINVAL,
             "implicit mode needs perm");
-  PKS_CHECK(A->m < (int64_t(1) << 29), PKSELL_ERANGE, "m must be below 2^29 (8-byte x)");
+  PKS_CHECK(k >= 1 && k <= 64, PKSELL_EINVAL, "k must be in [1, 64]");
+  PKS_CHECK(A->m * k < (int64_t(1) << 29), PKSELL_ERANGE, "m * k must be below 2^29 (8-byte x)");
   PKS_CHECK(A->n == 0 || y, PKSELL_EINVAL, "null y");
   hipStream_t st = as_stream(stream);
   if (A->n == 0) return PKSELL_OK;
   if (A->m == 0) {
-    k_fill_zero<double><<<cdiv(A->n, kBlock), kBlock, 0, st>>>(y, A->n);
+    k_fill_zero<double><<<cdiv(A->n * k, kBlock), kBlock, 0, st>>>(y, A->n * k);
     PKS_LAUNCHED();
     return PKSELL_OK;
   }
@@ -845,6 +895,28 @@ int pksell_spmv_f64(const pksell_matrix *A, const double *x, double *y, void *st
   a.dmask = A->D >= 31 ? 0x7FFFFFFFu : (1u << A->D) - 1u;
   a.vmask = ~((2ull << A->D) - 1ull);
   const int64_t grid = cdiv(A->n_slices * A->C, kBlock);
+  if (k > 1) {  // passes of four columns (then two, one)
+    const bool cw = A->C == kWave;
+    for (int64_t r0 = 0; r0 < k;) {
+      const int64_t left = k - r0;
+      const uint32_t kk = (uint32_t)k, r = (uint32_t)r0;
+      if (left >= 4) {
+        if (cw) k_spmv64k<true, 4><<<grid, kBlock, 0, st>>>(a, kk, r);
+        else k_spmv64k<false, 4><<<grid, kBlock, 0, st>>>(a, kk, r);
+        r0 += 4;
+      } else if (left >= 2) {
+        if (cw) k_spmv64k<true, 2><<<grid, kBlock, 0, st>>>(a, kk, r);
+        else k_spmv64k<false, 2><<<grid, kBlock, 0, st>>>(a, kk, r);
+        r0 += 2;
+      } else {
+        if (cw) k_spmv64k<true, 1><<<grid, kBlock, 0, st>>>(a, kk, r);
+        else k_spmv64k<false, 1><<<grid, kBlock, 0, st>>>(a, kk, r);
+        r0 += 1;
+      }
+      PKS_LAUNCHED();
+    }
+    return PKSELL_OK;
+  }
   const bool buf = A->C == kWave && A->n_words < (int64_t(1) << 29);
   if (buf) {
     PKS_GROUP(slice_group(A->n_words, A->n_slices),

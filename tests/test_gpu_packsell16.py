@@ -5,9 +5,10 @@ rounds every lane's word count up to even.  The tests unfold those slots
 back into the paper's column-major 16-bit layout.  The words must then
 equal the 16-bit oracle's bit for bit, and the extra padding word must be
 zero.  Products must equal the oracle's float64 product on the same
-quantised values within 1e-6, normalised by ||A_q||_inf ||x||_inf.  Every
-other entry point except the solvers' inner operator, and k > 1, must
-reject these formats.
+quantised values within 1e-6, normalised by ||A_q||_inf ||x||_inf; with
+k right-hand sides every column must equal the single-vector product of
+that column bit for bit (both sum in word order).  Every other entry point
+except the solvers' inner operator must reject these formats.
 """
 import numpy as np
 import pytest
@@ -143,8 +144,6 @@ def test_other_entry_points_reject_16_bit_words():
     a = random_csr(51, 300, 300, per_row=5)
     A, _ = encode_both(a, "e5my", 7)
     with pytest.raises(B.PackSELLError):
-        B.spmv(A, torch.zeros(a.m, 4, device=DEV))  # k > 1
-    with pytest.raises(B.PackSELLError):
         B.spmv_t(A, torch.zeros(a.n, device=DEV))
     with pytest.raises(B.PackSELLError):
         B.BatchedSpMV([A], [torch.zeros(a.m, device=DEV)], [torch.zeros(a.n, device=DEV)])
@@ -153,3 +152,41 @@ def test_other_entry_points_reject_16_bit_words():
                  split_words=64)
     with pytest.raises(B.PackSELLError):
         B.encode(a.rowptr, a.col, a.val, a.n, a.m, "e5my", 7, 32, 256, B.IMPLICIT, DEV)
+
+
+@pytest.mark.parametrize("fmt,D", [("e5my", 7), ("e5my", 3), ("fix16", 7), ("fix16", 12)])
+@pytest.mark.parametrize("mode", [B.IMPLICIT, B.EXPLICIT])
+def test_multi_rhs(fmt, D, mode):
+    """k right-hand sides (row-major x and y; passes of 8, 4, 2 and 1
+    columns, 16-byte gathers when k is a multiple of 4): every column within
+    the bar of the oracle's product and equal to the single-vector product."""
+    a = random_csr(72, 2500, 2300, per_row=11)
+    A, E = encode_both(a, fmt, D, mode=mode)
+    q = P16.quantized(a.rowptr, a.val, a.n, FMT[fmt], D)
+    rng = np.random.default_rng(9)
+    for k in (2, 3, 4, 7, 8, 12, 32):
+        X = rng.uniform(-1, 1, (a.m, k)).astype(np.float32)
+        Xd = torch.from_numpy(X).to(DEV)
+        Y = B.spmv(A, Xd)
+        Yh = Y.cpu().numpy().astype(np.float64)
+        den = L.inf_norm(a.rowptr, q) * float(np.abs(X).max())
+        for r in range(k):
+            ref = L.spmv(a.rowptr, a.col, q, X[:, r].astype(np.float64))
+            if mode == B.EXPLICIT:
+                ref = ref[E.stored_rows]
+            assert float(np.max(np.abs(Yh[:, r] - ref))) / den <= SPMV_TOL, (k, r)
+            assert torch.equal(Y[:, r], B.spmv(A, Xd[:, r].contiguous())), (k, r)
+
+
+def test_multi_rhs_misaligned_x():
+    """k = 4 with x at a 4-byte offset: the column-at-a-time gathers."""
+    a = random_csr(73, 900, 800, per_row=9)
+    A, _ = encode_both(a, "fix16", 8)
+    k = 4
+    base = torch.from_numpy(np.random.default_rng(4).uniform(-1, 1, a.m * k + 1)
+                            .astype(np.float32)).to(DEV)
+    X = base[1:].view(a.m, k)
+    assert X.data_ptr() % 16 != 0
+    Y = B.spmv(A, X)
+    for r in range(k):
+        assert torch.equal(Y[:, r], B.spmv(A, X[:, r].contiguous()))

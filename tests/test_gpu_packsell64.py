@@ -123,3 +123,27 @@ def test_other_entry_points_reject_64_bit_words():
     with pytest.raises(B.PackSELLError):
         B.pcg(A, hi, torch.ones(a.n, dtype=torch.float64, device=DEV), tol=1e-8, m_in=5,
               max_outer=5)
+
+
+@pytest.mark.parametrize("C,sigma,mode", [(64, 256, B.IMPLICIT), (64, 256, B.EXPLICIT),
+                                          (16, 1, B.IMPLICIT)])
+def test_multi_rhs(C, sigma, mode):
+    """k right-hand sides (row-major x and y, passes of 4, 2 and 1 columns):
+    every column within the float64 bar of the oracle's product and equal to
+    the single-vector product of that column (both sum in word order)."""
+    a = random_csr(44, 1800, 1700, per_row=10)
+    A, E = encode_both(a, 11, C, sigma, mode)
+    q = P64.quantized(a.val, 11)
+    rng = np.random.default_rng(6)
+    for k in (2, 3, 4, 5, 8, 13):
+        X = rng.uniform(-1, 1, (a.m, k))
+        Xd = torch.from_numpy(X).to(DEV)
+        Y = B.spmv_f64(A, Xd)
+        Yh = Y.cpu().numpy()
+        den = L.inf_norm(a.rowptr, q) * float(np.abs(X).max())
+        for r in range(k):
+            ref = L.spmv(a.rowptr, a.col, q, X[:, r])
+            if mode == B.EXPLICIT:
+                ref = ref[E.stored_rows]
+            assert float(np.max(np.abs(Yh[:, r] - ref))) / den <= TOL64, (k, r)
+            assert torch.equal(Y[:, r], B.spmv_f64(A, Xd[:, r].contiguous())), (k, r)
