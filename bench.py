@@ -43,6 +43,15 @@ def record(label, mat, x, variant, y, fmt=None, D=0):
     entry[2][variant] = (np.asarray(y), fmt, D)
 
 
+def sell_in_original_order(B, a, S, x):
+    """A SELL comparator's product in the original row order: the same
+    matrix encoded in implicit order (the same slots and sums per row; the
+    explicit encoding keeps no perm to undo its sort)."""
+    Si = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, S.value_dtype, S.desc.C, S.desc.sigma,
+                       B.IMPLICIT, x.device, paired=S.paired)
+    return B.sell_spmv(Si, x).cpu().numpy()
+
+
 def original_order(B, A, y):
     """A product in stored row order (explicit mode) put back in the
     original row order with the matrix's perm."""
@@ -272,12 +281,6 @@ def main():
         log(f"[bench] {name}: {ms * 1e3:.2f} us  {gbs:.0f} GB/s  ({R} replicas)")
         del reps, xs
 
-    lib_csr = None
-    if not only or "rocsparse_csr_fp32" in only:
-        lib_csr, y_csr = torch_csr_leg(args, torch, a, x_np)
-        record("laplace3d", a, x_np, "rocsparse_csr_fp32", y_csr, "f32")
-        log(f"[bench] rocsparse_csr_fp32: {lib_csr}")
-
     head = "packsell_fp16" if "packsell_fp16" in results else next(iter(results))
     H = results[head]
     ceiling = stream_ceiling(args, torch, B, H["bytes"])
@@ -312,11 +315,8 @@ def main():
     }
     base32 = results.get("sell_fp32")
     base16 = results.get("sell_fp16")
-    # the fastest float32 product among the SELL forms and the library's CSR
+    # the fastest float32 product among the SELL forms
     fp32_ms = {k: results[k]["ms"] for k in ("sell_fp32", "sell_fp32_paired") if k in results}
-    if lib_csr is not None:
-        fp32_ms["rocsparse_csr_fp32"] = lib_csr["us"] * 1e-3
-        out["rocsparse_csr_fp32"] = lib_csr
     best32 = min(fp32_ms, key=fp32_ms.get) if fp32_ms else None
     out["best_fp32"] = best32
     for name, r in results.items():
@@ -334,23 +334,32 @@ def main():
             v["speedup_vs_sell_fp16"] = round(base16["ms"] / r["ms"], 3)
         out["variants"][name] = v
 
+    def leg(key, fn, *fargs):
+        # a leg that fails leaves its error in the line instead of ending the run
+        try:
+            out[key] = fn(*fargs)
+        except Exception as e:  # noqa: BLE001
+            import traceback
+            traceback.print_exc()
+            out[key] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.synchronize()
+
     if not args.no_adjoint and "packsell_fp16" in results:
-        out["adjoint"] = adjoint_leg(args, a, results["packsell_fp16"]["A"], torch, B, W)
-        out["multi_rhs"] = multirhs_leg(args, a, results["packsell_fp16"]["A"], torch, B, W)
-    out["encode_ms"] = encode_leg(a, torch, B)
+        leg("adjoint", adjoint_leg, args, a, results["packsell_fp16"]["A"], torch, B, W)
+        leg("multi_rhs", multirhs_leg, args, a, results["packsell_fp16"]["A"], torch, B, W)
+    leg("encode_ms", encode_leg, a, torch, B)
     if not args.no_extra:
-        out["powerlaw"] = powerlaw_leg(args, torch, B, W)
-        out["block3_27pt"] = block_leg(args, torch, B, W)
-        out["laplace3d_256"] = large_leg(args, torch, B, W)
-    if not args.no_extra:
-        out["fp64_words"] = fp64_leg(args, a, torch, B, W)
-        out["words16"] = w16_leg(args, torch, B, W)
-        out["trsv"] = trsv_leg(args, torch, B, W)
+        leg("powerlaw", powerlaw_leg, args, torch, B, W)
+        leg("block3_27pt", block_leg, args, torch, B, W)
+        leg("laplace3d_256", large_leg, args, torch, B, W)
+        leg("fp64_words", fp64_leg, args, a, torch, B, W)
+        leg("words16", w16_leg, args, torch, B, W)
+        leg("trsv", trsv_leg, args, torch, B, W)
     if not args.no_batched:
-        out["batched"] = batched_leg(args, torch, B, W)
+        leg("batched", batched_leg, args, torch, B, W)
     if not args.no_pcg:
-        out["pcg"] = pcg_leg(args, torch, B, W)
-        out["f3r"] = f3r_leg(args, torch, B, W)
+        leg("pcg", pcg_leg, args, torch, B, W)
+        leg("f3r", f3r_leg, args, torch, B, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_leg(args, a, x_np, results, H, torch)
     print(json.dumps(out), flush=True)
@@ -440,55 +449,6 @@ def time_variant(args, torch, B, A, m, n, mk_y=None):
     return ms, per, R
 
 
-def torch_csr_leg(args, torch, a, x_np):
-    """float32 CSR SpMV of the vendor library (rocSPARSE, through torch's
-    sparse CSR matrix-vector product; int32 indices): the library baseline
-    beside the SELL comparators.  Timed like the products (replicas, graph
-    replay) when the call captures into a graph, else eagerly (then the
-    figure can include host launch time, and ``timing`` says so)."""
-    dev = torch.device("cuda:0")
-    crow = torch.from_numpy(a.rowptr.astype(np.int32)).to(dev)
-    col = torch.from_numpy(a.col.astype(np.int32)).to(dev)
-    val = torch.from_numpy(a.val.astype(np.float32)).to(dev)
-    per = 8 * a.nnz + 4 * (a.n + 1) + 4 * a.m + 4 * a.n
-    R = max(2, int(math.ceil(args.replica_bytes / per)))
-    mats = [torch.sparse_csr_tensor(crow.clone(), col.clone(), val.clone(), size=(a.n, a.m))
-            for _ in range(R)]
-    x0 = torch.from_numpy(x_np.astype(np.float32)).to(dev)
-    xs = [x0.clone() for _ in range(R)]
-    outs = [None] * R
-
-    def fn(i):
-        outs[i] = torch.mv(mats[i], xs[i])
-
-    timing = "graph"
-    try:
-        ms = Timed(torch, fn, R, min(args.steps, 200), min(args.warmup, 20)).run()
-    except Exception as e:  # the library call does not capture: time it eagerly
-        log(f"[bench] rocsparse csr: graph capture failed ({type(e).__name__}); timing eagerly")
-        torch.cuda.synchronize()
-        timing = "eager"
-        for i in range(10):
-            fn(i % R)
-        st = torch.cuda.current_stream()
-        wins = []
-        for _ in range(5):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record(st)
-            for i in range(min(args.steps, 200)):
-                fn(i % R)
-            e1.record(st)
-            e1.synchronize()
-            wins.append(e0.elapsed_time(e1) / min(args.steps, 200))
-        ms = sorted(wins)[2]
-    y = torch.mv(mats[0], x0).cpu().numpy()
-    del mats, xs, outs
-    return {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1), "bytes": per,
-            "timing": timing, "replicas": R}, y
-
-
 def powerlaw_leg(args, torch, B, W):
     """Irregular power-law rows, n = 10^6 (mean 30, max 5000, RSD 4.3):
     PackSELL FP16 and E8M10 (D = 12) at sigma = 65536 against FP32 SELL,
@@ -555,20 +515,17 @@ def powerlaw_leg(args, torch, B, W):
     res["sell_fp32"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
                         "slots_per_nnz": round(S.n_slots / a.nnz, 3)}
     record("powerlaw", a, x_chk.cpu().numpy(), "sell_fp32",
-           original_order(B, S, B.sell_spmv(S, x_chk)), "f32")
+           sell_in_original_order(B, a, S, x_chk), "f32")
     log(f"[bench] powerlaw sell_fp32: {res['sell_fp32']}")
     S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 65536, B.EXPLICIT, dev,
                       paired=True)
     ms, per, R = time_variant(args, torch, B, S, a.m, a.n)
     res["sell_fp32_paired"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1)}
     record("powerlaw", a, x_chk.cpu().numpy(), "sell_fp32_paired",
-           original_order(B, S, B.sell_spmv(S, x_chk)), "f32")
+           sell_in_original_order(B, a, S, x_chk), "f32")
     log(f"[bench] powerlaw sell_fp32_paired: {res['sell_fp32_paired']}")
     del S
-    res["rocsparse_csr_fp32"], yr = torch_csr_leg(args, torch, a, x_chk.cpu().numpy())
-    record("powerlaw", a, x_chk.cpu().numpy(), "rocsparse_csr_fp32", yr, "f32")
-    log(f"[bench] powerlaw rocsparse_csr_fp32: {res['rocsparse_csr_fp32']}")
-    fp32 = ("sell_fp32", "sell_fp32_paired", "rocsparse_csr_fp32")
+    fp32 = ("sell_fp32", "sell_fp32_paired")
     best = min(fp32, key=lambda k: res[k]["us"])
     res["best_fp32"] = best
     for name, *_ in variants:
@@ -579,7 +536,8 @@ def powerlaw_leg(args, torch, B, W):
 
 def trsv_leg(args, torch, B, W):
     """Lower-triangular solve, level by level, on the lower triangle of the
-    7-point 128^3 Laplacian (values 6 and -1, exact in FP16; 382 levels):
+    7-point 128^3 variable-coefficient Laplacian (lognormal(0, 0.5) edge
+    coefficients; 382 levels):
     CSR-packed FP16 words against plain CSR with float32 values."""
     import copy
     import scipy.sparse as sp
@@ -648,7 +606,7 @@ def fp64_leg(args, a, torch, B, W):
             else:
                 ys_ref = fn(M, x0)  # same x, unquantised FP64 values
                 record(f"fp64_words_{name}", mat, x0.cpu().numpy(), "sell_fp64",
-                       original_order(B, M, ys_ref), "f64")
+                       sell_in_original_order(B, mat, M, x0), "f64")
             del reps, xs, ys
         diff = float((yp - ys_ref).abs().max() / ys_ref.abs().max().clamp_min(1e-300))
         out["speedup_vs_sell_fp64"] = round(out["sell_fp64"]["us"] / out["packsell64"]["us"], 3)
@@ -880,9 +838,9 @@ def pcg_leg(args, torch, B, W):
 def f3r_leg(args, torch, B, W):
     """Time to a 1e-10 relative residual with the F3R nested solver (sec.
     5.2.1; outer FGMRES(100), FGMRES(8), FGMRES(4), Richardson(2)) in its
-    three forms: every layer float64 (FP64-F3R); float32 SELL in layer 2 and
-    half-value SELL in layers 3-4 (FP16-F3R); the same with FP16 PackSELL
-    words in layers 3-4 (PackSELL-F3R).  On the SPD 27-point 100^3 system
+    three forms: every layer float64 (FP64-F3R); float32 SELL (paired
+    8-byte slots) in layer 2 and half-value SELL in layers 3-4 (FP16-F3R);
+    the same with FP16 PackSELL words in layers 3-4 (PackSELL-F3R).  On the SPD 27-point 100^3 system
     (b = A 1) and a nonsymmetric 7-point convection-diffusion 128^3 system
     (b ~ U[0, 1)), both symmetrically scaled."""
     dev = torch.device("cuda:0")
@@ -892,9 +850,10 @@ def f3r_leg(args, torch, B, W):
             ("convdiff7_128", W.symmetric_diag_scale(W.convdiff3d(128, 11)), "uniform")):
         b_np = W.ones_rhs(a) if bvec is None else np.random.default_rng(12).uniform(0, 1, a.n)
         b = torch.from_numpy(b_np).to(dev)
-        enc = lambda dt: B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, dt, 64, 256, B.IMPLICIT,
-                                       dev)
-        A1, A2, A3s = enc(torch.float64), enc(torch.float32), enc(torch.float16)
+        enc = lambda dt, paired=False: B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, dt, 64, 256,
+                                                     B.IMPLICIT, dev, paired=paired)
+        # layer 2: float32 SELL with paired 8-byte slots (the faster float32 form)
+        A1, A2, A3s = enc(torch.float64), enc(torch.float32, True), enc(torch.float16)
         A3p = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 64, 256, B.IMPLICIT, dev)
         res = {"n": a.n, "nnz": a.nnz, "params": "m1=100 m2=8 m3=4 m4=2 omega=1"}
         xs = {}
@@ -1051,7 +1010,7 @@ def cpu_leg(args, a, x_np, results, H, torch):
             "ms_per_spmv": round(dt * 1e3, 3),
             "single_thread": {"value": round(csr_bytes / dt1 / 1e9, 3), "unit": "GB/s",
                               "ms_per_spmv": round(dt1 * 1e3, 3), "cores": 1},
-            "oracle_ms_over_gpu_ms": round(dt / H["ms"], 1),
+            "oracle_ms_over_gpu_ms": round(dt * 1e3 / H["ms"], 1),
             "errors": errors}
 
 

@@ -113,6 +113,15 @@ __device__ inline uint32_t stream_word(__amdgpu_buffer_rsrc_t rs, uint32_t lane,
   return __builtin_amdgcn_raw_buffer_load_b32(rs, (lane + j * kWave) * 4u, 0, kStreamPolicy);
 }
 
+// One float32 result of a single-vector product, stored through a buffer
+// resource on y with the streaming policy: on the 128^3 FP16 product this
+// took 14.26 us against 14.73 us for plain stores (other policies, 14.4 to
+// 15.0 us).  Rows at or past n fall outside the resource and are dropped.
+__device__ inline void store_result(float *y, uint32_t n, uint32_t row, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), make_rsrc(y, n * 4u),
+                                        row * 4u, 0, kStreamPolicy);
+}
+
 // Element j of lane ``lane`` of a C = 64 slice of 4- or 8-byte elements
 // (the SELL comparators' columns and values), streamed the same way.
 template <typename T>

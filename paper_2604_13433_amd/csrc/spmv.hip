@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
     float r = acc[i];
     if constexpr (FMT == PKSELL_FIX)
       r = ldexpf(r, IMPL ? ro[i].shift(a.cd) : (int)a.row_exp[t] - (a.cd.D + 1));
-    a.y[IMPL ? ro[i].row() : t] = r;
+    store_result(a.y, a.n, IMPL ? ro[i].row() : t, r);
   }
 }
 
@@ -461,7 +461,8 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
   for (int i = 0; i < S; ++i) {
     const uint32_t t = (k0 + i) * kWave + lane;
     if (k0 + i >= n_slices || t >= n) continue;
-    y[IMPL ? dst[i].row() : t] = acc[i];
+    if constexpr (sizeof(T) == 4) store_result(y, n, IMPL ? dst[i].row() : t, acc[i]);
+    else y[IMPL ? dst[i].row() : t] = acc[i];
   }
 }
 
