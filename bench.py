@@ -449,6 +449,19 @@ def time_variant(args, torch, B, A, m, n, mk_y=None):
     return ms, per, R
 
 
+def time_csr32(args, torch, B, A):
+    """ms per product of a float32 CSR comparator with replica rotation."""
+    dev = torch.device("cuda:0")
+    per = A.bytes_per_spmv()
+    R = max(2, int(math.ceil(args.replica_bytes / per)))
+    reps = [A] + [A.replicate() for _ in range(R - 1)]
+    xs = [(torch.rand(A.m, device=dev) * 2 - 1) for _ in range(R)]
+    ys = [torch.empty(A.n, device=dev) for _ in range(R)]
+    ms = Timed(torch, lambda i: B.csr32_spmv(reps[i], xs[i], ys[i]), R, min(args.steps, 200),
+               min(args.warmup, 20)).run()
+    return ms, per, R
+
+
 def powerlaw_leg(args, torch, B, W):
     """Irregular power-law rows, n = 10^6 (mean 30, max 5000, RSD 4.3):
     PackSELL FP16 and E8M10 (D = 12) at sigma = 65536 against FP32 SELL,
@@ -469,6 +482,10 @@ def powerlaw_leg(args, torch, B, W):
     # point with a per-row scale (FIX, D = 15) on the best layout
     variants += [(f"packed_csr_e8m{22 - D}_chunk512", "e8my", D, 512) for D in (1, 2, 9)]
     variants += [("packed_csr_fix16_chunk512", "fix", 15, 512)]
+    # --only (with --leg powerlaw) restricts the leg to the named variants
+    only = set(filter(None, args.only.split(","))) if args.leg == "powerlaw" else set()
+    want = lambda name: not only or name in only
+    variants = [v for v in variants if want(v[0])]
     x_chk = torch.from_numpy(W.uniform_vector(a.m, 41)).to(dev)
     for name, fmt, D, J in variants:
         csr = name.startswith("packed_csr")
@@ -492,45 +509,64 @@ def powerlaw_leg(args, torch, B, W):
         log(f"[bench] powerlaw {name}: {res[name]}")
         del A
     # four right-hand sides through the chunk product: one 16-byte gather per word
-    A = B.encode_packed_csr(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 512, dev)
-    per = A.bytes_per_spmv(4)
-    R = max(2, int(math.ceil(args.replica_bytes / per)))
-    reps = [A] + [A.replicate() for _ in range(R - 1)]
-    xs = [torch.rand((a.m, 4), device=dev) * 2 - 1 for _ in range(R)]
-    ys = [torch.empty((a.n, 4), device=dev) for _ in range(R)]
-    ms = Timed(torch, lambda i: B.spmv(reps[i], xs[i], ys[i]), R, min(args.steps, 200),
-               min(args.warmup, 20)).run()
-    res["packed_csr_fp16_chunk512_k4"] = {"us": round(ms * 1e3, 2),
-                                          "us_per_rhs": round(ms * 1e3 / 4, 2),
-                                          "GB/s": round(per / (ms * 1e-3) / 1e9, 1)}
-    x4 = torch.from_numpy(W.uniform_vector(a.m, 42, k=4)).to(dev)
-    y4 = B.spmv(A, x4).cpu().numpy()
-    for c in (0, 3):
-        record(f"powerlaw_k4_col{c}", a, x4[:, c].cpu().numpy(), "packed_csr_fp16_chunk512_k4",
-               y4[:, c], "fp16", 15)
-    log(f"[bench] powerlaw packed_csr_fp16_chunk512_k4: {res['packed_csr_fp16_chunk512_k4']}")
-    del reps, xs, ys, A
-    S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 65536, B.EXPLICIT, dev)
-    ms, per, R = time_variant(args, torch, B, S, a.m, a.n)
-    res["sell_fp32"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
-                        "slots_per_nnz": round(S.n_slots / a.nnz, 3)}
-    record("powerlaw", a, x_chk.cpu().numpy(), "sell_fp32",
-           sell_in_original_order(B, a, S, x_chk), "f32")
-    log(f"[bench] powerlaw sell_fp32: {res['sell_fp32']}")
-    S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 65536, B.EXPLICIT, dev,
-                      paired=True)
-    ms, per, R = time_variant(args, torch, B, S, a.m, a.n)
-    res["sell_fp32_paired"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1)}
-    record("powerlaw", a, x_chk.cpu().numpy(), "sell_fp32_paired",
-           sell_in_original_order(B, a, S, x_chk), "f32")
-    log(f"[bench] powerlaw sell_fp32_paired: {res['sell_fp32_paired']}")
-    del S
-    fp32 = ("sell_fp32", "sell_fp32_paired")
-    best = min(fp32, key=lambda k: res[k]["us"])
-    res["best_fp32"] = best
-    for name, *_ in variants:
-        res[name]["speedup_vs_sell_fp32"] = round(res["sell_fp32"]["us"] / res[name]["us"], 3)
-        res[name]["speedup_vs_best_fp32"] = round(res[best]["us"] / res[name]["us"], 3)
+    if want("packed_csr_fp16_chunk512_k4"):
+        A = B.encode_packed_csr(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 512, dev)
+        per = A.bytes_per_spmv(4)
+        R = max(2, int(math.ceil(args.replica_bytes / per)))
+        reps = [A] + [A.replicate() for _ in range(R - 1)]
+        xs = [torch.rand((a.m, 4), device=dev) * 2 - 1 for _ in range(R)]
+        ys = [torch.empty((a.n, 4), device=dev) for _ in range(R)]
+        ms = Timed(torch, lambda i: B.spmv(reps[i], xs[i], ys[i]), R, min(args.steps, 200),
+                   min(args.warmup, 20)).run()
+        res["packed_csr_fp16_chunk512_k4"] = {"us": round(ms * 1e3, 2),
+                                              "us_per_rhs": round(ms * 1e3 / 4, 2),
+                                              "GB/s": round(per / (ms * 1e-3) / 1e9, 1)}
+        x4 = torch.from_numpy(W.uniform_vector(a.m, 42, k=4)).to(dev)
+        y4 = B.spmv(A, x4).cpu().numpy()
+        for c in (0, 3):
+            record(f"powerlaw_k4_col{c}", a, x4[:, c].cpu().numpy(), "packed_csr_fp16_chunk512_k4",
+                   y4[:, c], "fp16", 15)
+        log(f"[bench] powerlaw packed_csr_fp16_chunk512_k4: {res['packed_csr_fp16_chunk512_k4']}")
+        del reps, xs, ys, A
+    if want("sell_fp32"):
+        S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 65536, B.EXPLICIT, dev)
+        ms, per, R = time_variant(args, torch, B, S, a.m, a.n)
+        res["sell_fp32"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
+                            "slots_per_nnz": round(S.n_slots / a.nnz, 3)}
+        record("powerlaw", a, x_chk.cpu().numpy(), "sell_fp32",
+               sell_in_original_order(B, a, S, x_chk), "f32")
+        log(f"[bench] powerlaw sell_fp32: {res['sell_fp32']}")
+    if want("sell_fp32_paired"):
+        S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 65536, B.EXPLICIT, dev,
+                          paired=True)
+        ms, per, R = time_variant(args, torch, B, S, a.m, a.n)
+        res["sell_fp32_paired"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1)}
+        record("powerlaw", a, x_chk.cpu().numpy(), "sell_fp32_paired",
+               sell_in_original_order(B, a, S, x_chk), "f32")
+        log(f"[bench] powerlaw sell_fp32_paired: {res['sell_fp32_paired']}")
+        del S
+    # float32 CSR balanced over entry chunks (the CSR-packed product's own
+    # scheme with plain 8-byte entries): the like-for-like float32 form here
+    for T in (256, 512, 1024):
+        if not want(f"csr32_chunk{T}"):
+            continue
+        Cm = B.csr32_encode(a.rowptr, a.col, a.val, a.n, a.m, T, dev)
+        ms, per, R = time_csr32(args, torch, B, Cm)
+        res[f"csr32_chunk{T}"] = {"us": round(ms * 1e3, 2), "GB/s": round(per / (ms * 1e-3) / 1e9, 1),
+                                  "chunks": Cm.n_chunks}
+        record("powerlaw", a, x_chk.cpu().numpy(), f"csr32_chunk{T}",
+               B.csr32_spmv(Cm, x_chk).cpu().numpy(), "f32")
+        log(f"[bench] powerlaw csr32_chunk{T}: {res[f'csr32_chunk{T}']}")
+        del Cm
+    fp32 = [k for k in ("sell_fp32", "sell_fp32_paired", "csr32_chunk256", "csr32_chunk512",
+                        "csr32_chunk1024") if k in res]
+    if fp32:
+        best = min(fp32, key=lambda k: res[k]["us"])
+        res["best_fp32"] = best
+        for name, *_ in variants:
+            if "sell_fp32" in res:
+                res[name]["speedup_vs_sell_fp32"] = round(res["sell_fp32"]["us"] / res[name]["us"], 3)
+            res[name]["speedup_vs_best_fp32"] = round(res[best]["us"] / res[name]["us"], 3)
     return res
 
 

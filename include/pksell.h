@@ -175,6 +175,24 @@ typedef struct pksell_sell {
   void *val;
 } pksell_sell;
 
+/* Plain CSR with float32 values, the comparator of the CSR-packed product:
+ * entries in row order, each 8 bytes (column in the low 32 bits, float32
+ * value bits in the high 32), and a chunk plan over entries.
+ *   rowptr int64[n + 1] (the caller's; rowptr[0] = 0, non-decreasing,
+ *          rowptr[n] = nnz), ent uint64[nnz], lo uint32[n_chunks + 1]
+ *          (the first row starting at or after entry c T, then n),
+ *   partial float32[3 n_chunks] (scratch of the product) */
+typedef struct pksell_csr32 {
+  int64_t n, m, nnz;
+  int32_t T;        /* entries per chunk: 256, 512 or 1024 */
+  int32_t reserved;
+  int64_t n_chunks; /* ceil(nnz / T) */
+  const int64_t *rowptr;
+  uint64_t *ent;
+  uint32_t *lo;
+  float *partial;
+} pksell_csr32;
+
 /* Result of pksell_pcg (host struct). */
 typedef struct pksell_pcg_info {
   int32_t outer_iterations; /* outer (FCG) iterations, or CG iterations */
@@ -393,6 +411,33 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y,
                      void *stream);
 
 /* ------------------------------------------------------------------------
+ * Float32 CSR balanced over entries: the comparator for the CSR-packed
+ * product (not in the paper).  The entry stream is cut into chunks of T
+ * entries, one 64-lane wave each, with the chunk kernel of the CSR-packed
+ * words: lane-sequential entries, segmented wave scans for the row sums,
+ * rows across chunks added in chunk order.
+ * ---------------------------------------------------------------------- */
+
+/* Fills A's sizes (n, m, nnz, T, n_chunks) from the arguments; no device
+ * work.  EINVAL unless T is 256, 512 or 1024, n, m < 2^30 and
+ * nnz < 2^31. */
+int pksell_csr32_query(int64_t n, int64_t m, int64_t nnz, int32_t T, pksell_csr32 *A);
+
+/* Builds ent (float32 values; float64 input rounded to nearest) and lo
+ * from a device CSR (rowptr as above; col int32[nnz] in [0, m); val
+ * float32 or float64 [nnz] per val_dtype).  Asynchronous on ``stream``.
+ * Needs A->rowptr, A->ent and A->lo set; A->rowptr must stay valid for
+ * the products. */
+int pksell_csr32_encode(const int32_t *col, const void *val, int32_t val_dtype,
+                        pksell_csr32 *A, void *stream);
+
+/* y = A x, float32, each row's products summed in entry order within a
+ * lane and then across lanes and chunks in a fixed order (deterministic).
+ * x float32[m], y float32[n]; A->partial must hold 3 n_chunks floats.
+ * Columns out of range read 0. */
+int pksell_csr32_spmv(const pksell_csr32 *A, const float *x, float *y, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched products: many PackSELL matrices (uneven sizes, one value format,
  * C = 64, each with its own D) and k right-hand sides in one persistent
  * launch.  Not in the paper; the per-matrix arithmetic is pksell_spmv's.
@@ -456,9 +501,7 @@ int pksell_pcg_workspace(const pksell_matrix *A_lo, const pksell_sell *A_hi,
  *    encoding of the same matrix (implicit row order; FP16, E8MY or FIX
  *    words, or 16-bit E5MY or FIX16 words with C = 64), started from zero on
  *    the right-hand side r / ||r||.  Inner dot products, alpha and beta are
- *    accumulated in float64.  max_outer bounds outer iterations.  The
- *    inner vectors keep r and p as interleaved float32 pairs, so this form
- *    takes n < 2^29 (their byte offsets fit 32 bits); larger n: EINVAL.
+ *    accumulated in float64.  max_outer bounds outer iterations.
  *  - A_lo == NULL: plain float64 CG on A_hi (the baseline); max_outer bounds
  *    iterations, m_in is ignored.
  *

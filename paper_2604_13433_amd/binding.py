@@ -64,6 +64,11 @@ class CBatch(ctypes.Structure):
                 ("items", vp), ("unit_start", vp)]
 
 
+class CCsr32(ctypes.Structure):
+    _fields_ = [("n", i64), ("m", i64), ("nnz", i64), ("T", i32), ("reserved", i32),
+                ("n_chunks", i64), ("rowptr", vp), ("ent", vp), ("lo", vp), ("partial", vp)]
+
+
 class CF3RParams(ctypes.Structure):
     _fields_ = [("m1", i32), ("m2", i32), ("m3", i32), ("m4", i32), ("omega", ctypes.c_double),
                 ("max_cycles", i32), ("reserved", i32)]
@@ -116,6 +121,9 @@ _PROTOS.update({
     "pksell_f3r": ([ctypes.POINTER(CSell), ctypes.POINTER(CSell), ctypes.POINTER(CSell),
                     ctypes.POINTER(CMatrix), vp, vp, ctypes.c_double, ctypes.POINTER(CF3RParams),
                     ctypes.POINTER(CPcgInfo), vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "pksell_csr32_query": ([i64, i64, i64, i32, ctypes.POINTER(CCsr32)], ctypes.c_int),
+    "pksell_csr32_encode": ([vp, vp, i32, ctypes.POINTER(CCsr32), vp], ctypes.c_int),
+    "pksell_csr32_spmv": ([ctypes.POINTER(CCsr32), vp, vp, vp], ctypes.c_int),
     "pksell_pcg64_workspace": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CMatrix),
                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pksell_pcg64": ([ctypes.POINTER(CMatrix), ctypes.POINTER(CMatrix), vp, vp, ctypes.c_double,
@@ -664,6 +672,72 @@ def sell_spmv(S: SellMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> 
     _block(x, S.dtype, S.m, 1, "x")
     _block(y, S.dtype, S.n, 1, "y")
     _check(lib().pksell_sell_spmv(ctypes.byref(S.desc), _ptr(x), _ptr(y), _stream(x.device)))
+    return y
+
+
+class Csr32Matrix:
+    """Plain CSR with float32 values in 8-byte entries and a chunk plan (the
+    comparator of the CSR-packed product)."""
+
+    def __init__(self, desc: CCsr32, tensors: dict, device):
+        self.desc = desc
+        self.t = tensors
+        self.device = device
+
+    n = property(lambda s: s.desc.n)
+    m = property(lambda s: s.desc.m)
+    nnz = property(lambda s: s.desc.nnz)
+    n_chunks = property(lambda s: s.desc.n_chunks)
+
+    def bytes_per_spmv(self) -> int:
+        d = self.desc
+        return int(8 * d.nnz + 8 * (d.n + 1) + 4 * (d.n_chunks + 1) + 4 * d.m + 4 * d.n)
+
+    def replicate(self):
+        c = Csr32Matrix(CCsr32.from_buffer_copy(self.desc),
+                        {k: v.clone() for k, v in self.t.items()}, self.device)
+        c._bind()
+        return c
+
+    def _bind(self):
+        d = self.desc
+        d.rowptr = self.t["rowptr"].data_ptr()
+        d.ent = self.t["ent"].data_ptr()
+        d.lo = self.t["lo"].data_ptr()
+        d.partial = self.t["partial"].data_ptr()
+
+
+def csr32_encode(rowptr, col, val, n: int, m: int, T: int = 512, device="cuda") -> Csr32Matrix:
+    """CSR (numpy or torch) -> float32 CSR entries with a chunk plan of T
+    entries per chunk (256, 512 or 1024)."""
+    device = torch.device(device)
+    rp = _dev(rowptr, torch.int64, device)
+    cl = _dev(col, torch.int32, device)
+    f64 = (isinstance(val, np.ndarray) and val.dtype == np.float64) or \
+        (isinstance(val, torch.Tensor) and val.dtype == torch.float64)
+    vl = _dev(val, torch.float64 if f64 else torch.float32, device)
+    nnz = int(cl.numel())
+    _require(rp.numel() == n + 1, "rowptr must have n + 1 entries")
+    desc = CCsr32()
+    _check(lib().pksell_csr32_query(n, m, nnz, T, ctypes.byref(desc)))
+    t = {"rowptr": rp,
+         "ent": torch.empty(max(1, nnz), dtype=torch.int64, device=device),
+         "lo": torch.empty(desc.n_chunks + 1, dtype=torch.int32, device=device),
+         "partial": torch.empty(max(1, 3 * desc.n_chunks), dtype=torch.float32, device=device)}
+    A = Csr32Matrix(desc, t, device)
+    A._bind()
+    _check(lib().pksell_csr32_encode(_ptr(cl), _ptr(vl), F64 if f64 else F32, ctypes.byref(desc),
+                                     _stream(device)))
+    return A
+
+
+def csr32_spmv(A: Csr32Matrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    """y = A x in float32 (x: m float32 on the device)."""
+    _block(x, torch.float32, A.m, 1, "x")
+    if y is None:
+        y = torch.empty(A.n, dtype=torch.float32, device=x.device)
+    _block(y, torch.float32, A.n, 1, "y")
+    _check(lib().pksell_csr32_spmv(ctypes.byref(A.desc), _ptr(x), _ptr(y), _stream(x.device)))
     return y
 
 

@@ -267,11 +267,11 @@ __global__ __launch_bounds__(kB) void k_batched_pipe(const Item *__restrict__ it
         for (int r = 0; r < NA; ++r) acc[r] = ldexpf(acc[r], sh);
       }
       const uint32_t row = out_row(I.perm, I.perm_bytes, t, I.geo);
-      if constexpr (L == 1) {
-        I.out[row] = acc[0];
+      if constexpr (L == 1) {  // streaming (nontemporal) stores
+        __builtin_nontemporal_store(acc[0], I.out + row);
       } else {
-        *reinterpret_cast<f32x4 *>(I.out + (int64_t)row * k + 4 * cur.q) =
-            f32x4{acc[0], acc[1], acc[2], acc[3]};
+        __builtin_nontemporal_store(f32x4{acc[0], acc[1], acc[2], acc[3]},
+                                    reinterpret_cast<f32x4 *>(I.out + (int64_t)row * k + 4 * cur.q));
       }
     }
     if (!more) break;

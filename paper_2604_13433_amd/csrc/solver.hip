@@ -7,10 +7,11 @@
 //
 // One CG iteration is two kernels: (A) the product q = A p, where p is
 // formed on the fly as r + beta * p_old at every gathered column and
-// written once by its row's lane, writing the workgroup partial sums of
-// p.q; (B) the vector updates, writing the partial sums of r.r.  r and
-// p_old sit side by side as one pair per row (two pair buffers alternate:
-// (B) writes the next one), so a gathered column is one load, not two.  There is no communication between workgroups inside
+// written once by its row's lane (two p buffers alternate), writing the
+// workgroup partial sums of p.q; (B) the vector updates, writing the
+// partial sums of r.r.  In float64 CG, r and p_old sit side by side as one
+// pair per row (two pair buffers alternate: (B) writes the next one), so a
+// gathered column is one 16-byte load, not two.  There is no communication between workgroups inside
 // a kernel: every workgroup of the next kernel sums the previous kernel's
 // partials itself, in one fixed order, so all of them reach the same alpha,
 // beta and stopping decision (deterministically), and workgroup 0 records
@@ -233,11 +234,10 @@ __device__ inline double sell_row(const SellView &S, const Lane &ln, uint32_t st
 
 // (A) float32 inner step on PackSELL.  Totals of the previous r.r give
 // beta (0 on the first inner step); then p_new = r + beta p_old, q = A_q
-// p_new, and the partials of p_new . q.  r and p_old are read as one
-// interleaved pair (r_i, p_i) per row, so each gathered column costs one
-// 8-byte load.
+// p_new, and the partials of p_new . q.
 template <int FMT, bool CWAVE>
-__global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float2 *__restrict__ rp_cur,
+__global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restrict__ r,
+                                               const float *__restrict__ p_old,
                                                float *__restrict__ p_new, float *__restrict__ q,
                                                State *st, Parts rr_in, Parts pq_out) {
   const bool stop = outer_stopped(st) || st->inner_stop;
@@ -260,22 +260,21 @@ __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float2 *__rest
       row_out<FMT>(A.perm, A.perm_bytes, A.row_exp, live ? ln.t : A.n, A.n, A.geo);
   double part = 0.0;
   if (live) {
-    const __amdgpu_buffer_rsrc_t rrp = make_rsrc(rp_cur, A.n * 8u);
+    const __amdgpu_buffer_rsrc_t rr_r = make_rsrc(r, A.n * 4u);
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(p_old, A.n * 4u);
     float acc[1] = {0.0f};
     const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)A.C;
     packsell_row<FMT, 1>(A.pack + ln.s + ln.l, stride, ln.w, left_offset32(ln.t, A.geo), A.cd,
                          [&](uint32_t c, int, bool live) {
-                           const uint32_t o = live ? c << 3 : A.n * 8u;  // flag 0: no request
-                           const float2 g = buffer_load_f32x2(rrp, o);
-                           return fmaf(beta, g.y, g.x);
+                           const uint32_t o = live ? c << 2 : A.n * 4u;  // flag 0: no request
+                           return fmaf(beta, buffer_load_f32(rp, o), buffer_load_f32(rr_r, o));
                          },
                          acc);
     if (ln.t < A.n) {
       float qi = acc[0];
       if constexpr (FMT == PKSELL_FIX) qi = ldexpf(qi, ro.shift(A.cd));
       const uint32_t i = ro.row();
-      const float2 own = rp_cur[i];
-      const float pn = fmaf(beta, own.y, own.x);
+      const float pn = fmaf(beta, p_old[i], r[i]);
       p_new[i] = pn;
       q[i] = qi;
       part = (double)pn * (double)qi;
@@ -295,8 +294,8 @@ constexpr int kPairB = 128;
 // G words per group and slice, sized on the host to the matrix's slice
 // width (each word of a group issues a load and a gather, padding or not).
 template <int FMT, bool BUF, int G = kUnroll>
-__global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A,
-                                                    const float2 *__restrict__ rp_cur,
+__global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__restrict__ r,
+                                                    const float *__restrict__ p_old,
                                                     float *__restrict__ p_new,
                                                     float *__restrict__ q, State *st,
                                                     Parts rr_in, Parts pq_out) {
@@ -344,8 +343,9 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A,
   }
   if (stop || quit) return;
   const float beta = (float)beta_d;
-  const __amdgpu_buffer_rsrc_t rrp = make_rsrc(rp_cur, A.n * 8u);
-  const uint32_t oob = A.n * 8u;  // flag-0 words: past the resource, no request
+  const __amdgpu_buffer_rsrc_t rr_r = make_rsrc(r, A.n * 4u);
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(p_old, A.n * 4u);
+  const uint32_t oob = A.n * 4u;  // flag-0 words: past the resources, no request
   uint32_t c[S];
   float acc[S];
   uint32_t wm = 0;
@@ -374,17 +374,15 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A,
       for (int u = 0; u < G; ++u) {
         const Unpacked d = unpack(p[i][u], A.cd);
         c[i] += d.delta;
-        o[i][u] = (p[i][u] & 1u) ? c[i] << 3 : oob;
+        o[i][u] = (p[i][u] & 1u) ? c[i] << 2 : oob;
         v[i][u] = decode_value<FMT>(d.vbits);
       }
     float xv[S][G];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int u = 0; u < G; ++u) {
-        const float2 g = buffer_load_f32x2(rrp, o[i][u]);
-        xv[i][u] = fmaf(beta, g.y, g.x);
-      }
+      for (int u = 0; u < G; ++u)
+        xv[i][u] = fmaf(beta, buffer_load_f32(rp, o[i][u]), buffer_load_f32(rr_r, o[i][u]));
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
@@ -398,8 +396,7 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A,
     float qi = acc[i];
     if constexpr (FMT == PKSELL_FIX) qi = ldexpf(qi, ro[i].shift(A.cd));
     const uint32_t row = ro[i].row();
-    const float2 own = rp_cur[row];
-    const float pn = fmaf(beta, own.y, own.x);
+    const float pn = fmaf(beta, p_old[row], r[row]);
     p_new[row] = pn;
     q[row] = qi;
     part += (double)pn * (double)qi;
@@ -414,8 +411,8 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A,
 // the previous partials are summed.  Same grid and partial layout as
 // k_inner_a2 (two slices per wave, 128-thread workgroups).
 template <int FMT, int G>
-__global__ __launch_bounds__(kPairB) void k_inner16(PackView A,
-                                                   const float2 *__restrict__ rp_cur,
+__global__ __launch_bounds__(kPairB) void k_inner16(PackView A, const float *__restrict__ r,
+                                                   const float *__restrict__ p_old,
                                                    float *__restrict__ p_new,
                                                    float *__restrict__ q, State *st,
                                                    Parts rr_in, Parts pq_out) {
@@ -455,8 +452,9 @@ __global__ __launch_bounds__(kPairB) void k_inner16(PackView A,
   }
   if (stop || quit) return;
   const float beta = (float)beta_d;
-  const __amdgpu_buffer_rsrc_t rrp = make_rsrc(rp_cur, A.n * 8u);
-  const uint32_t oob = A.n * 8u;  // flag-0 words: past the resource, no request
+  const __amdgpu_buffer_rsrc_t rr_r = make_rsrc(r, A.n * 4u);
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(p_old, A.n * 4u);
+  const uint32_t oob = A.n * 4u;  // flag-0 words: past the resources, no request
   const uint32_t dmask = A.cd.dmask, vmask = A.cd.vmask & 0xFFFFu;
   uint32_t c[S];
   float acc[S];
@@ -483,7 +481,7 @@ __global__ __launch_bounds__(kPairB) void k_inner16(PackView A,
         const uint32_t wd = (h & 1) ? p[i][h >> 1] >> 16 : p[i][h >> 1] & 0xFFFFu;
         const bool flag = wd & 1u;
         c[i] += flag ? (wd >> 1) & dmask : (wd >> 1);
-        o[i][h] = flag ? c[i] << 3 : oob;
+        o[i][h] = flag ? c[i] << 2 : oob;
         const uint32_t bits = flag ? wd & vmask : 0u;
         if constexpr (FMT == PKSELL_E5MY)
           v[i][h] = __half2float(__ushort_as_half((unsigned short)bits));
@@ -494,10 +492,8 @@ __global__ __launch_bounds__(kPairB) void k_inner16(PackView A,
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int h = 0; h < 2 * G; ++h) {
-        const float2 g = buffer_load_f32x2(rrp, o[i][h]);
-        xv[i][h] = fmaf(beta, g.y, g.x);
-      }
+      for (int h = 0; h < 2 * G; ++h)
+        xv[i][h] = fmaf(beta, buffer_load_f32(rp, o[i][h]), buffer_load_f32(rr_r, o[i][h]));
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
@@ -511,8 +507,7 @@ __global__ __launch_bounds__(kPairB) void k_inner16(PackView A,
     float qi = acc[i];
     if constexpr (FMT == PKSELL_FIX16) qi = ldexpf(qi, ro[i].shift(A.cd));
     const uint32_t row = ro[i].row();
-    const float2 own = rp_cur[row];
-    const float pn = fmaf(beta, own.y, own.x);
+    const float pn = fmaf(beta, p_old[row], r[row]);
     p_new[row] = pn;
     q[row] = qi;
     part += (double)pn * (double)qi;
@@ -522,13 +517,10 @@ __global__ __launch_bounds__(kPairB) void k_inner16(PackView A,
 }
 
 // (B) float32 inner update: alpha = rr / pq; z += alpha p, r -= alpha q;
-// the next (r, p) pairs; partials of the new r.r.  The first elements'
-// loads are issued before the product's partials are summed, so their
-// latency overlaps that sum.
+// partials of the new r.r.  The first elements' loads are issued before
+// the product's partials are summed, so their latency overlaps that sum.
 __global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ z,
-                                               const float2 *__restrict__ rp_cur,
-                                               float2 *__restrict__ rp_next,
-                                               const float *__restrict__ p,
+                                               float *__restrict__ r, const float *__restrict__ p,
                                                const float *__restrict__ q, State *st,
                                                Parts pq_in, Parts rr_out) {
   if (!st->in_step_ok) return;
@@ -542,11 +534,11 @@ __global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ 
       zz[u] = in ? z[i] : 0.0f;
       pp[u] = in ? p[i] : 0.0f;
       qq[u] = in ? q[i] : 0.0f;
-      rv[u] = in ? rp_cur[i].x : 0.0f;
+      rv[u] = in ? r[i] : 0.0f;
     }
   };
-  uint32_t i0 = blockIdx.x * kB + threadIdx.x;
-  if (i0 < n) load(i0);
+  const uint32_t first_i = blockIdx.x * kB + threadIdx.x;
+  if (first_i < n) load(first_i);
   double pq[1];
   get_totals(pq_in, pq);
   if (!(pq[0] > 0.0 && isfinite(pq[0]))) {
@@ -557,15 +549,15 @@ __global__ __launch_bounds__(kB) void k_inner_b(uint32_t n, float *__restrict__ 
   const double alpha_d = rr / pq[0];
   const float alpha = (float)alpha_d;
   double part = 0.0;
-  for (; i0 < n; i0 += kVecUnroll * S) {
-    if (i0 != blockIdx.x * kB + threadIdx.x) load(i0);
+  for (uint32_t i0 = first_i; i0 < n; i0 += kVecUnroll * S) {
+    if (i0 != first_i) load(i0);
 #pragma unroll
     for (int u = 0; u < kVecUnroll; ++u) {
       const uint32_t i = i0 + u * S;
       if (i < n) {
         z[i] = fmaf(alpha, pp[u], zz[u]);
         const float ri = fmaf(-alpha, qq[u], rv[u]);
-        rp_next[i] = make_float2(ri, pp[u]);
+        r[i] = ri;
         part += (double)ri * (double)ri;
       }
     }
@@ -709,11 +701,12 @@ __global__ __launch_bounds__(kB) void k_pair_init(uint32_t n, const double *__re
 
 // ---- flexible-CG outer kernels (sec. 5.2.2) -----------------------------------
 
-// Inner start: nr = ||r|| (from st->rr), the pairs (r_in, p) = (r / nr, 0)
-// in float32, z = 0, partials of r_in . r_in.
+// Inner start: nr = ||r|| (from st->rr), r_in = r / nr (float32), z = 0,
+// p_old = 0, partials of r_in . r_in.
 __global__ __launch_bounds__(kB) void k_inner_init(uint32_t n, const double *__restrict__ r,
-                                                  float2 *__restrict__ rp0, float *__restrict__ zin,
-                                                  State *st, Parts rr_out) {
+                                                  float *__restrict__ rin, float *__restrict__ zin,
+                                                  float *__restrict__ p0, State *st,
+                                                  Parts rr_out) {
   if (outer_stopped(st)) return;
   const double nr = sqrt(st->rr);
   const bool stop = !(nr > 0.0 && isfinite(nr));
@@ -729,8 +722,9 @@ __global__ __launch_bounds__(kB) void k_inner_init(uint32_t n, const double *__r
       const uint32_t i = i0 + u * S;
       if (i < n) {
         const float v = (float)(rv[u] * inv);
-        rp0[i] = make_float2(v, 0.0f);
+        rin[i] = v;
         zin[i] = 0.0f;
+        p0[i] = 0.0f;
         part += (double)v * (double)v;
       }
     }
@@ -922,8 +916,7 @@ struct Work {
   Parts pa, pb0, pb1;  // product-grid partials; two alternating vector-grid sets
   double *r, *q, *p0, *p1;
   double2 *dp0, *dp1;  // plain CG: (r, p) pairs, alternating
-  float2 *rp0, *rp1;  // inner (r, p) pairs, alternating
-  float *zin, *pin, *qin;
+  float *rin, *zin, *f0, *f1, *qin;
   size_t bytes;
 };
 
@@ -941,10 +934,10 @@ Work carve_work(void *ws, int64_t n, int64_t max_blocks, bool plain) {
   w.p1 = cv.take<double>(nn);
   w.dp0 = plain ? cv.take<double2>(nn) : nullptr;
   w.dp1 = plain ? cv.take<double2>(nn) : nullptr;
-  w.rp0 = cv.take<float2>(nn);
-  w.rp1 = cv.take<float2>(nn);
+  w.rin = cv.take<float>(nn);
   w.zin = cv.take<float>(nn);
-  w.pin = cv.take<float>(nn);
+  w.f0 = cv.take<float>(nn);
+  w.f1 = cv.take<float>(nn);
   w.qin = cv.take<float>(nn);
   w.bytes = cv.used;
   return w;
@@ -1075,13 +1068,13 @@ struct Solve {
   }
 
   template <int FMT, bool CW>
-  void inner_a(const PackView &A, const float2 *rp, Parts rr_in, Parts pq_out) {
+  void inner_a(const PackView &A, const float *po, float *pn, Parts rr_in, Parts pq_out) {
     // gp workgroups either way: 4 slices each (256 threads x 1 slice per
     // wave, or 128 threads x 2 slices per wave), so the partial count agrees
     if constexpr (CW) {
       if (stream_ok) {
 #define PKS_IA2(GG)                                                                       \
-  k_inner_a2<FMT, true, GG><<<gp, kPairB, 0, s>>>(A, rp, w.pin, w.qin, w.st, rr_in, pq_out)
+  k_inner_a2<FMT, true, GG><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out)
         switch (g_in) {
           case 4: PKS_IA2(4); break;
           case 5: PKS_IA2(5); break;
@@ -1091,17 +1084,17 @@ struct Solve {
         }
 #undef PKS_IA2
       } else {
-        k_inner_a2<FMT, false><<<gp, kPairB, 0, s>>>(A, rp, w.pin, w.qin, w.st, rr_in, pq_out);
+        k_inner_a2<FMT, false><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
       }
     } else
-      k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, rp, w.pin, w.qin, w.st, rr_in, pq_out);
+      k_inner_a<FMT, CW><<<gp, kB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out);
   }
 
   // 16-bit inner words (C = 64): g16 slots per group.
   template <int FMT>
-  void inner16(const PackView &A, const float2 *rp, Parts rr_in, Parts pq_out) {
+  void inner16(const PackView &A, const float *po, float *pn, Parts rr_in, Parts pq_out) {
 #define PKS_I16(GG) \
-  k_inner16<FMT, GG><<<gp, kPairB, 0, s>>>(A, rp, w.pin, w.qin, w.st, rr_in, pq_out)
+  k_inner16<FMT, GG><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out)
     switch (g16) {
       case 2: PKS_I16(2); break;
       case 3: PKS_I16(3); break;
@@ -1115,23 +1108,23 @@ struct Solve {
     const SellView &S = hv;
     const PackView A = pack_view(lo);
     const Parts ppq = pa_for(gp);
-    k_inner_init<<<vb, kB, 0, s>>>(n, w.r, w.rp0, w.zin, w.st, vec(w.pb0));
+    k_inner_init<<<vb, kB, 0, s>>>(n, w.r, w.rin, w.zin, w.f0, w.st, vec(w.pb0));
     PKS_LAUNCHED();
     for (int it = 0; it < m_in; ++it) {
-      const float2 *rp = (it & 1) ? w.rp1 : w.rp0;
-      float2 *rp_next = (it & 1) ? w.rp0 : w.rp1;
+      const float *po = (it & 1) ? w.f1 : w.f0;
+      float *pn = (it & 1) ? w.f0 : w.f1;
       const Parts rr_in = vec((it & 1) ? w.pb1 : w.pb0);
       const Parts rr_out = vec((it & 1) ? w.pb0 : w.pb1);
       const bool cw = lo->C == kWave;
       switch (lo->fmt) {
-        case PKSELL_FP16: cw ? inner_a<PKSELL_FP16, true>(A, rp, rr_in, ppq) : inner_a<PKSELL_FP16, false>(A, rp, rr_in, ppq); break;
-        case PKSELL_E8MY: cw ? inner_a<PKSELL_E8MY, true>(A, rp, rr_in, ppq) : inner_a<PKSELL_E8MY, false>(A, rp, rr_in, ppq); break;
-        case PKSELL_E5MY: inner16<PKSELL_E5MY>(A, rp, rr_in, ppq); break;
-        case PKSELL_FIX16: inner16<PKSELL_FIX16>(A, rp, rr_in, ppq); break;
-        default: cw ? inner_a<PKSELL_FIX, true>(A, rp, rr_in, ppq) : inner_a<PKSELL_FIX, false>(A, rp, rr_in, ppq); break;
+        case PKSELL_FP16: cw ? inner_a<PKSELL_FP16, true>(A, po, pn, rr_in, ppq) : inner_a<PKSELL_FP16, false>(A, po, pn, rr_in, ppq); break;
+        case PKSELL_E8MY: cw ? inner_a<PKSELL_E8MY, true>(A, po, pn, rr_in, ppq) : inner_a<PKSELL_E8MY, false>(A, po, pn, rr_in, ppq); break;
+        case PKSELL_E5MY: inner16<PKSELL_E5MY>(A, po, pn, rr_in, ppq); break;
+        case PKSELL_FIX16: inner16<PKSELL_FIX16>(A, po, pn, rr_in, ppq); break;
+        default: cw ? inner_a<PKSELL_FIX, true>(A, po, pn, rr_in, ppq) : inner_a<PKSELL_FIX, false>(A, po, pn, rr_in, ppq); break;
       }
       PKS_LAUNCHED();
-      k_inner_b<<<vb, kB, 0, s>>>(n, w.zin, rp, rp_next, w.pin, w.qin, w.st, ppq, rr_out);
+      k_inner_b<<<vb, kB, 0, s>>>(n, w.zin, w.rin, pn, w.qin, w.st, ppq, rr_out);
       PKS_LAUNCHED();
     }
     k_outer_zq<<<vb, kB, 0, s>>>(n, w.zin, w.q, w.st, vec(w.pb0));
@@ -1286,8 +1279,6 @@ int run_pcg(const pksell_matrix *A_lo, const SellView &hv, int64_t n, const doub
     PKS_CHECK(!is_w16(A_lo->fmt) || (A_lo->C == kWave && A_lo->n_words < (int64_t(1) << 31)),
               PKSELL_EINVAL, "16-bit inner words need C = 64 and fewer than 2^31 words");
     PKS_CHECK(m_in >= 1 && m_in <= 10000, PKSELL_EINVAL, "m_in must be in [1, 10000]");
-    PKS_CHECK(n < (int64_t(1) << 29), PKSELL_EINVAL,
-              "the inner-outer solve needs n < 2^29 (8-byte (r, p) pair offsets)");
   }
   PKS_CHECK(tol > 0.0 && max_outer >= 1, PKSELL_EINVAL, "tol must be > 0, max_outer >= 1");
   Solve sv;

@@ -121,7 +121,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_group(SpmvArgs a) {
     for (int r = 0; r < 4; ++r) acc[r] = ldexpf(acc[r], ro.shift(a.cd));
   }
   const int64_t o = (int64_t)ro.row() * a.k + 4 * g.q;
-  *reinterpret_cast<f32x4 *>(a.y + o) = f32x4{acc[0], acc[1], acc[2], acc[3]};
+  // streaming (nontemporal) store, as for the single-vector results
+  __builtin_nontemporal_store(f32x4{acc[0], acc[1], acc[2], acc[3]},
+                              reinterpret_cast<f32x4 *>(a.y + o));
 }
 
 // C = 64, k = 1: each wave walks two consecutive slices together, so the

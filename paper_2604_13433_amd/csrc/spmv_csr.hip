@@ -40,6 +40,11 @@ namespace {
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCsrWaves = 4;  // waves (chunks) per workgroup
+
+// FMT value of the float32 CSR comparator: 8-byte entries (column in the
+// low half, float32 value bits in the high half), absolute columns, no
+// words to decode.  Its product reuses the chunk kernel below.
+constexpr int kCsr32 = -1;
 constexpr int kCsrBlock = kCsrWaves * kWave;
 
 struct CsrArgs {
@@ -101,6 +106,11 @@ __device__ inline void seg_scan_sum(bool f, float &s, uint32_t lane) {
   }
 }
 
+// Per-lane entry registers: K for the float32 CSR comparator, 1 (unused)
+// for words.
+template <int FMT, int K>
+constexpr int kCsrEntries = FMT == kCsr32 ? K : 1;
+
 template <int FMT, int K, int NR>
 __global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
   constexpr uint32_t T = K * kWave;
@@ -138,10 +148,34 @@ __global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
   __builtin_amdgcn_wave_barrier();
   const uint32_t hb = heads[lane];
 
-  // the lane's K words (zero words past the end: delta 0, no value)
+  // the lane's K words (zero words past the end: delta 0, no value), or
+  // its K float32 CSR entries
   const int64_t q0 = p0 + (int64_t)lane * K;
   uint32_t w[K];
-  if (q0 + K <= a.n_words) {
+  uint32_t ecol[kCsrEntries<FMT, K>], eval[kCsrEntries<FMT, K>];
+  if constexpr (FMT == kCsr32) {
+    const uint64_t *ent = reinterpret_cast<const uint64_t *>(a.pack);
+    if (q0 + K <= a.n_words) {
+      const u32x4 *p4 = reinterpret_cast<const u32x4 *>(ent + q0);
+#pragma unroll
+      for (int i = 0; i < K / 2; ++i) {
+        const u32x4 u = __builtin_nontemporal_load(p4 + i);
+        ecol[2 * i] = u.x;
+        eval[2 * i] = u.y;
+        ecol[2 * i + 1] = u.z;
+        eval[2 * i + 1] = u.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint64_t e = q0 + j < a.n_words ? ent[q0 + j] : 0ull;
+        ecol[j] = (uint32_t)e;
+        eval[j] = (uint32_t)(e >> 32);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) w[j] = q0 + j < a.n_words ? 1u : 0u;  // live entries
+  } else if (q0 + K <= a.n_words) {
     const u32x4 *p4 = reinterpret_cast<const u32x4 *>(a.pack + q0);
 #pragma unroll
     for (int i = 0; i < K / 4; ++i) {
@@ -158,13 +192,14 @@ __global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
 
   // pass 1: the lane's column aggregate (absolute after a head, else a
   // delta sum) and the row of its last head
+  // (float32 CSR entries carry their columns: only the rows are scanned)
   uint32_t run = 0, lrow = 0;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const uint32_t d = unpack(w[j], a.cd).delta;
+    const uint32_t d = FMT == kCsr32 ? 0u : unpack(w[j], a.cd).delta;
     if ((hb >> j) & 1u) {
       lrow = hrow[lane * K + j];
-      run = row_base(lrow, a.k_left) + d;
+      run = FMT == kCsr32 ? 0u : row_base(lrow, a.k_left) + d;
     } else {
       run += d;
     }
@@ -182,7 +217,7 @@ __global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
     ev = 0u;
     er = rlo - 1u;
   }
-  const uint32_t anchor = a.anchor[c];
+  const uint32_t anchor = FMT == kCsr32 ? 0u : a.anchor[c];
   uint32_t col = ef ? ev : anchor + ev;
 
   // pass 2: columns, gathers, per-row sums in word order
@@ -191,10 +226,15 @@ __global__ __launch_bounds__(kCsrBlock) void k_csr_chunks(CsrArgs a) {
   float xv[K][NR], val[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const Unpacked u = unpack(w[j], a.cd);
-    if ((hb >> j) & 1u) col = row_base(hrow[lane * K + j], a.k_left) + u.delta;
-    else col += u.delta;
-    val[j] = decode_value<FMT>(u.vbits);
+    if constexpr (FMT == kCsr32) {
+      col = ecol[j];
+      val[j] = __builtin_bit_cast(float, eval[j]);
+    } else {
+      const Unpacked u = unpack(w[j], a.cd);
+      if ((hb >> j) & 1u) col = row_base(hrow[lane * K + j], a.k_left) + u.delta;
+      else col += u.delta;
+      val[j] = decode_value<FMT>(u.vbits);
+    }
     const uint32_t off = (w[j] & 1u) ? col * 4u * NR : oob;
     if constexpr (NR == 4) {
       const f32x4 v4 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rx, off, 0, 0));
@@ -369,4 +409,116 @@ int spmv_chunks(const pksell_matrix *A, const float *x, float *y, int64_t k, hip
   }
 }
 
+
+namespace {
+
+// lo[c] = the first row whose entries start at or after entry c T; lo[n_chunks] = n.
+__global__ void k_csr32_lo(const int64_t *__restrict__ rowptr, int64_t n, int64_t n_chunks,
+                           int64_t T, uint32_t *__restrict__ lo) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > n_chunks) return;
+  if (c == n_chunks) {
+    lo[c] = (uint32_t)n;
+    return;
+  }
+  const int64_t p = c * T;
+  int64_t lo_i = 0, hi_i = n;
+  while (lo_i < hi_i) {
+    const int64_t mid = (lo_i + hi_i) / 2;
+    if (rowptr[mid] < p) lo_i = mid + 1;
+    else hi_i = mid;
+  }
+  lo[c] = (uint32_t)lo_i;
+}
+
+template <typename V>
+__global__ void k_csr32_fill(const int32_t *__restrict__ col, const V *__restrict__ val,
+                             int64_t nnz, uint64_t *__restrict__ ent) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnz) return;
+  const float v = (float)val[i];
+  ent[i] = (uint64_t)(uint32_t)col[i] | ((uint64_t)__builtin_bit_cast(uint32_t, v) << 32);
+}
+
+}  // namespace
 }  // namespace pksell
+
+using namespace pksell;
+
+extern "C" {
+
+int pksell_csr32_query(int64_t n, int64_t m, int64_t nnz, int32_t T, pksell_csr32 *A) {
+  PKS_CHECK(A, PKSELL_EINVAL, "null descriptor");
+  PKS_CHECK(T == 256 || T == 512 || T == 1024, PKSELL_EINVAL, "T must be 256, 512 or 1024");
+  PKS_CHECK(n >= 0 && m >= 0 && n < (int64_t(1) << 30) && m < (int64_t(1) << 30), PKSELL_EINVAL,
+            "n and m must be in [0, 2^30)");
+  PKS_CHECK(nnz >= 0 && nnz < (int64_t(1) << 31), PKSELL_EINVAL, "nnz must be in [0, 2^31)");
+  std::memset(A, 0, sizeof(*A));
+  A->n = n;
+  A->m = m;
+  A->nnz = nnz;
+  A->T = T;
+  A->n_chunks = cdiv(nnz, T);
+  return PKSELL_OK;
+}
+
+int pksell_csr32_encode(const int32_t *col, const void *val, int32_t val_dtype, pksell_csr32 *A,
+                        void *stream) {
+  PKS_CHECK(A, PKSELL_EINVAL, "null descriptor");
+  PKS_CHECK(val_dtype == PKSELL_F32 || val_dtype == PKSELL_F64, PKSELL_EINVAL,
+            "val_dtype must be PKSELL_F32 or PKSELL_F64");
+  PKS_CHECK(A->n_chunks == cdiv(A->nnz, A->T), PKSELL_EINVAL, "descriptor not from the query");
+  PKS_CHECK(A->rowptr && A->lo && (A->nnz == 0 || (A->ent && col && val)), PKSELL_EINVAL,
+            "arrays not set");
+  hipStream_t st = as_stream(stream);
+  if (A->nnz > 0) {
+    if (val_dtype == PKSELL_F32)
+      k_csr32_fill<float><<<cdiv(A->nnz, 256), 256, 0, st>>>(col, static_cast<const float *>(val),
+                                                            A->nnz, A->ent);
+    else
+      k_csr32_fill<double><<<cdiv(A->nnz, 256), 256, 0, st>>>(
+          col, static_cast<const double *>(val), A->nnz, A->ent);
+    PKS_LAUNCHED();
+  }
+  k_csr32_lo<<<cdiv(A->n_chunks + 1, 256), 256, 0, st>>>(A->rowptr, A->n, A->n_chunks, A->T,
+                                                         A->lo);
+  PKS_LAUNCHED();
+  return PKSELL_OK;
+}
+
+int pksell_csr32_spmv(const pksell_csr32 *A, const float *x, float *y, void *stream) {
+  PKS_CHECK(A, PKSELL_EINVAL, "null descriptor");
+  PKS_CHECK(A->T == 256 || A->T == 512 || A->T == 1024, PKSELL_EINVAL, "bad T");
+  PKS_CHECK(A->n_chunks == cdiv(A->nnz, A->T), PKSELL_EINVAL, "descriptor not from the query");
+  PKS_CHECK(A->n == 0 || y, PKSELL_EINVAL, "null y");
+  hipStream_t st = as_stream(stream);
+  if (A->n == 0) return PKSELL_OK;
+  if (A->n_chunks == 0) {  // no entries: every row is empty
+    k_csr_zero<<<cdiv(A->n, 256), 256, 0, st>>>(y, A->n);
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
+  PKS_CHECK(x && A->rowptr && A->ent && A->lo && A->partial, PKSELL_EINVAL, "arrays not set");
+  PKS_CHECK(((uintptr_t)A->ent & 15) == 0, PKSELL_EINVAL, "ent must be 16-byte aligned");
+  CsrArgs a{};
+  a.pack = reinterpret_cast<const uint32_t *>(A->ent);
+  a.rowptr = A->rowptr;
+  a.lo = A->lo;
+  a.anchor = nullptr;
+  a.row_exp = nullptr;
+  a.x = x;
+  a.y = y;
+  a.head_part = A->partial;
+  a.tail_part = A->partial + A->n_chunks;
+  a.tail_row = reinterpret_cast<int32_t *>(A->partial + 2 * A->n_chunks);
+  a.nr = 1;
+  a.n_words = A->nnz;
+  a.n = (uint32_t)A->n;
+  a.m = (uint32_t)A->m;
+  a.n_chunks = (uint32_t)A->n_chunks;
+  a.k_left = 0;
+  a.D = 0;
+  return launch_chunks_nr<kCsr32, 1>(a, A->T / kWave, st);
+}
+
+}  // extern "C"

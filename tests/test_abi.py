@@ -249,3 +249,18 @@ def test_encode_checks_chunk_words_for_one_row_slices(sigma, J):
     rc = B.lib().pksell_encode(p, p, p, B.F32, ctypes.byref(desc), p, max(ws, 4096), None)
     assert rc == B.EINVAL
     assert b"split_words" in B.lib().pksell_last_error()
+
+
+@pytest.mark.parametrize("n,m,nnz,T", [(10, 10, 10, 300), (10, 10, 10, 128), (-1, 10, 10, 512),
+                                       (1 << 30, 10, 10, 512), (10, 10, 1 << 31, 512)])
+def test_csr32_query_rejects(n, m, nnz, T):
+    d = B.CCsr32()
+    assert B.lib().pksell_csr32_query(n, m, nnz, T, ctypes.byref(d)) == B.EINVAL
+    assert B.lib().pksell_last_error()
+
+
+def test_csr32_query_sizes():
+    d = B.CCsr32()
+    assert B.lib().pksell_csr32_query(7, 9, 1025, 512, ctypes.byref(d)) == B.OK
+    assert (d.n, d.m, d.nnz, d.T, d.n_chunks) == (7, 9, 1025, 512, 3)
+    assert ctypes.sizeof(B.CCsr32) == 72
