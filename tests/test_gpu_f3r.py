@@ -171,3 +171,35 @@ def test_workspace_too_small():
                             ctypes.byref(prm), ctypes.byref(info), B._ptr(ws), need.value - 1,
                             B._stream(DEV))
     assert rc == B.EWORKSPACE
+
+
+def test_mixed_forms_identical_on_m4_full_size():
+    """The 27-point 100^3 system of the solver benchmark (n = 10^6): FP16
+    SELL and FP16 PackSELL inner layers give the same solve bit for bit,
+    and both reach a true residual below 1e-10 in float64."""
+    a = W.symmetric_diag_scale(W.m4_stencil27())
+    b = W.ones_rhs(a)
+    bd = torch.from_numpy(b).to(DEV)
+    A1 = sell(a, torch.float64)
+    A2 = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, torch.float32, 64, 256, B.IMPLICIT, DEV,
+                       paired=True)
+    xs, infs = B.f3r(A1, bd, A2, sell(a, torch.float16), tol=1e-10)
+    xp, infp = B.f3r(A1, bd, A2, packed(a), tol=1e-10)
+    assert torch.equal(xs, xp) and infs["outer_iterations"] == infp["outer_iterations"]
+    assert true_residual(a, b, xp.cpu().numpy()) < 1e-10
+    assert float((xp - 1.0).abs().max()) < 1e-7
+
+
+def test_mid_size_mixed_form_matches_oracle():
+    """A 40^3 27-point system: the PackSELL form against the oracle's F3R
+    on the same float32 (layer 2) and FP16 (layers 3-4) values."""
+    a = spd(40, 5)
+    b = rhs(a, "ones")
+    bd = torch.from_numpy(b).to(DEV)
+    x, info = B.f3r(sell(a, torch.float64), bd, sell(a, torch.float32), packed(a), tol=1e-10)
+    x = x.cpu().numpy()
+    ref = F3.f3r(a.rowptr, a.col, a.val, v32(a), v16(a), b, F3.F3RParams(), tol=1e-10)
+    assert ref.converged
+    assert info["rel_residual"] < 1e-10 and true_residual(a, b, x) < 1e-10
+    assert np.max(np.abs(x - ref.x)) < 1e-7 * np.abs(ref.x).max()
+    assert abs(info["outer_iterations"] - ref.outer_steps) <= 2

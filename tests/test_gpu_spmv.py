@@ -135,6 +135,24 @@ def test_lane_groups_equal_single_vector_products(k):
         assert torch.equal(Y[:, r], B.spmv(A, X[:, r].contiguous())), r
 
 
+@pytest.mark.parametrize("k", [32, 64])
+def test_lane_groups_wide_window(k):
+    """A 96^3 7-point Laplacian (k_left = 9216, implicit order): at k = 32
+    and 64 the x rows one sigma-block reads span several MiB.  Every column
+    equals the one-vector product bit for bit, and the oracle's within the
+    bar."""
+    a = W.m2_laplace3d(96)
+    A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 64, 256, B.IMPLICIT, DEV)
+    assert A.k_left == 96 * 96
+    X = torch.from_numpy(W.uniform_vector(a.m, 11, k=k)).to(DEV)
+    Y = B.spmv(A, X)
+    for r in (0, 1, 27, 28, 31, k - 1):
+        assert torch.equal(Y[:, r], B.spmv(A, X[:, r].contiguous())), r
+    cols = [0, 28, k - 1]
+    ref, q = oracle_product(a, F.FMT_FP16, 15, X[:, cols].cpu().numpy())
+    assert normalised_error(Y[:, cols].cpu().numpy(), ref, a, q, X[:, cols].cpu().numpy()) <= SPMV_TOL
+
+
 def test_m1_poisson_fp16():
     a = W.m1_poisson2d()
     x = W.uniform_vector(a.m, 1)
