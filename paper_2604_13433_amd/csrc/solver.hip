@@ -284,16 +284,43 @@ __global__ __launch_bounds__(kB) void k_inner_a(PackView A, const float *__restr
   put_partials(v, pq_out);
 }
 
+// Word loads of the inner products.  The inner operator is read once per
+// inner iteration, m_in times in a row.  When its words (with the inner
+// vectors) fit in the 256 MB last-level cache, loads with the default
+// policy (RES) let the later iterations find them there: the inner-outer
+// CG with E8M8 words on the 27-point 100^3 system took 14.7 ms against
+// 17.7 ms with the streaming policy.  When they do not fit, the streaming
+// policy (read once, not kept) is the faster one.
+template <bool RES>
+__device__ inline uint32_t inner_word(__amdgpu_buffer_rsrc_t rs, uint32_t lane, uint32_t j) {
+  return __builtin_amdgcn_raw_buffer_load_b32(rs, (lane + j * kWave) * 4u, 0,
+                                              RES ? 0 : kStreamPolicy);
+}
+
+// One float32 element stored through a buffer resource on [v, v + n) with
+// the default policy (the next kernels read p and q again); rows at or past
+// n fall outside the resource and are dropped.
+__device__ inline void store_row(float *v, uint32_t n, uint32_t row, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), make_rsrc(v, n * 4u),
+                                        row * 4u, 0, 0);
+}
+
 // (A) for C = 64: the same step with two slices per wave and 128-thread
 // workgroups (four slices per workgroup, as in k_inner_a), so the grid runs
-// in about one round of waves; the first eight words of both slices are
-// requested before the previous partials are summed, so their latency
-// overlaps the beta prologue.  Same arithmetic per row as k_inner_a.
+// in about one round of waves.  The first group of words of both slices,
+// and r and p_old at the lane's own rows, are requested before the previous
+// partials are summed, so their latency overlaps the beta prologue.  With
+// streamed words the loads need no branch (words past a slice's width read
+// 0 from its resource, with no request), so each gather goes out as soon as
+// its word has arrived; the last group finishes and stores one slice before
+// the next slice's products wait on their gathers.  Same arithmetic per row
+// as k_inner_a.
 constexpr int kPairB = 128;
 
 // G words per group and slice, sized on the host to the matrix's slice
 // width (each word of a group issues a load and a gather, padding or not).
-template <int FMT, bool BUF, int G = kUnroll>
+// RES: words loaded with the default policy (see inner_word).
+template <int FMT, bool BUF, int G = kUnroll, bool RES = false>
 __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__restrict__ r,
                                                     const float *__restrict__ p_old,
                                                     float *__restrict__ p_new,
@@ -315,20 +342,35 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
   for (int i = 0; i < S; ++i)
     ro[i] = row_out<FMT>(A.perm, A.perm_bytes, A.row_exp, stop ? A.n : (k0 + i) * kWave + lane,
                          A.n, A.geo);
-  auto word = [&](int i, uint32_t j) {
-    return BUF ? stream_word(rs[i], lane, j)
-               : __builtin_nontemporal_load(A.pack + off[i] + lane + j * kWave);
-  };
 #pragma unroll
   for (int i = 0; i < S; ++i) {
     w[i] = stop ? 0u : (uint32_t)((off[i + 1] - off[i]) >> 6);
     rs[i] = slice_words(A.pack + off[i], w[i]);
+  }
+  auto load_group = [&](uint32_t j) {
 #pragma unroll
-    for (int u = 0; u < G; ++u) {
-      uint32_t v = 0u;
-      if (u < (int)w[i]) v = word(i, u);
-      p[i][u] = v;
-    }
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        uint32_t v = 0u;  // past the slice's width: a padding word
+        if (BUF)
+          v = inner_word<RES>(rs[i], lane, j + u);
+        else if (j + u < w[i])
+          v = __builtin_nontemporal_load(A.pack + off[i] + lane + (j + u) * kWave);
+        p[i][u] = v;
+      }
+  };
+  load_group(0);
+  // The lane's own rows (row n, past every resource, for phantom rows and
+  // slices past the end: their loads read 0 and their stores are dropped).
+  const __amdgpu_buffer_rsrc_t rr_r = make_rsrc(r, A.n * 4u);
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(p_old, A.n * 4u);
+  uint32_t dst[S];
+  float r_row[S], p_row[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    const uint32_t t = (k0 + i) * kWave + lane;
+    dst[i] = (!stop && k0 + i < A.n_slices && t < A.n) ? ro[i].row() : A.n;
   }
   const bool first = st->in_first;
   double rr[1] = {0.0};
@@ -343,8 +385,6 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
   }
   if (stop || quit) return;
   const float beta = (float)beta_d;
-  const __amdgpu_buffer_rsrc_t rr_r = make_rsrc(r, A.n * 4u);
-  const __amdgpu_buffer_rsrc_t rp = make_rsrc(p_old, A.n * 4u);
   const uint32_t oob = A.n * 4u;  // flag-0 words: past the resources, no request
   uint32_t c[S];
   float acc[S];
@@ -355,51 +395,48 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
     acc[i] = 0.0f;
     wm = max(wm, w[i]);
   }
-  for (uint32_t j = 0; j < wm; j += G) {
-    if (j > 0) {
-#pragma unroll
-      for (int i = 0; i < S; ++i)
-#pragma unroll
-        for (int u = 0; u < G; ++u) {
-          uint32_t v = 0u;
-          if (j + u < w[i]) v = word(i, j + u);
-          p[i][u] = v;
-        }
-    }
-    uint32_t o[S][G];
-    float v[S][G];
+  // columns, values and gathers of the loaded group
+  auto gather_group = [&](float (&v)[S][G], float (&xv)[S][G]) {
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const Unpacked d = unpack(p[i][u], A.cd);
         c[i] += d.delta;
-        o[i][u] = (p[i][u] & 1u) ? c[i] << 2 : oob;
+        const uint32_t o = (p[i][u] & 1u) ? c[i] << 2 : oob;
         v[i][u] = decode_value<FMT>(d.vbits);
+        xv[i][u] = fmaf(beta, buffer_load_f32(rp, o), buffer_load_f32(rr_r, o));
       }
-    float xv[S][G];
-#pragma unroll
-    for (int i = 0; i < S; ++i)
-#pragma unroll
-      for (int u = 0; u < G; ++u)
-        xv[i][u] = fmaf(beta, buffer_load_f32(rp, o[i][u]), buffer_load_f32(rr_r, o[i][u]));
+  };
+  uint32_t j = 0;
+  for (; j + G < wm; j += G) {  // every group but the last
+    float v[S][G], xv[S][G];
+    gather_group(v, xv);
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
       for (int u = 0; u < G; ++u) acc[i] = fmaf(v[i][u], xv[i][u], acc[i]);
+    load_group(j + G);
   }
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    r_row[i] = buffer_load_f32(rr_r, dst[i] * 4u);
+    p_row[i] = buffer_load_f32(rp, dst[i] * 4u);
+  }
+  float v[S][G], xv[S][G];
+  gather_group(v, xv);
   double part = 0.0;
 #pragma unroll
   for (int i = 0; i < S; ++i) {
-    const uint32_t t = (k0 + i) * kWave + lane;
-    if (k0 + i >= A.n_slices || t >= A.n) continue;
+#pragma unroll
+    for (int u = 0; u < G; ++u) acc[i] = fmaf(v[i][u], xv[i][u], acc[i]);
     float qi = acc[i];
     if constexpr (FMT == PKSELL_FIX) qi = ldexpf(qi, ro[i].shift(A.cd));
-    const uint32_t row = ro[i].row();
-    const float pn = fmaf(beta, p_old[row], r[row]);
-    p_new[row] = pn;
-    q[row] = qi;
+    const float pn = fmaf(beta, p_row[i], r_row[i]);  // 0 for rows past n
+    store_row(p_new, A.n, dst[i], pn);
+    store_row(q, A.n, dst[i], qi);
     part += (double)pn * (double)qi;
+    __builtin_amdgcn_sched_barrier(0);  // keep the next slice's products after these stores
   }
   double vv[1] = {part};
   put_partials<1, kPairB>(vv, pq_out);
@@ -407,10 +444,12 @@ __global__ __launch_bounds__(kPairB) void k_inner_a2(PackView A, const float *__
 
 // (A) for 16-bit words (E5MY, FIX16; C = 64): the step of k_inner_a2 with
 // every 32-bit slot holding two consecutive words of a row (low half
-// first), G slots (2G words) per group, the first slots requested before
-// the previous partials are summed.  Same grid and partial layout as
-// k_inner_a2 (two slices per wave, 128-thread workgroups).
-template <int FMT, int G>
+// first), G slots (2G words) per group.  Same grid and partial layout as
+// k_inner_a2 (two slices per wave, 128-thread workgroups), and the same
+// order of work: the first slots and the own rows' r and p_old requested
+// before the previous partials are summed, branch-free slot loads, the
+// first slice stored before the second waits on its gathers.
+template <int FMT, int G, bool RES = false>
 __global__ __launch_bounds__(kPairB) void k_inner16(PackView A, const float *__restrict__ r,
                                                    const float *__restrict__ p_old,
                                                    float *__restrict__ p_new,
@@ -436,8 +475,20 @@ __global__ __launch_bounds__(kPairB) void k_inner16(PackView A, const float *__r
   for (int i = 0; i < S; ++i) {
     w[i] = stop ? 0u : (uint32_t)((off[i + 1] - off[i]) >> 7);
     rs[i] = slice_words(A.pack + (off[i] >> 1), w[i]);
+  }
+  // slots past a slice's width read 0 from its resource, with no request
+  auto load_group = [&](uint32_t j) {
 #pragma unroll
-    for (int u = 0; u < G; ++u) p[i][u] = u < (int)w[i] ? stream_word(rs[i], lane, u) : 0u;
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int u = 0; u < G; ++u) p[i][u] = inner_word<RES>(rs[i], lane, j + u);
+  };
+  load_group(0);
+  uint32_t dst[S];  // row n (past every resource) for phantom rows
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    const uint32_t t = (k0 + i) * kWave + lane;
+    dst[i] = (!stop && k0 + i < A.n_slices && t < A.n) ? ro[i].row() : A.n;
   }
   const bool first = st->in_first;
   double rr[1] = {0.0};
@@ -465,15 +516,8 @@ __global__ __launch_bounds__(kPairB) void k_inner16(PackView A, const float *__r
     acc[i] = 0.0f;
     wm = max(wm, w[i]);
   }
-  for (uint32_t j = 0; j < wm; j += G) {
-    if (j > 0) {
-#pragma unroll
-      for (int i = 0; i < S; ++i)
-#pragma unroll
-        for (int u = 0; u < G; ++u) p[i][u] = j + u < w[i] ? stream_word(rs[i], lane, j + u) : 0u;
-    }
-    uint32_t o[S][2 * G];
-    float v[S][2 * G];
+  // columns, values and gathers of the loaded group (two words per slot)
+  auto gather_group = [&](float (&v)[S][2 * G], float (&xv)[S][2 * G]) {
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
@@ -481,36 +525,45 @@ __global__ __launch_bounds__(kPairB) void k_inner16(PackView A, const float *__r
         const uint32_t wd = (h & 1) ? p[i][h >> 1] >> 16 : p[i][h >> 1] & 0xFFFFu;
         const bool flag = wd & 1u;
         c[i] += flag ? (wd >> 1) & dmask : (wd >> 1);
-        o[i][h] = flag ? c[i] << 2 : oob;
+        const uint32_t o = flag ? c[i] << 2 : oob;
         const uint32_t bits = flag ? wd & vmask : 0u;
         if constexpr (FMT == PKSELL_E5MY)
           v[i][h] = __half2float(__ushort_as_half((unsigned short)bits));
         else
           v[i][h] = (float)(int32_t)(int16_t)(uint16_t)bits;  // FIX16: q * 2^(D+1)
+        xv[i][h] = fmaf(beta, buffer_load_f32(rp, o), buffer_load_f32(rr_r, o));
       }
-    float xv[S][2 * G];
-#pragma unroll
-    for (int i = 0; i < S; ++i)
-#pragma unroll
-      for (int h = 0; h < 2 * G; ++h)
-        xv[i][h] = fmaf(beta, buffer_load_f32(rp, o[i][h]), buffer_load_f32(rr_r, o[i][h]));
+  };
+  uint32_t j = 0;
+  for (; j + G < wm; j += G) {  // every group but the last
+    float v[S][2 * G], xv[S][2 * G];
+    gather_group(v, xv);
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
       for (int h = 0; h < 2 * G; ++h) acc[i] = fmaf(v[i][h], xv[i][h], acc[i]);
+    load_group(j + G);
   }
+  float r_row[S], p_row[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    r_row[i] = buffer_load_f32(rr_r, dst[i] * 4u);
+    p_row[i] = buffer_load_f32(rp, dst[i] * 4u);
+  }
+  float v[S][2 * G], xv[S][2 * G];
+  gather_group(v, xv);
   double part = 0.0;
 #pragma unroll
   for (int i = 0; i < S; ++i) {
-    const uint32_t t = (k0 + i) * kWave + lane;
-    if (k0 + i >= A.n_slices || t >= A.n) continue;
+#pragma unroll
+    for (int h = 0; h < 2 * G; ++h) acc[i] = fmaf(v[i][h], xv[i][h], acc[i]);
     float qi = acc[i];
     if constexpr (FMT == PKSELL_FIX16) qi = ldexpf(qi, ro[i].shift(A.cd));
-    const uint32_t row = ro[i].row();
-    const float pn = fmaf(beta, p_old[row], r[row]);
-    p_new[row] = pn;
-    q[row] = qi;
+    const float pn = fmaf(beta, p_row[i], r_row[i]);  // 0 for rows past n
+    store_row(p_new, A.n, dst[i], pn);
+    store_row(q, A.n, dst[i], qi);
     part += (double)pn * (double)qi;
+    __builtin_amdgcn_sched_barrier(0);  // keep the next slice's products after these stores
   }
   double vv[1] = {part};
   put_partials<1, kPairB>(vv, pq_out);
@@ -1028,6 +1081,7 @@ struct Solve {
   bool stream_ok;   // the inner words are addressable by 32-bit byte offsets
   int g_in;         // inner product: words per group (4..8)
   int g16;          // 16-bit inner words: slots per group (2..4)
+  bool resident;    // inner words loaded so that they stay in the last-level cache
 
   Parts pa_for(uint32_t grid) const { return {w.pa.p, grid}; }
   Parts vec(const Parts &p) const { return {p.p, vb}; }
@@ -1073,8 +1127,11 @@ struct Solve {
     // wave, or 128 threads x 2 slices per wave), so the partial count agrees
     if constexpr (CW) {
       if (stream_ok) {
-#define PKS_IA2(GG)                                                                       \
-  k_inner_a2<FMT, true, GG><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out)
+#define PKS_IA2(GG)                                                                      \
+  (resident ? k_inner_a2<FMT, true, GG, true><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin,  \
+                                                                   w.st, rr_in, pq_out)      \
+            : k_inner_a2<FMT, true, GG, false><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, \
+                                                                    w.st, rr_in, pq_out))
         switch (g_in) {
           case 4: PKS_IA2(4); break;
           case 5: PKS_IA2(5); break;
@@ -1093,8 +1150,12 @@ struct Solve {
   // 16-bit inner words (C = 64): g16 slots per group.
   template <int FMT>
   void inner16(const PackView &A, const float *po, float *pn, Parts rr_in, Parts pq_out) {
-#define PKS_I16(GG) \
-  k_inner16<FMT, GG><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in, pq_out)
+#define PKS_I16(GG)                                                                         \
+  (resident                                                                                     \
+       ? k_inner16<FMT, GG, true><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in,   \
+                                                        pq_out)                                 \
+       : k_inner16<FMT, GG, false><<<gp, kPairB, 0, s>>>(A, w.rin, po, pn, w.qin, w.st, rr_in,  \
+                                                         pq_out))
     switch (g16) {
       case 2: PKS_I16(2); break;
       case 3: PKS_I16(3); break;
@@ -1291,6 +1352,15 @@ int run_pcg(const pksell_matrix *A_lo, const SellView &hv, int64_t n, const doub
   sv.gs = (uint32_t)cdiv((int64_t)hv.n_slices * hv.C, kB);
   sv.gp = A_lo ? (uint32_t)cdiv(A_lo->n_slices * A_lo->C, kB) : 0u;
   sv.stream_ok = A_lo && A_lo->n_words < (int64_t(1) << 30);
+  // The inner words and the five float32 inner vectors, read m_in times in
+  // a row, stay in the 256 MB last-level cache when they take at most
+  // 192 MiB of it (a margin for the rest of the traffic).
+  if (A_lo) {
+    const int64_t word_bytes = is_w16(A_lo->fmt) ? 2 : 4;
+    sv.resident = A_lo->n_words * word_bytes + 20 * (int64_t)n <= (int64_t(192) << 20);
+  } else {
+    sv.resident = false;
+  }
   sv.g_in = A_lo ? group_for(A_lo->n_words, A_lo->n_slices * A_lo->C) : 8;
   sv.g16 = 4;
   if (A_lo && is_w16(A_lo->fmt) && A_lo->n_slices > 0) {
