@@ -1279,10 +1279,21 @@ int solve(Solve &sv, double tol, int32_t m_in, int32_t max_outer, pksell_pcg_inf
   if ((rc = restart(sv, h))) return rc;
 
   const bool plain = sv.lo == nullptr;
-  constexpr int kCgPerGraph = 16;
+  // Iterations per graph replay: the host reads the state once per replay,
+  // and the steps enqueued after convergence (or the iteration limit) find
+  // the solver stopped and exit at once.  Two outer steps per replay halve
+  // the host round trips (about 40 us each) for at most one idle step.
+  constexpr int kCgPerGraph = 16, kOuterPerGraph = 2;
   hipGraphExec_t exec = nullptr;
   rc = plain ? capture(s, [&] { return sv.cg_iterations(kCgPerGraph); }, &exec)
-             : capture(s, [&] { return sv.outer_iteration(m_in); }, &exec);
+             : capture(s,
+                       [&] {
+                         int r = PKSELL_OK;
+                         for (int i = 0; i < kOuterPerGraph && r == PKSELL_OK; ++i)
+                           r = sv.outer_iteration(m_in);
+                         return r;
+                       },
+                       &exec);
   if (rc) return rc;
   int status = PKSELL_OK;
   for (;;) {
