@@ -900,8 +900,15 @@ def f3r_leg(args, torch, B, W):
         A3p = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 64, 256, B.IMPLICIT, dev)
         res = {"n": a.n, "nnz": a.nnz, "params": "m1=100 m2=8 m3=4 m4=2 omega=1"}
         xs = {}
+        # the *_resident forms set cache_hint RESIDENT on the layer 3-4 operator
+        # (applied 64 times per outer step), so that it can stay in the
+        # last-level cache between its products
+        A3s_r, A3p_r = A3s.replicate(), A3p.replicate()
+        A3s_r.cache_hint = A3p_r.cache_hint = B.CACHE_RESIDENT
         for name, kw in (("fp64_f3r", {}), ("fp16_f3r", dict(A2=A2, A3=A3s)),
-                         ("packsell_f3r", dict(A2=A2, A3=A3p))):
+                         ("packsell_f3r", dict(A2=A2, A3=A3p)),
+                         ("fp16_f3r_resident", dict(A2=A2, A3=A3s_r)),
+                         ("packsell_f3r_resident", dict(A2=A2, A3=A3p_r))):
             times, info, x = [], None, None
             for _ in range(3):
                 x, info = B.f3r(A1, b, tol=1e-10, **kw)
@@ -913,13 +920,17 @@ def f3r_leg(args, torch, B, W):
                              outer_steps=info["outer_iterations"], rel_residual=info["rel_residual"],
                              true_rel_residual_host=true)
             log(f"[bench] F3R {label} {name}: {res[name]}")
-        for name in ("fp16_f3r", "packsell_f3r"):
+        for name in ("fp16_f3r", "packsell_f3r", "fp16_f3r_resident", "packsell_f3r_resident"):
             res[name]["speedup_vs_fp64_f3r"] = round(res["fp64_f3r"]["ms"] / res[name]["ms"], 3)
         res["packsell_over_fp16_speedup"] = round(res["fp16_f3r"]["ms"] / res["packsell_f3r"]["ms"], 3)
-        res["fp16_and_packsell_iterates_identical"] = bool(torch.equal(xs["fp16_f3r"],
-                                                                      xs["packsell_f3r"]))
+        res["packsell_over_fp16_speedup_resident"] = round(
+            res["fp16_f3r_resident"]["ms"] / res["packsell_f3r_resident"]["ms"], 3)
+        res["fp16_and_packsell_iterates_identical"] = bool(
+            torch.equal(xs["fp16_f3r"], xs["packsell_f3r"]) and
+            torch.equal(xs["fp16_f3r"], xs["fp16_f3r_resident"]) and
+            torch.equal(xs["packsell_f3r"], xs["packsell_f3r_resident"]))
         out[label] = res
-        del A1, A2, A3s, A3p
+        del A1, A2, A3s, A3p, A3s_r, A3p_r
     return out
 
 

@@ -151,13 +151,29 @@ typedef struct pksell_matrix {
   int64_t *offset;
   void *perm;
   int16_t *row_exp;
-  int32_t split_words, reserved;
+  int32_t split_words, cache_hint; /* cache_hint: PKSELL_CACHE_* below */
   int64_t n_units, n_split_units, n_split_slices;
   uint32_t *units;
   uint32_t *splits;
   uint32_t *ckpt;
   float *partial;
 } pksell_matrix;
+
+/* How the single-vector products with C = 64 (pksell_spmv with k = 1 on
+ * 32-bit words; pksell_sell_spmv with float32 vectors) load the matrix;
+ * other products ignore it.  pksell_encode_query and pksell_sell_query set
+ * 0; the caller may change it at any time between products.  Any other
+ * value acts as PKSELL_CACHE_STREAM.
+ *   PKSELL_CACHE_STREAM    streaming cache policy: the product reads each
+ *                          word once and keeps none (the fastest policy
+ *                          when the matrix is not read again soon);
+ *   PKSELL_CACHE_RESIDENT  default policy: for a matrix applied many times
+ *                          in a row (an iterative method), so that one that
+ *                          fits in the 256 MB last-level cache stays there
+ *                          between products.
+ * The results are the same either way, bit for bit. */
+#define PKSELL_CACHE_STREAM 0
+#define PKSELL_CACHE_RESIDENT 1
 
 /* Plain SELL-C-sigma (sec. 3) with float32 or float64 values and int32
  * columns -- the same-GPU comparator and the float64 operator of the outer
@@ -167,7 +183,7 @@ typedef struct pksell_matrix {
 typedef struct pksell_sell {
   int64_t n, m, nnz;
   int32_t C, sigma, perm_mode, perm_bytes, dtype; /* PKSELL_F32/F64/F16 */
-  int32_t reserved;
+  int32_t cache_hint; /* PKSELL_CACHE_* (above) */
   int64_t n_slices, n_slots;
   int64_t *offset;
   void *perm;

@@ -21,6 +21,7 @@ FP16, E8MY, FIX, E11MY, E5MY, FIX16 = 0, 1, 2, 3, 4, 5  # E5MY, FIX16: 16-bit wo
 EXPLICIT, IMPLICIT = 0, 1
 F32, F64, F16 = 4, 8, 2  # F16: SELL half values (float32 vectors)
 F32_PAIRED = 12  # SELL float32 values and int32 columns in one 8-byte slot
+CACHE_STREAM, CACHE_RESIDENT = 0, 1  # cache_hint of a matrix (include/pksell.h)
 FMT_BY_NAME = {"fp16": FP16, "e8my": E8MY, "fix": FIX, "e11my": E11MY, "e5my": E5MY,
                "fix16": FIX16}
 W16 = (E5MY, FIX16)
@@ -40,7 +41,7 @@ class CMatrix(ctypes.Structure):
                 ("perm_mode", i32), ("perm_bytes", i32),
                 ("n_slices", i64), ("n_words", i64), ("n_dummies", i64), ("k_left", i64),
                 ("pack", vp), ("offset", vp), ("perm", vp), ("row_exp", vp),
-                ("split_words", i32), ("reserved", i32),
+                ("split_words", i32), ("cache_hint", i32),
                 ("n_units", i64), ("n_split_units", i64), ("n_split_slices", i64),
                 ("units", vp), ("splits", vp), ("ckpt", vp), ("partial", vp)]
 
@@ -48,7 +49,7 @@ class CMatrix(ctypes.Structure):
 class CSell(ctypes.Structure):
     _fields_ = [("n", i64), ("m", i64), ("nnz", i64),
                 ("C", i32), ("sigma", i32), ("perm_mode", i32), ("perm_bytes", i32),
-                ("dtype", i32), ("reserved", i32),
+                ("dtype", i32), ("cache_hint", i32),
                 ("n_slices", i64), ("n_slots", i64),
                 ("offset", vp), ("perm", vp), ("col", vp), ("val", vp)]
 
@@ -219,6 +220,17 @@ class PackSELLMatrix:
     C = property(lambda s: s.desc.C)
     sigma = property(lambda s: s.desc.sigma)
     perm_mode = property(lambda s: s.desc.perm_mode)
+
+    @property
+    def cache_hint(self) -> int:
+        """CACHE_STREAM (the default) or CACHE_RESIDENT: how the
+        single-vector product (k = 1, C = 64) loads the words (same results
+        either way)."""
+        return self.desc.cache_hint
+
+    @cache_hint.setter
+    def cache_hint(self, v: int):
+        self.desc.cache_hint = int(v)
 
     @property
     def pack(self):
@@ -585,6 +597,16 @@ class SellMatrix:
     n = property(lambda s: s.desc.n)
     m = property(lambda s: s.desc.m)
     n_slots = property(lambda s: s.desc.n_slots)
+
+    @property
+    def cache_hint(self) -> int:
+        """CACHE_STREAM (the default) or CACHE_RESIDENT: how the C = 64
+        float32-vector product loads the slots (same results either way)."""
+        return self.desc.cache_hint
+
+    @cache_hint.setter
+    def cache_hint(self, v: int):
+        self.desc.cache_hint = int(v)
 
     @property
     def dtype(self):

@@ -109,8 +109,19 @@ __device__ inline __amdgpu_buffer_rsrc_t slice_words(const uint32_t *first, uint
   return make_rsrc(first, w * 256u);
 }
 
+// POL = 0 (default policy) instead serves a matrix applied many times in a
+// row (cache_hint PKSELL_CACHE_RESIDENT): one that fits in the 256 MB
+// last-level cache then stays there between products.
+template <int POL = kStreamPolicy>
 __device__ inline uint32_t stream_word(__amdgpu_buffer_rsrc_t rs, uint32_t lane, uint32_t j) {
-  return __builtin_amdgcn_raw_buffer_load_b32(rs, (lane + j * kWave) * 4u, 0, kStreamPolicy);
+  return __builtin_amdgcn_raw_buffer_load_b32(rs, (lane + j * kWave) * 4u, 0, POL);
+}
+
+// The word-load policy of a product: streaming, or the default policy for
+// a matrix whose cache_hint is PKSELL_CACHE_RESIDENT.
+template <bool RES>
+constexpr int word_policy() {
+  return RES ? 0 : kStreamPolicy;
 }
 
 // One float32 result of a single-vector product, stored through a buffer
@@ -122,17 +133,17 @@ __device__ inline void store_result(float *y, uint32_t n, uint32_t row, float v)
                                         row * 4u, 0, kStreamPolicy);
 }
 
-// Element j of lane ``lane`` of a C = 64 slice of 4- or 8-byte elements
-// (the SELL comparators' columns and values), streamed the same way.
-template <typename T>
+// Element j of lane ``lane`` of a C = 64 slice of 2-, 4- or 8-byte
+// elements (the SELL comparators' columns and values), loaded the same way.
+template <typename T, int POL = kStreamPolicy>
 __device__ inline T stream_elem(__amdgpu_buffer_rsrc_t rs, uint32_t lane, uint32_t j) {
   const uint32_t off = (lane + j * kWave) * (uint32_t)sizeof(T);
   if constexpr (sizeof(T) == 2)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, kStreamPolicy));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, POL));
   else if constexpr (sizeof(T) == 4)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, kStreamPolicy));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, POL));
   else
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kStreamPolicy));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, POL));
 }
 
 // The PackSELL row loop (sec. 4.4) for one lane: walks the w words of its

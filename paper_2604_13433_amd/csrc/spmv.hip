@@ -33,12 +33,15 @@ struct SpmvArgs {
   RowGeo geo;
   Codec cd;
   int32_t group;  // two-slice kernels: words per group (host side only)
+  bool resident;  // k = 1, streamed words: cache_hint PKSELL_CACHE_RESIDENT (host side only)
 };
 
 // KB right-hand sides (columns r0 .. r0+KB-1 of the row-major x / y blocks;
 // K1: k == 1, so the x offset is a shift; V4: k and r0 are multiples of 4,
-// so x is gathered and y stored four columns at a time).
-template <int FMT, bool CWAVE, int KB, bool K1, bool V4 = false, bool BUF = false>
+// so x is gathered and y stored four columns at a time; RES: streamed words
+// loaded with the default policy, for cache_hint RESIDENT).
+template <int FMT, bool CWAVE, int KB, bool K1, bool V4 = false, bool BUF = false,
+          bool RES = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
   Lane ln;
   if (!lane_slice<CWAVE>(a.offset, a.n_slices, a.geo, ln)) return;
@@ -60,7 +63,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
   } else if constexpr (BUF) {  // C = 64: streamed words (slice start is wave-uniform)
     static_assert(CWAVE, "streamed words need C = 64");
     const __amdgpu_buffer_rsrc_t rs = slice_words(a.pack + ln.s, ln.w);
-    packsell_row_f<FMT, KB>([&](uint32_t j) { return stream_word(rs, ln.l, j); }, ln.w,
+    packsell_row_f<FMT, KB>(
+        [&](uint32_t j) { return stream_word<word_policy<RES>()>(rs, ln.l, j); }, ln.w,
                             left_offset32(t, a.geo), a.cd,
                             [&](uint32_t c, int r, bool live) {
                               const uint32_t xo = K1 ? (c << 2) : (c * kx + x0 + 4u * r);
@@ -143,7 +147,8 @@ constexpr int kPairBlock = 128;
 // G words per group and slice: the host sizes it to the matrix's slice
 // width (every word of a group issues a load and a gather, padding or not,
 // each a full 64-lane instruction).
-template <int FMT, bool BUF, bool IMPL, int G = kUnroll>
+// RES: words loaded with the default policy (cache_hint RESIDENT).
+template <int FMT, bool BUF, bool IMPL, int G = kUnroll, bool RES = false>
 __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
   constexpr int S = 2;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
       for (int q = 0; q < G; ++q) {
         uint32_t wd = 0u;  // past the slice's width: a padding word
         if (BUF)
-          wd = stream_word(rs[i], lane, j + q);
+          wd = stream_word<word_policy<RES>()>(rs[i], lane, j + q);
         else if (j + q < w[i])
           wd = __builtin_nontemporal_load(a.pack + off[i] + lane + (j + q) * kWave);
         p[i][q] = wd;
@@ -363,13 +368,15 @@ __device__ inline double fma_t(double a, double b, double c) { return fma(a, b, 
 // comparator, with the same lane mapping and batched loads as the PackSELL
 // kernel.  Values are VT (T, or half with T = float), vectors and sums T.
 // BUF (C = 64 and arrays below 4 GiB): columns and values are streamed
-// through per-slice buffer resources, as the PackSELL words are.
-template <typename T, bool CWAVE, bool BUF = false, typename VT = T, int G = kUnroll>
+// through per-slice buffer resources, as the PackSELL words are (RES: with
+// the default policy, for cache_hint RESIDENT).
+template <typename T, bool CWAVE, bool BUF = false, typename VT = T, int G = kUnroll,
+          bool RES = false>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict__ offset,
                                                       const int32_t *__restrict__ scol,
                                                       const VT *__restrict__ sval, const void *perm,
                                                       int32_t perm_bytes, const T *__restrict__ x,
-                                                      T *__restrict__ y, uint32_t n,
+                                                      T *__restrict__ y, uint32_t n, uint32_t m,
                                                       uint32_t n_slices, int32_t C, RowGeo g) {
   Lane ln;
   if (!lane_slice<CWAVE>(offset, n_slices, g, ln)) return;
@@ -377,13 +384,43 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
   const RowOut dst = row_out(perm, perm_bytes, t, n, g);
   const uint32_t stride = CWAVE ? (uint32_t)kWave : (uint32_t)C;
   T acc = 0;
+  if constexpr (BUF) {
+    // Branch-free, as the two-slice kernel: slots past the slice's width
+    // read 0 from its resources (no request), their gathers point past x
+    // (0, no request) and their products add 0 exactly, so each gather
+    // goes out as soon as its slot has arrived.
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(scol + ln.s, kPairedVT<VT> ? 0u : w * 256u);
+    const __amdgpu_buffer_rsrc_t rv = make_rsrc(sval + ln.s, w * kWave * (uint32_t)sizeof(VT));
+    const __amdgpu_buffer_rsrc_t rx = make_rsrc(x, m * (uint32_t)sizeof(T));
+    const uint32_t oob = m * (uint32_t)sizeof(T);
+    constexpr int P = word_policy<RES>();
+    for (uint32_t j = 0; j < w; j += G) {
+      T vv[G], xv[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        int32_t cc;
+        if constexpr (kPairedVT<VT>) {  // one 8-byte load per slot
+          const uint64_t u = stream_elem<uint64_t, P>(rv, ln.l, j + q);
+          cc = (int32_t)(uint32_t)u;
+          vv[q] = __uint_as_float((uint32_t)(u >> 32));
+        } else {
+          cc = stream_elem<int32_t, P>(rc, ln.l, j + q);
+          vv[q] = (T)stream_elem<VT, P>(rv, ln.l, j + q);
+        }
+        const uint32_t o = j + q < w ? (uint32_t)cc * (uint32_t)sizeof(T) : oob;
+        if constexpr (sizeof(T) == 8)
+          xv[q] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rx, o, 0, 0));
+        else
+          xv[q] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rx, o, 0, 0));
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) acc = fma_t(vv[q], xv[q], acc);
+    }
+    if (t < n) y[dst.row()] = acc;
+    return;
+  }
   const int32_t *pc = kPairedVT<VT> ? nullptr : scol + ln.s + ln.l;
   const VT *pv = sval + ln.s + ln.l;
-  // (BUF implies C = 64, where ln.s is wave-uniform)
-  const __amdgpu_buffer_rsrc_t rc =
-      BUF && !kPairedVT<VT> ? make_rsrc(scol + ln.s, w * 256u) : make_rsrc(scol, 0u);
-  const __amdgpu_buffer_rsrc_t rv =
-      BUF ? make_rsrc(sval + ln.s, w * kWave * (uint32_t)sizeof(VT)) : make_rsrc(sval, 0u);
   for (uint32_t j = 0; j < w; j += G) {
     int32_t cc[G];
     T vv[G];
@@ -392,14 +429,9 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
       const bool in = j + q < w;
       if constexpr (kPairedVT<VT>) {  // one 8-byte load per slot
         uint64_t u = 0;
-        if (in)
-          u = BUF ? stream_elem<uint64_t>(rv, ln.l, j + q)
-                  : __builtin_nontemporal_load(&pv[(j + q) * stride].u);
+        if (in) u = __builtin_nontemporal_load(&pv[(j + q) * stride].u);
         cc[q] = (int32_t)(uint32_t)u;
         vv[q] = __uint_as_float((uint32_t)(u >> 32));
-      } else if constexpr (BUF) {
-        cc[q] = in ? stream_elem<int32_t>(rc, ln.l, j + q) : 0;
-        vv[q] = in ? (T)stream_elem<VT>(rv, ln.l, j + q) : T(0);
       } else {
         cc[q] = in ? __builtin_nontemporal_load(pc + (j + q) * stride) : 0;
         vv[q] = in ? (T)__builtin_nontemporal_load(pv + (j + q) * stride) : T(0);
@@ -415,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(const int64_t *__restrict_
 
 // SELL with C = 64 and streamed slots, two slices per wave in 128-thread
 // workgroups: the comparator gets the same structure as k_spmv_pair.
-template <typename T, bool IMPL, typename VT = T, int G = kUnroll>
+template <typename T, bool IMPL, typename VT = T, int G = kUnroll, bool RES = false>
 __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restrict__ offset,
                                                          const int32_t *__restrict__ scol,
                                                          const VT *__restrict__ sval,
@@ -465,12 +497,12 @@ __global__ __launch_bounds__(kPairBlock) void k_sell_pair(const int64_t *__restr
       for (int q = 0; q < G; ++q) {
         int32_t cc;
         if constexpr (kPairedVT<VT>) {  // one 8-byte load per slot
-          const uint64_t u = stream_elem<uint64_t>(rv[i], lane, j + q);
+          const uint64_t u = stream_elem<uint64_t, word_policy<RES>()>(rv[i], lane, j + q);
           cc = (int32_t)(uint32_t)u;
           vv[i][q] = __uint_as_float((uint32_t)(u >> 32));
         } else {
-          cc = stream_elem<int32_t>(rc[i], lane, j + q);
-          vv[i][q] = (T)stream_elem<VT>(rv[i], lane, j + q);
+          cc = stream_elem<int32_t, word_policy<RES>()>(rc[i], lane, j + q);
+          vv[i][q] = (T)stream_elem<VT, word_policy<RES>()>(rv[i], lane, j + q);
         }
         const uint32_t o = j + q < w[i] ? (uint32_t)cc * 4u : oob;
         xv[i][q] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rx, o, 0, 0));
@@ -631,6 +663,7 @@ SpmvArgs make_args(const pksell_matrix *A, const float *x, float *y, int64_t k) 
   a.r0 = 0;
   a.cd = make_codec(A->D);
   a.group = pair_group(A->n_words, A->n_slices);
+  a.resident = A->cache_hint == PKSELL_CACHE_RESIDENT;
   return a;
 }
 
@@ -676,17 +709,25 @@ inline int slice_group(int64_t words, int64_t n_slices) {
     default: { constexpr int GG = 8; __VA_ARGS__; } break; \
   }
 
+template <int FMT, bool IMPL, bool RES>
+void launch_pair_res(const SpmvArgs &a, int G, int64_t pg, hipStream_t st) {
+  switch (G) {
+    case 2: k_spmv_pair<FMT, true, IMPL, 2, RES><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 3: k_spmv_pair<FMT, true, IMPL, 3, RES><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 4: k_spmv_pair<FMT, true, IMPL, 4, RES><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 5: k_spmv_pair<FMT, true, IMPL, 5, RES><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 6: k_spmv_pair<FMT, true, IMPL, 6, RES><<<pg, kPairBlock, 0, st>>>(a); break;
+    case 7: k_spmv_pair<FMT, true, IMPL, 7, RES><<<pg, kPairBlock, 0, st>>>(a); break;
+    default: k_spmv_pair<FMT, true, IMPL, 8, RES><<<pg, kPairBlock, 0, st>>>(a); break;
+  }
+}
+
 template <int FMT, bool IMPL>
 void launch_pair(const SpmvArgs &a, int G, int64_t pg, hipStream_t st) {
-  switch (G) {
-    case 2: k_spmv_pair<FMT, true, IMPL, 2><<<pg, kPairBlock, 0, st>>>(a); break;
-    case 3: k_spmv_pair<FMT, true, IMPL, 3><<<pg, kPairBlock, 0, st>>>(a); break;
-    case 4: k_spmv_pair<FMT, true, IMPL, 4><<<pg, kPairBlock, 0, st>>>(a); break;
-    case 5: k_spmv_pair<FMT, true, IMPL, 5><<<pg, kPairBlock, 0, st>>>(a); break;
-    case 6: k_spmv_pair<FMT, true, IMPL, 6><<<pg, kPairBlock, 0, st>>>(a); break;
-    case 7: k_spmv_pair<FMT, true, IMPL, 7><<<pg, kPairBlock, 0, st>>>(a); break;
-    default: k_spmv_pair<FMT, true, IMPL, 8><<<pg, kPairBlock, 0, st>>>(a); break;
-  }
+  if (a.resident)
+    launch_pair_res<FMT, IMPL, true>(a, G, pg, st);
+  else
+    launch_pair_res<FMT, IMPL, false>(a, G, pg, st);
 }
 
 template <int FMT, bool CW>
@@ -695,7 +736,9 @@ int launch_fmt_cw(const SpmvArgs &base, int64_t grid, int64_t k, bool buf, bool 
   if (k == 1) {
     if constexpr (CW) {
       if (!pair) {
-        if (buf)
+        if (buf && base.resident)
+          k_spmv<FMT, CW, 1, true, false, true, true><<<grid, kBlock, 0, st>>>(base);
+        else if (buf)
           k_spmv<FMT, CW, 1, true, false, true><<<grid, kBlock, 0, st>>>(base);
         else
           k_spmv<FMT, CW, 1, true><<<grid, kBlock, 0, st>>>(base);
@@ -809,10 +852,12 @@ void launch_sell_pair(const pksell_sell *S, const void *x, void *y, const void *
   float *yf = static_cast<float *>(y);
   const RowGeo g = make_geo(S->sigma, 0, S->C);
   const uint32_t n = (uint32_t)S->n, ns = (uint32_t)S->n_slices;
-#define PKS_SP(GG)                                                                       \
-  k_sell_pair<float, IMPL, VT, GG><<<pg, kPairBlock, 0, st>>>(S->offset, S->col, val, perm, \
-                                                              S->perm_bytes, xf, yf, n,     \
-                                                              (uint32_t)S->m, ns, g)
+  const bool res = S->cache_hint == PKSELL_CACHE_RESIDENT;
+#define PKS_SP1(GG, RES)                                                                       \
+  k_sell_pair<float, IMPL, VT, GG, RES><<<pg, kPairBlock, 0, st>>>(S->offset, S->col, val, perm, \
+                                                                   S->perm_bytes, xf, yf, n,     \
+                                                                   (uint32_t)S->m, ns, g)
+#define PKS_SP(GG) (res ? PKS_SP1(GG, true) : PKS_SP1(GG, false))
   switch (G) {
     case 2: PKS_SP(2); break;
     case 3: PKS_SP(3); break;
@@ -823,6 +868,7 @@ void launch_sell_pair(const pksell_sell *S, const void *x, void *y, const void *
     default: PKS_SP(8); break;
   }
 #undef PKS_SP
+#undef PKS_SP1
 }
 
 // 16-bit words (spmv16.hip).
@@ -996,12 +1042,15 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
   }
   PKS_CHECK(x, PKSELL_EINVAL, "null x");
   const int64_t grid = cdiv(S->n_slices * S->C, kBlock);
-#define PKS_SELL(T, CW, BF, VT)                                                             \
-  k_sell_spmv<T, CW, BF, VT><<<grid, kBlock, 0, st>>>(                                       \
+#define PKS_SELL_R(T, CW, BF, VT, RES)                                                      \
+  k_sell_spmv<T, CW, BF, VT, kUnroll, RES><<<grid, kBlock, 0, st>>>(                         \
       S->offset, S->col, static_cast<const VT *>(S->val), perm, S->perm_bytes,               \
-      static_cast<const T *>(x), static_cast<T *>(y), (uint32_t)S->n, (uint32_t)S->n_slices, \
-      S->C, make_geo(S->sigma, 0, S->C))
-  const bool buf = S->C == kWave && S->n_slots < (int64_t(1) << 29);
+      static_cast<const T *>(x), static_cast<T *>(y), (uint32_t)S->n, (uint32_t)S->m,        \
+      (uint32_t)S->n_slices, S->C, make_geo(S->sigma, 0, S->C))
+#define PKS_SELL(T, CW, BF, VT) PKS_SELL_R(T, CW, BF, VT, false)
+  const bool res = S->cache_hint == PKSELL_CACHE_RESIDENT;
+  // streamed slots and range-checked gathers: 32-bit byte offsets
+  const bool buf = S->C == kWave && S->n_slots < (int64_t(1) << 29) && S->m < (int64_t(1) << 29);
   // two slices per wave for narrow float32-vector slices (float64 ran
   // slower paired)
   if (buf && S->dtype != PKSELL_F64 && pair_slices(S->n_slots, S->n_slices)) {
@@ -1018,15 +1067,18 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
       else launch_sell_pair<false, float>(S, x, y, perm, G, pg, st);
     }
   } else if (S->dtype == PKSELL_F32_PAIRED) {
-    if (buf) PKS_SELL(float, true, true, Paired);
+    if (buf && res) PKS_SELL_R(float, true, true, Paired, true);
+    else if (buf) PKS_SELL(float, true, true, Paired);
     else if (S->C == kWave) PKS_SELL(float, true, false, Paired);
     else PKS_SELL(float, false, false, Paired);
   } else if (S->dtype == PKSELL_F16) {
-    if (buf) PKS_SELL(float, true, true, _Float16);
+    if (buf && res) PKS_SELL_R(float, true, true, _Float16, true);
+    else if (buf) PKS_SELL(float, true, true, _Float16);
     else if (S->C == kWave) PKS_SELL(float, true, false, _Float16);
     else PKS_SELL(float, false, false, _Float16);
   } else if (S->dtype == PKSELL_F32) {
-    if (buf) PKS_SELL(float, true, true, float);
+    if (buf && res) PKS_SELL_R(float, true, true, float, true);
+    else if (buf) PKS_SELL(float, true, true, float);
     else if (S->C == kWave) PKS_SELL(float, true, false, float);
     else PKS_SELL(float, false, false, float);
   } else {
@@ -1035,11 +1087,12 @@ int pksell_sell_spmv(const pksell_sell *S, const void *x, void *y, void *stream)
                 k_sell_spmv<double, true, true, double, GG><<<grid, kBlock, 0, st>>>(
                     S->offset, S->col, static_cast<const double *>(S->val), perm, S->perm_bytes,
                     static_cast<const double *>(x), static_cast<double *>(y), (uint32_t)S->n,
-                    (uint32_t)S->n_slices, S->C, make_geo(S->sigma, 0, S->C)));
+                    (uint32_t)S->m, (uint32_t)S->n_slices, S->C, make_geo(S->sigma, 0, S->C)));
     } else if (S->C == kWave) PKS_SELL(double, true, false, double);
     else PKS_SELL(double, false, false, double);
   }
 #undef PKS_SELL
+#undef PKS_SELL_R
   PKS_LAUNCHED();
   return PKSELL_OK;
 }

@@ -103,6 +103,15 @@ def test_solves_repeat_bit_for_bit():
     y1, _ = B.f3r(A1, bd, tol=1e-10)
     y2, _ = B.f3r(A1, bd, tol=1e-10)
     assert torch.equal(y1, y2)
+    # inner operators loaded with the resident cache policy: the same solve
+    A3.cache_hint = B.CACHE_RESIDENT
+    x3, _ = B.f3r(A1, bd, A2, A3, tol=1e-10)
+    assert torch.equal(x1, x3)
+    S3 = sell(a, torch.float16)
+    z1, _ = B.f3r(A1, bd, A2, S3, tol=1e-10)
+    S3.cache_hint = B.CACHE_RESIDENT
+    z2, _ = B.f3r(A1, bd, A2, S3, tol=1e-10)
+    assert torch.equal(z1, z2)
 
 
 def test_restart_cycles_follow_the_oracle():

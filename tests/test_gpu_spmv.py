@@ -398,3 +398,32 @@ def test_sell_paired_slots_equal_plain_sell(C):
                 vals = sell_values(a.val, torch.float32)
                 ref = L.spmv(a.rowptr, a.col, vals, x.cpu().numpy())
                 assert normalised_error(yp.cpu().numpy(), ref, a, vals, x.cpu().numpy()) <= SPMV_TOL
+
+
+@pytest.mark.parametrize("stencil", ["laplace7_48", "stencil27_24"])
+def test_cache_hint_resident_same_results(stencil):
+    """cache_hint RESIDENT changes only the load policy of the single-vector
+    products: the 7-point matrix runs the two-slice kernels, the 27-point
+    one the one-slice-per-wave kernels.  PackSELL (FP16, E8M13, FIX; both
+    row orders) and SELL (float32, paired, half values) products equal the
+    streaming ones bit for bit, and the oracle's within the bar."""
+    a = W.m2_laplace3d(48) if stencil == "laplace7_48" else W.m4_stencil27(24, seed=3)
+    x = W.uniform_vector(a.m, 5)
+    xt = torch.from_numpy(x).to(DEV)
+    for fmt, D in (("fp16", 15), ("e8my", 9), ("fix", 15)):
+        for mode in (B.IMPLICIT, B.EXPLICIT):
+            A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 256, mode, DEV)
+            assert A.cache_hint == B.CACHE_STREAM
+            y0 = B.spmv(A, xt)
+            A.cache_hint = B.CACHE_RESIDENT
+            y1 = B.spmv(A, xt)
+            assert torch.equal(y0, y1), (fmt, mode)
+            if mode == B.IMPLICIT:
+                ref, q = oracle_product(a, FMTS[fmt], D, x)
+                assert normalised_error(y1.cpu().numpy(), ref, a, q, x) <= SPMV_TOL
+    for dt, paired in ((torch.float32, False), (torch.float32, True), (torch.float16, False)):
+        S = B.sell_encode(a.rowptr, a.col, a.val, a.n, a.m, dt, 64, 256, B.IMPLICIT, DEV,
+                          paired=paired)
+        y0 = B.sell_spmv(S, xt)
+        S.cache_hint = B.CACHE_RESIDENT
+        assert torch.equal(y0, B.sell_spmv(S, xt)), (dt, paired)
