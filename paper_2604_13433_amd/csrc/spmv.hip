@@ -183,12 +183,13 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
   __amdgpu_buffer_rsrc_t rs[S];
 #pragma unroll
   for (int i = 0; i < S; ++i) rs[i] = slice_words(a.pack + off[i], w[i]);
-  // One group of G words per slice: loads, columns, gathers.  Streamed loads
-  // need no branch (words past a slice's width read 0 from its resource,
-  // with no request), which lets each gather go out as soon as its word has
-  // arrived instead of after the whole group.
-  auto group = [&](uint32_t j, float (&v)[S][G], float (&xv)[S][G]) {
-    uint32_t p[S][G];
+  // Groups of G words per slice.  Streamed loads need no branch (words past
+  // a slice's width read 0 from its resource, with no request), which lets
+  // each gather go out as soon as its word has arrived instead of after the
+  // whole group.  With more than one group, the next group's words are
+  // requested before this group's gathers, so the word stream stays in
+  // flight while the wave waits on x.
+  auto load = [&](uint32_t j, uint32_t (&p)[S][G]) {
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
@@ -200,6 +201,8 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
           wd = __builtin_nontemporal_load(a.pack + off[i] + lane + (j + q) * kWave);
         p[i][q] = wd;
       }
+  };
+  auto gather = [&](const uint32_t (&p)[S][G], float (&v)[S][G], float (&xv)[S][G]) {
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
@@ -210,21 +213,44 @@ __global__ __launch_bounds__(kPairBlock) void k_spmv_pair(SpmvArgs a) {
         xv[i][q] = buffer_load_f32(rx, (p[i][q] & 1u) ? c[i] << 2 : a.m * 4u);
       }
   };
+  // (Groups of 7 or 8 words keep the plain order: the extra G words of
+  // registers would cost the one-group 128^3 product an occupancy step.)
+  constexpr bool kPipe = G <= 6;
+  uint32_t p[S][G];
   uint32_t j = 0;
-  for (; j + G < wm; j += G) {  // every group but the last
-    float v[S][G], xv[S][G];
-    group(j, v, xv);
+  if constexpr (kPipe) {
+    load(0, p);
+    for (; j + G < wm; j += G) {  // every group but the last
+      uint32_t pn[S][G];
+      load(j + G, pn);
+      float v[S][G], xv[S][G];
+      gather(p, v, xv);
 #pragma unroll
-    for (int i = 0; i < S; ++i)
+      for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int q = 0; q < G; ++q) acc[i] = fmaf(v[i][q], xv[i][q], acc[i]);
+        for (int q = 0; q < G; ++q) {
+          acc[i] = fmaf(v[i][q], xv[i][q], acc[i]);
+          p[i][q] = pn[i][q];
+        }
+    }
+  } else {
+    for (; j + G < wm; j += G) {  // every group but the last
+      float v[S][G], xv[S][G];
+      load(j, p);
+      gather(p, v, xv);
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int q = 0; q < G; ++q) acc[i] = fmaf(v[i][q], xv[i][q], acc[i]);
+    }
+    load(j, p);
   }
   // The last group: each slice's sum is finished and stored before the next
   // slice's products wait on its gathers, so the first store is already on
   // its way while those gathers are in flight (128^3 FP16 product: 14.9 ->
   // 13.7 us in a timing copy, with the branch-free loads above).
   float v[S][G], xv[S][G];
-  group(j, v, xv);
+  gather(p, v, xv);
   // Stores are not branched on: rows past n (phantom rows of the last
   // slice, slices past the end) go to row n, outside y's resource, and are
   // dropped; a branch would let the compiler sink this slice's whole group
