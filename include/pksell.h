@@ -478,7 +478,8 @@ typedef struct pksell_batch {
   int32_t group;            /* lanes per row: L = 2..16 (forward, vec4, k >= 8), else 1 */
   int32_t words_per_group;  /* k = 1 loop: words per group, from the batch's average
                                slice width (4..8) */
-  int32_t reserved;
+  int32_t pair_units;       /* k = 1 forward: slice pairs over all matrices, each one
+                               wave of the two-slice product (0: the pipelined loop) */
   void *items;
   void *unit_start;
 } pksell_batch;
@@ -493,10 +494,12 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
                       int32_t transpose, pksell_batch *plan, void *ws,
                       size_t ws_bytes, void *stream);
 
-/* Runs a plan: one persistent launch (lane groups, group > 1: every k in one
- * pass; otherwise one launch per pass of up to 32 right-hand sides)
- * (a transposed plan first zeroes its outputs with a kernel, then scatters
- * with float32 atomics).  Asynchronous, and safe to capture in a graph. */
+/* Runs a plan: k = 1 forward plans with pair_units > 0, one launch of the
+ * two-slice product over every slice pair of the batch; otherwise one
+ * persistent launch (lane groups, group > 1: every k in one pass; else one
+ * launch per pass of up to 32 right-hand sides) (a transposed plan first
+ * zeroes its outputs with a kernel, then scatters with float32 atomics).
+ * Asynchronous, and safe to capture in a graph. */
 int pksell_spmv_batched(const pksell_batch *plan, void *stream);
 
 /* ------------------------------------------------------------------------

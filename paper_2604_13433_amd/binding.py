@@ -61,7 +61,7 @@ class CBatchItem(ctypes.Structure):
 class CBatch(ctypes.Structure):
     _fields_ = [("count", i32), ("fmt", i32), ("k", i32), ("transpose", i32),
                 ("total_units", i64), ("units_per_wave", i32), ("waves", i32),
-                ("vec4", i32), ("group", i32), ("words_per_group", i32), ("reserved", i32),
+                ("vec4", i32), ("group", i32), ("words_per_group", i32), ("pair_units", i32),
                 ("items", vp), ("unit_start", vp)]
 
 

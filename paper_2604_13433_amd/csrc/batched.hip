@@ -12,12 +12,15 @@
 // or, for forward products with k a multiple of 4 and k >= 8, a 64 / L-row
 // part of a slice in lane groups of L lanes per row (all k in one pass).
 // The transposed product scatters with float32 atomics after zeroing its
-// outputs in a separate launch.  Launches read only the device table, so
-// they can be captured into a graph and replayed.
+// outputs in a separate launch.  Forward products with k = 1 instead run
+// the single-matrix two-slice kernel over the batch: one wave per pair of
+// consecutive slices of one matrix (pairs prefix-summed per matrix), on a
+// grid of all pairs.  Launches read only the device table, so they can be
+// captured into a graph and replayed.
 #include <algorithm>
 #include <vector>
 
-#include "rowdot.hpp"
+#include "pair.hpp"
 
 namespace pksell {
 
@@ -302,8 +305,63 @@ PipeKernel k_batched_pipe_for(int L, int G) {
   }
 }
 
-// Forward products with k = 1 or with lane groups run the pipelined loop;
-// transposed products and other k run k_batched in passes.
+// k = 1, forward: the two-slice product of the single-matrix kernels, one
+// wave per slice pair u (pair_start: pairs prefix-summed per matrix), on a
+// grid of every pair (workgroups remapped so each XCD walks one contiguous
+// range of pairs).  The matrix of a pair is found by a scalar binary search
+// of the prefix table.
+template <int FMT, int G>
+__global__ __launch_bounds__(kPairBlock) void k_batched_pair(const Item *__restrict__ items,
+                                                           const uint32_t *__restrict__ pair_start,
+                                                           uint32_t count, uint32_t total) {
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t u =
+      __builtin_amdgcn_readfirstlane(b * (kPairBlock / kWave) + threadIdx.x / kWave);
+  if (u >= total) return;
+  const uint32_t it = find_item(pair_start, count, u);
+  const Item &I = items[it];
+  SpmvArgs a;
+  a.pack = I.pack;
+  a.offset = I.offset;
+  a.perm = I.perm;
+  a.row_exp = I.row_exp;
+  a.x = I.in;
+  a.y = I.out;
+  a.n = I.n;
+  a.m = I.m;
+  a.n_slices = I.n_slices;
+  a.C = kWave;
+  a.perm_bytes = (int32_t)I.perm_bytes;
+  a.k = 1;
+  a.r0 = 0;
+  a.geo = I.geo;
+  a.cd = I.cd;
+  const uint32_t k0 = (u - pair_start[it]) * 2;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  if (I.perm != nullptr)
+    pair_product<FMT, true, true, G, false>(a, k0, lane);
+  else
+    pair_product<FMT, true, false, G, false>(a, k0, lane);
+}
+
+typedef void (*PairKernel)(const Item *, const uint32_t *, uint32_t, uint32_t);
+
+template <int FMT>
+PairKernel k_batched_pair_for(int G) {
+  switch (G) {
+    case 4: return k_batched_pair<FMT, 4>;
+    case 5: return k_batched_pair<FMT, 5>;
+    case 6: return k_batched_pair<FMT, 6>;
+    case 7: return k_batched_pair<FMT, 7>;
+    default: return k_batched_pair<FMT, 8>;
+  }
+}
+
+// Forward products with k = 1 run the two-slice kernel when the plan has
+// pairs (every matrix's words addressable through 32-bit byte offsets);
+// lane groups (and k = 1 without pairs) the pipelined loop; transposed
+// products and other k run k_batched in passes.
+bool uses_pairs(const pksell_batch &p) { return !p.transpose && p.k == 1 && p.pair_units > 0; }
 bool uses_pipe(const pksell_batch &p) { return !p.transpose && (p.k == 1 || p.group > 1); }
 
 // Workgroups of the batched kernel that fit on one CU at once.
@@ -342,7 +400,7 @@ int pksell_batch_plan_bytes(int32_t count, size_t *bytes) {
   PKS_CHECK(count >= 1 && bytes, PKSELL_EINVAL, "count must be >= 1");
   Carver cv(nullptr);
   cv.take<Item>((size_t)count);
-  cv.take<uint32_t>((size_t)count + 1);
+  cv.take<uint32_t>(2 * ((size_t)count + 1));  // unit prefix, then slice-pair prefix
   *bytes = cv.used;
   return PKSELL_OK;
 }
@@ -356,7 +414,9 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
   pksell_batch_plan_bytes(count, &need);
   PKS_CHECK(ws && ws_bytes >= need, PKSELL_EWORKSPACE, "plan workspace: need %zu bytes", need);
   std::vector<Item> host((size_t)count);
-  std::vector<uint32_t> start((size_t)count + 1, 0);
+  std::vector<uint32_t> start(2 * ((size_t)count + 1), 0);  // units, then slice pairs
+  uint32_t *pstart = start.data() + count + 1;
+  bool pairs_ok = true;  // every matrix's words addressable by 32-bit byte offsets
   int fmt = -1;
   // 16-byte gathers and stores need k % 4 == 0 and 16-byte aligned blocks;
   // forward products with k >= 8 then use lane groups of L lanes per row
@@ -398,14 +458,16 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
     const int64_t next = (int64_t)start[(size_t)i] + A->n_slices * L;
     PKS_CHECK(next < (int64_t(1) << 32), PKSELL_ERANGE, "too many work units");
     start[(size_t)i + 1] = (uint32_t)next;
+    pstart[i + 1] = pstart[i] + (uint32_t)cdiv(A->n_slices, 2);
+    pairs_ok &= A->n_words < (int64_t(1) << 30);
   }
   Carver cv(ws);
   Item *dev_items = cv.take<Item>((size_t)count);
-  uint32_t *dev_start = cv.take<uint32_t>((size_t)count + 1);
+  uint32_t *dev_start = cv.take<uint32_t>(2 * ((size_t)count + 1));
   hipStream_t st = as_stream(stream);
   PKS_HIP(hipMemcpyAsync(dev_items, host.data(), sizeof(Item) * (size_t)count,
                          hipMemcpyHostToDevice, st));
-  PKS_HIP(hipMemcpyAsync(dev_start, start.data(), sizeof(uint32_t) * ((size_t)count + 1),
+  PKS_HIP(hipMemcpyAsync(dev_start, start.data(), sizeof(uint32_t) * 2 * ((size_t)count + 1),
                          hipMemcpyHostToDevice, st));
   PKS_HIP(hipStreamSynchronize(st));
   int dev = 0, cus = 256;
@@ -431,6 +493,8 @@ int pksell_batch_plan(const pksell_batch_item *items, int32_t count, int64_t k,
   PKS_CHECK(plan->total_units + 4 * waves < (int64_t(1) << 32), PKSELL_ERANGE, "too many work units");
   plan->items = dev_items;
   plan->unit_start = dev_start;
+  // k = 1 forward: the two-slice kernel's work units (slice pairs)
+  plan->pair_units = (L == 1 && k == 1 && !transpose && pairs_ok) ? (int32_t)pstart[count] : 0;
   return PKSELL_OK;
 }
 
@@ -449,6 +513,19 @@ int pksell_spmv_batched(const pksell_batch *plan, void *stream) {
   const uint32_t cnt = (uint32_t)plan->count, tot = (uint32_t)plan->total_units;
   // 16-byte gathers and stores when every x / y row group is aligned
   const bool v4 = plan->vec4 && !plan->transpose;
+  if (uses_pairs(*plan)) {
+    const uint32_t pairs = (uint32_t)plan->pair_units;
+    const int64_t pg = cdiv(pairs, kPairBlock / kWave);
+    const uint32_t *pstart = start + plan->count + 1;
+    const int G = plan->words_per_group;
+    switch (plan->fmt) {
+      case PKSELL_FP16: k_batched_pair_for<PKSELL_FP16>(G)<<<pg, kPairBlock, 0, st>>>(items, pstart, cnt, pairs); break;
+      case PKSELL_E8MY: k_batched_pair_for<PKSELL_E8MY>(G)<<<pg, kPairBlock, 0, st>>>(items, pstart, cnt, pairs); break;
+      default: k_batched_pair_for<PKSELL_FIX>(G)<<<pg, kPairBlock, 0, st>>>(items, pstart, cnt, pairs); break;
+    }
+    PKS_LAUNCHED();
+    return PKSELL_OK;
+  }
   if (uses_pipe(*plan)) {
     PKS_CHECK(plan->group == 1 || (v4 && k >= 8 && plan->group == group_size(k)), PKSELL_EINVAL,
               "bad plan");

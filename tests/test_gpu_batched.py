@@ -108,3 +108,39 @@ def test_m5_full_size_k8():
         x = xs[i].cpu().numpy()
         ref, q = oracle_product(a, F.FMT_E8MY, 9, x)
         assert normalised_error(ys[i].cpu().numpy(), ref, a, q, x) <= SPMV_TOL
+
+
+def test_k1_two_slice_path_mixed_orders_and_empty():
+    """k = 1 forward plans run the two-slice kernel over slice pairs: FP16,
+    E8MY and FIX words, implicit and explicit row orders and an empty matrix
+    in one batch, each output equal to its single-matrix product bit for
+    bit; a transposed plan of the same batch keeps the persistent loop."""
+    mats = small_batch(7, 11)
+    mats.insert(3, W.csr_from_triplets(0, 0, [], [], []))
+    for fmt, D in [("fp16", 15), ("e8my", 9), ("fix", 15)]:
+        enc = [B.encode(a.rowptr, a.col, a.val, a.n, a.m, fmt, D, 64, 256,
+                        B.EXPLICIT if i % 2 else B.IMPLICIT, DEV) for i, a in enumerate(mats)]
+        xs = [torch.from_numpy(W.uniform_vector(a.m, 40 + i)).to(DEV) for i, a in enumerate(mats)]
+        ys = [torch.full((a.n,), float("nan"), device=DEV) for a in mats]
+        run = B.BatchedSpMV(enc, xs, ys)
+        assert run.plan.pair_units == sum((A.desc.n_slices + 1) // 2 for A in enc)
+        run()
+        for i, A in enumerate(enc):
+            assert torch.equal(ys[i], B.spmv(A, xs[i])), (fmt, i)
+        tr = B.BatchedSpMV(enc, [torch.ones(a.n, device=DEV) for a in mats],
+                           [torch.empty(a.m, device=DEV) for a in mats], transpose=True)
+        assert tr.plan.pair_units == 0
+
+
+def test_m5_full_size_k1():
+    """64 stencils at k = 1 (the two-slice path): every output equal to the
+    single-matrix product bit for bit, graph replay included."""
+    mats = W.m5_batch()
+    enc = encode_all(mats)
+    xs = [torch.from_numpy(W.uniform_vector(a.m, i)).to(DEV) for i, a in enumerate(mats)]
+    ys = [torch.empty(a.n, device=DEV) for a in mats]
+    run = B.BatchedSpMV(enc, xs, ys).capture()
+    run.replay()
+    torch.cuda.synchronize()
+    for i, A in enumerate(enc):
+        assert torch.equal(ys[i], B.spmv(A, xs[i])), i
