@@ -118,7 +118,7 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     p.add_argument("--no-extra", action="store_true",
                    help="skip the power-law and block-stencil legs")
-    p.add_argument("--leg", default="", choices=["", "powerlaw", "trsv", "f3r", "pcg"],
+    p.add_argument("--leg", default="", choices=["", "powerlaw", "trsv", "f3r", "pcg", "multirhs"],
                    help="run only this leg and print its JSON (for profiling one kernel)")
     p.add_argument("--calib-copy-mb", type=int, default=0,
                    help="first run one plain device copy of this many MiB (a known-size "
@@ -202,7 +202,7 @@ def main():
         del src, dst
     if args.leg:
         leg = {"powerlaw": powerlaw_leg, "trsv": trsv_leg, "f3r": f3r_leg,
-               "pcg": pcg_leg}[args.leg]
+               "pcg": pcg_leg, "multirhs": multirhs_only_leg}[args.leg]
         print(json.dumps({args.leg: leg(args, torch, B, W)}), flush=True)
         return
     g = args.grid
@@ -781,6 +781,14 @@ def multirhs_leg(args, a, A, torch, B, W):
         log(f"[bench] single-matrix k={k}: {res[f'k{k}']}")
         del reps, xs, ys
     return res
+
+
+def multirhs_only_leg(args, torch, B, W):
+    """The multi-RHS leg by itself, on the headline matrix (for profiling)."""
+    a = W.m2_laplace3d(args.grid)
+    A = B.encode(a.rowptr, a.col, a.val, a.n, a.m, "fp16", 15, 64, 256, B.EXPLICIT,
+                 torch.device("cuda:0"))
+    return multirhs_leg(args, a, A, torch, B, W)
 
 
 def batched_leg(args, torch, B, W):
