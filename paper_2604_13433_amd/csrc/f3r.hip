@@ -33,6 +33,7 @@ namespace {
 constexpr int kFB = 256;          // threads per block of the vector kernels
 constexpr uint32_t kFBlocks = 512;  // at most this many vector blocks
 constexpr int kDotChunk = 8;      // basis vectors per pass of the dot kernel
+constexpr int kRows = 4;          // rows per thread whose loads are in flight together
 constexpr int kMaxM = 200;        // longest FGMRES cycle
 
 // Small float64 state of one FGMRES layer: the Hessenberg matrix
@@ -63,11 +64,50 @@ __device__ inline double block_sum1(double v) {
   return s;
 }
 
+// block_sum1 of NV values at once (one exchange through LDS for all of
+// them); each sum in the same order as block_sum1's.
+template <int NV>
+__device__ inline void block_sum_n(double (&v)[NV]) {
+  __shared__ double sh[NV][kFB / kWave];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double t = wave_sum(v[q]);
+    if (lane == 0) sh[q][w] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+    for (int i = 0; i < kFB / kWave; ++i) s += sh[q][i];
+    v[q] = s;
+  }
+  __syncthreads();
+}
+
 // Sum of the nblk partials of slot q, the same order in every block.
 __device__ inline double sum_parts(const double *part, uint32_t nblk, int q) {
   double s = 0.0;
   for (uint32_t i = threadIdx.x; i < nblk; i += kFB) s += part[(size_t)q * nblk + i];
   return block_sum1(s);
+}
+
+// sum_parts of slots q0 .. q0 + kDotChunk - 1 (those below nv) into h, with
+// all their partials loaded at once; the same sums in the same order.
+__device__ inline void sum_parts_chunk(const double *part, uint32_t nblk, int q0, int nv,
+                                       double *h) {
+  double v[kDotChunk];
+#pragma unroll
+  for (int u = 0; u < kDotChunk; ++u) v[u] = 0.0;
+  for (uint32_t i = threadIdx.x; i < nblk; i += kFB)
+#pragma unroll
+    for (int u = 0; u < kDotChunk; ++u)
+      if (q0 + u < nv) v[u] += part[(size_t)(q0 + u) * nblk + i];
+  block_sum_n<kDotChunk>(v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int u = 0; u < kDotChunk; ++u)
+      if (q0 + u < nv) h[q0 + u] = v[u];
 }
 
 __device__ inline uint32_t rows_lo(uint32_t n) {
@@ -101,11 +141,11 @@ __global__ __launch_bounds__(kFB) void k_mdot(const T *__restrict__ V, int64_t l
       for (int u = 0; u < kDotChunk; ++u)
         if (q0 + u < nv) acc[u] += (double)V[(int64_t)(q0 + u) * ld + r] * wv;
     }
+    block_sum_n<kDotChunk>(acc);
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int u = 0; u < kDotChunk; ++u) {
-      const double s = block_sum1(acc[u]);
-      if (threadIdx.x == 0 && q0 + u < nv) part[(size_t)(q0 + u) * gridDim.x + blockIdx.x] = s;
-    }
+      for (int u = 0; u < kDotChunk; ++u)
+        if (q0 + u < nv) part[(size_t)(q0 + u) * gridDim.x + blockIdx.x] = acc[u];
   }
 }
 
@@ -146,6 +186,86 @@ __global__ __launch_bounds__(kFB) void k_maxpy(const T *__restrict__ V, int64_t 
   }
 }
 
+// k_mdot and k_maxpy for a basis of NC <= kDotChunk vectors, a count known
+// when the launch is recorded (the inner layers): the same sums in the same
+// order, with the loads of kRows rows of every vector in flight together
+// and no per-vector test.  Rows past the tile read its last row again and
+// add nothing.
+template <typename T, int NC>
+__global__ __launch_bounds__(kFB) void k_mdot_n(const T *__restrict__ V, int64_t ld,
+                                                 const T *__restrict__ w, uint32_t n,
+                                                 double *__restrict__ part) {
+  const uint32_t lo = rows_lo(n), hi = rows_hi(n);
+  double acc[NC];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) acc[u] = 0.0;
+  for (uint32_t r0 = lo + threadIdx.x; r0 < hi; r0 += kRows * kFB) {
+    T wv[kRows], vv[kRows][NC];
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      const uint32_t r = min(r0 + e * kFB, hi - 1);
+      wv[e] = w[r];
+#pragma unroll
+      for (int u = 0; u < NC; ++u) vv[e][u] = V[(int64_t)u * ld + r];
+    }
+#pragma unroll
+    for (int e = 0; e < kRows; ++e)
+      if (r0 + e * kFB < hi)
+#pragma unroll
+        for (int u = 0; u < NC; ++u) acc[u] += (double)vv[e][u] * (double)wv[e];
+  }
+  block_sum_n<NC>(acc);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int u = 0; u < NC; ++u) part[(size_t)u * gridDim.x + blockIdx.x] = acc[u];
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(kFB) void k_maxpy_n(const T *__restrict__ V, int64_t ld,
+                                                  const double *__restrict__ part,
+                                                  T *__restrict__ w, uint32_t n, Hess hs, int j,
+                                                  int accumulate, double *__restrict__ norm_part) {
+  __shared__ double h[kDotChunk];
+  sum_parts_chunk(part, gridDim.x, 0, NC, h);
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int q = 0; q < NC; ++q) {
+      double *hq = hs.H + (int64_t)j * hs.ld + q;
+      *hq = accumulate ? *hq + h[q] : h[q];
+    }
+  }
+  double hq[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) hq[q] = h[q];
+  const uint32_t lo = rows_lo(n), hi = rows_hi(n);
+  double nrm = 0.0;
+  for (uint32_t r0 = lo + threadIdx.x; r0 < hi; r0 += kRows * kFB) {
+    double sv[kRows];
+    T vv[kRows][NC];
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      const uint32_t r = min(r0 + e * kFB, hi - 1);
+      sv[e] = (double)w[r];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) vv[e][q] = V[(int64_t)q * ld + r];
+    }
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      if (r0 + e * kFB >= hi) continue;
+      double t = sv[e];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) t -= hq[q] * (double)vv[e][q];
+      const T tt = (T)t;
+      w[r0 + e * kFB] = tt;
+      nrm += (double)tt * (double)tt;
+    }
+  }
+  if (norm_part) {
+    nrm = block_sum1(nrm);
+    if (threadIdx.x == 0) norm_part[blockIdx.x] = nrm;
+  }
+}
+
 // dst = src / h with h = sqrt(sum of norm_part) (0 where h is 0).
 //  - start (j < 0): h is the right-hand side's norm beta: g = beta e1.
 //  - step j: h = H[j+1, j]; block 0 rotates column j by the previous
@@ -163,8 +283,15 @@ __global__ __launch_bounds__(kFB) void k_scale_rotate(const T *src, T *dst, int6
   const int j = jdev ? (j_fixed < 0 ? -1 : *jdev) : j_fixed;
   T *d = jdev && j >= 0 ? dst + (int64_t)(j + 1) * dst_ld : dst;
   const double inv = h > 0.0 ? 1.0 / h : 0.0;
-  for (uint32_t r = blockIdx.x * kFB + threadIdx.x; r < n; r += gridDim.x * kFB)
-    d[r] = (T)((double)src[r] * inv);
+  const uint32_t S = gridDim.x * kFB;
+  for (uint32_t r0 = blockIdx.x * kFB + threadIdx.x; r0 < n; r0 += kRows * S) {
+    T v[kRows];  // all loads first (src and d may be the same vector)
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) v[e] = r0 + e * S < n ? src[r0 + e * S] : T(0);
+#pragma unroll
+    for (int e = 0; e < kRows; ++e)
+      if (r0 + e * S < n) d[r0 + e * S] = (T)((double)v[e] * inv);
+  }
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   if (j < 0) {
     hs.g[0] = h;
@@ -237,10 +364,17 @@ __global__ __launch_bounds__(kFB) void k_load_rhs(const TS *src, int64_t ld, con
   const TS *s = jdev ? src + (int64_t)(*jdev) * ld : src;
   const uint32_t lo = rows_lo(n), hi = rows_hi(n);
   double nrm = 0.0;
-  for (uint32_t r = lo + threadIdx.x; r < hi; r += kFB) {
-    const TD t = (TD)s[r];
-    dst[r] = t;
-    nrm += (double)t * (double)t;
+  for (uint32_t r0 = lo + threadIdx.x; r0 < hi; r0 += kRows * kFB) {
+    TS v[kRows];
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) v[e] = r0 + e * kFB < hi ? s[r0 + e * kFB] : TS(0);
+#pragma unroll
+    for (int e = 0; e < kRows; ++e)
+      if (r0 + e * kFB < hi) {
+        const TD t = (TD)v[e];
+        dst[r0 + e * kFB] = t;
+        nrm += (double)t * (double)t;
+      }
   }
   nrm = block_sum1(nrm);
   if (threadIdx.x == 0) norm_part[blockIdx.x] = nrm;
@@ -251,10 +385,21 @@ __global__ __launch_bounds__(kFB) void k_residual(const double *__restrict__ b, 
                                                    uint32_t n, double *__restrict__ norm_part) {
   const uint32_t lo = rows_lo(n), hi = rows_hi(n);
   double nrm = 0.0;
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += kFB) {
-    const double v = b[i] - r[i];
-    r[i] = v;
-    nrm += v * v;
+  for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += kRows * kFB) {
+    double bv[kRows], rv[kRows];
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      const uint32_t i = i0 + e * kFB;
+      bv[e] = i < hi ? b[i] : 0.0;
+      rv[e] = i < hi ? r[i] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < kRows; ++e)
+      if (i0 + e * kFB < hi) {
+        const double v = bv[e] - rv[e];
+        r[i0 + e * kFB] = v;
+        nrm += v * v;
+      }
   }
   nrm = block_sum1(nrm);
   if (threadIdx.x == 0) norm_part[blockIdx.x] = nrm;
@@ -268,11 +413,25 @@ __global__ __launch_bounds__(kFB) void k_rich(const T *__restrict__ v, const T *
                                                T *__restrict__ z, uint32_t n, double omega,
                                                int mode) {
   const T w = (T)omega;
-  for (uint32_t r = blockIdx.x * kFB + threadIdx.x; r < n; r += gridDim.x * kFB) {
-    const T vr = v[r];
-    if (mode == 0) z[r] = w * vr;
-    else if (mode == 1) z[r] = w * vr + w * (vr - w * t[r]);
-    else z[r] = z[r] + w * (vr - t[r]);
+  const uint32_t S = gridDim.x * kFB;
+  for (uint32_t r0 = blockIdx.x * kFB + threadIdx.x; r0 < n; r0 += kRows * S) {
+    T vr[kRows], tr[kRows], zr[kRows];
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      const uint32_t r = r0 + e * S;
+      const bool in = r < n;
+      vr[e] = in ? v[r] : T(0);
+      tr[e] = in && mode != 0 ? t[r] : T(0);
+      zr[e] = in && mode == 2 ? z[r] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      const uint32_t r = r0 + e * S;
+      if (r >= n) continue;
+      if (mode == 0) z[r] = w * vr[e];
+      else if (mode == 1) z[r] = w * vr[e] + w * (vr[e] - w * tr[e]);
+      else z[r] = zr[e] + w * (vr[e] - tr[e]);
+    }
   }
 }
 
@@ -359,10 +518,25 @@ struct F3RSolve {
   template <typename TV>
   int orthogonalise(const TV *V, int j, const int32_t *jdev, TV *wv, Hess hs) {
     for (int pass = 0; pass < 2; ++pass) {
+      double *np = pass == 1 ? w.pn : nullptr;
+      if (jdev == nullptr && j + 1 <= kDotChunk) {  // basis size known now
+#define PKS_GS(NC)                                                                         \
+  case NC:                                                                                 \
+    k_mdot_n<TV, NC><<<nb, kFB, 0, s>>>(V, n, wv, n, w.pa);                                \
+    k_maxpy_n<TV, NC><<<nb, kFB, 0, s>>>(V, n, w.pa, wv, n, hs, j, pass, np);              \
+    break;
+        switch (j + 1) {
+          PKS_GS(1) PKS_GS(2) PKS_GS(3) PKS_GS(4) PKS_GS(5) PKS_GS(6) PKS_GS(7)
+          default: k_mdot_n<TV, 8><<<nb, kFB, 0, s>>>(V, n, wv, n, w.pa);
+                   k_maxpy_n<TV, 8><<<nb, kFB, 0, s>>>(V, n, w.pa, wv, n, hs, j, pass, np);
+        }
+#undef PKS_GS
+        PKS_LAUNCHED();
+        continue;
+      }
       k_mdot<TV><<<nb, kFB, 0, s>>>(V, n, j + 1, jdev, wv, n, w.pa);
       PKS_LAUNCHED();
-      k_maxpy<TV><<<nb, kFB, 0, s>>>(V, n, j + 1, jdev, w.pa, wv, n, hs, j, pass,
-                                     pass == 1 ? w.pn : nullptr);
+      k_maxpy<TV><<<nb, kFB, 0, s>>>(V, n, j + 1, jdev, w.pa, wv, n, hs, j, pass, np);
       PKS_LAUNCHED();
     }
     return PKSELL_OK;
