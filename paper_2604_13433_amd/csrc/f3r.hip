@@ -33,7 +33,12 @@ namespace {
 constexpr int kFB = 256;          // threads per block of the vector kernels
 constexpr uint32_t kFBlocks = 512;  // at most this many vector blocks
 constexpr int kDotChunk = 8;      // basis vectors per pass of the dot kernel
-constexpr int kRows = 4;          // rows per thread whose loads are in flight together
+// Rows per thread whose loads are in flight together: 8 for float32
+// vectors, 4 for float64 (registers).
+template <typename T>
+constexpr int rows_of() {
+  return sizeof(T) == 4 ? 8 : 4;
+}
 constexpr int kMaxM = 200;        // longest FGMRES cycle
 
 // Small float64 state of one FGMRES layer: the Hessenberg matrix
@@ -195,6 +200,7 @@ template <typename T, int NC>
 __global__ __launch_bounds__(kFB) void k_mdot_n(const T *__restrict__ V, int64_t ld,
                                                  const T *__restrict__ w, uint32_t n,
                                                  double *__restrict__ part) {
+  constexpr int kRows = rows_of<T>();
   const uint32_t lo = rows_lo(n), hi = rows_hi(n);
   double acc[NC];
 #pragma unroll
@@ -225,6 +231,7 @@ __global__ __launch_bounds__(kFB) void k_maxpy_n(const T *__restrict__ V, int64_
                                                   const double *__restrict__ part,
                                                   T *__restrict__ w, uint32_t n, Hess hs, int j,
                                                   int accumulate, double *__restrict__ norm_part) {
+  constexpr int kRows = rows_of<T>();
   __shared__ double h[kDotChunk];
   sum_parts_chunk(part, gridDim.x, 0, NC, h);
   __syncthreads();
@@ -279,6 +286,7 @@ __global__ __launch_bounds__(kFB) void k_scale_rotate(const T *src, T *dst, int6
                                                        const double *__restrict__ norm_part,
                                                        uint32_t nblk, Hess hs, int j_fixed,
                                                        Poll *poll) {
+  constexpr int kRows = rows_of<T>();
   const double h = sqrt(sum_parts(norm_part, nblk, 0));
   const int j = jdev ? (j_fixed < 0 ? -1 : *jdev) : j_fixed;
   T *d = jdev && j >= 0 ? dst + (int64_t)(j + 1) * dst_ld : dst;
@@ -361,6 +369,7 @@ template <typename TS, typename TD>
 __global__ __launch_bounds__(kFB) void k_load_rhs(const TS *src, int64_t ld, const int32_t *jdev,
                                                    TD *__restrict__ dst, uint32_t n,
                                                    double *__restrict__ norm_part) {
+  constexpr int kRows = rows_of<TS>();
   const TS *s = jdev ? src + (int64_t)(*jdev) * ld : src;
   const uint32_t lo = rows_lo(n), hi = rows_hi(n);
   double nrm = 0.0;
@@ -383,6 +392,7 @@ __global__ __launch_bounds__(kFB) void k_load_rhs(const TS *src, int64_t ld, con
 // r = b - Ax (Ax in r on entry) and the partials of ||r||^2.
 __global__ __launch_bounds__(kFB) void k_residual(const double *__restrict__ b, double *r,
                                                    uint32_t n, double *__restrict__ norm_part) {
+  constexpr int kRows = rows_of<double>();
   const uint32_t lo = rows_lo(n), hi = rows_hi(n);
   double nrm = 0.0;
   for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += kRows * kFB) {
@@ -412,6 +422,7 @@ template <typename T>
 __global__ __launch_bounds__(kFB) void k_rich(const T *__restrict__ v, const T *__restrict__ t,
                                                T *__restrict__ z, uint32_t n, double omega,
                                                int mode) {
+  constexpr int kRows = rows_of<T>();
   const T w = (T)omega;
   const uint32_t S = gridDim.x * kFB;
   for (uint32_t r0 = blockIdx.x * kFB + threadIdx.x; r0 < n; r0 += kRows * S) {
