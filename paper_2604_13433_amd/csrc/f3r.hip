@@ -134,17 +134,32 @@ template <typename T>
 __global__ __launch_bounds__(kFB) void k_mdot(const T *__restrict__ V, int64_t ld, int nv_fixed,
                                                const int32_t *jdev, const T *__restrict__ w,
                                                uint32_t n, double *__restrict__ part) {
+  constexpr int kRows = rows_of<T>();
   const int nv = count_of(nv_fixed, jdev, 1);
   const uint32_t lo = rows_lo(n), hi = rows_hi(n);
   for (int q0 = 0; q0 < nv; q0 += kDotChunk) {
     double acc[kDotChunk];
 #pragma unroll
     for (int u = 0; u < kDotChunk; ++u) acc[u] = 0.0;
-    for (uint32_t r = lo + threadIdx.x; r < hi; r += kFB) {
-      const double wv = (double)w[r];
+    // kRows rows per thread in flight; each sum still runs over the rows in
+    // order
+    for (uint32_t r0 = lo + threadIdx.x; r0 < hi; r0 += kRows * kFB) {
+      T wv[kRows], vv[kRows][kDotChunk];
 #pragma unroll
-      for (int u = 0; u < kDotChunk; ++u)
-        if (q0 + u < nv) acc[u] += (double)V[(int64_t)(q0 + u) * ld + r] * wv;
+      for (int e = 0; e < kRows; ++e) {
+        const uint32_t r = r0 + e * kFB;
+        const bool in = r < hi;
+        wv[e] = in ? w[r] : T(0);
+#pragma unroll
+        for (int u = 0; u < kDotChunk; ++u)
+          vv[e][u] = in && q0 + u < nv ? V[(int64_t)(q0 + u) * ld + r] : T(0);
+      }
+#pragma unroll
+      for (int e = 0; e < kRows; ++e)
+        if (r0 + e * kFB < hi)
+#pragma unroll
+          for (int u = 0; u < kDotChunk; ++u)
+            if (q0 + u < nv) acc[u] += (double)vv[e][u] * (double)wv[e];
     }
     block_sum_n<kDotChunk>(acc);
     if (threadIdx.x == 0)
@@ -162,13 +177,11 @@ __global__ __launch_bounds__(kFB) void k_maxpy(const T *__restrict__ V, int64_t 
                                                 const int32_t *jdev, const double *__restrict__ part,
                                                 T *__restrict__ w, uint32_t n, Hess hs, int j_fixed,
                                                 int accumulate, double *__restrict__ norm_part) {
+  constexpr int kRows = rows_of<T>();
   __shared__ double h[kMaxM + 1];
   const int nv = count_of(nv_fixed, jdev, 1);
   const int j = count_of(j_fixed, jdev, 0);
-  for (int q = 0; q < nv; ++q) {
-    const double s = sum_parts(part, gridDim.x, q);
-    if (threadIdx.x == 0) h[q] = s;
-  }
+  for (int q0 = 0; q0 < nv; q0 += kDotChunk) sum_parts_chunk(part, gridDim.x, q0, nv, h);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     for (int q = 0; q < nv; ++q) {
@@ -178,12 +191,32 @@ __global__ __launch_bounds__(kFB) void k_maxpy(const T *__restrict__ V, int64_t 
   }
   const uint32_t lo = rows_lo(n), hi = rows_hi(n);
   double nrm = 0.0;
-  for (uint32_t r = lo + threadIdx.x; r < hi; r += kFB) {
-    double s = (double)w[r];
-    for (int q = 0; q < nv; ++q) s -= h[q] * (double)V[(int64_t)q * ld + r];
-    const T t = (T)s;
-    w[r] = t;
-    nrm += (double)t * (double)t;
+  for (uint32_t r0 = lo + threadIdx.x; r0 < hi; r0 += kRows * kFB) {
+    double s[kRows];
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      const uint32_t r = r0 + e * kFB;
+      s[e] = r < hi ? (double)w[r] : 0.0;
+    }
+    for (int q = 0; q < nv; ++q) {
+      T vq[kRows];
+#pragma unroll
+      for (int e = 0; e < kRows; ++e) {
+        const uint32_t r = r0 + e * kFB;
+        vq[e] = r < hi ? V[(int64_t)q * ld + r] : T(0);
+      }
+#pragma unroll
+      for (int e = 0; e < kRows; ++e) s[e] -= h[q] * (double)vq[e];
+    }
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      const uint32_t r = r0 + e * kFB;
+      if (r < hi) {
+        const T t = (T)s[e];
+        w[r] = t;
+        nrm += (double)t * (double)t;
+      }
+    }
   }
   if (norm_part) {
     nrm = block_sum1(nrm);
