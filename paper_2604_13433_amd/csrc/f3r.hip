@@ -91,9 +91,17 @@ __device__ inline void block_sum_n(double (&v)[NV]) {
 }
 
 // Sum of the nblk partials of slot q, the same order in every block.
+// (Each thread adds its partials t, t + kFB, t + 2 kFB, ... in that order,
+// two requested at once: a grid of kFBlocks blocks is one round trip.)
 __device__ inline double sum_parts(const double *part, uint32_t nblk, int q) {
+  const double *pq = part + (size_t)q * nblk;
   double s = 0.0;
-  for (uint32_t i = threadIdx.x; i < nblk; i += kFB) s += part[(size_t)q * nblk + i];
+  for (uint32_t i = threadIdx.x; i < nblk; i += 2 * kFB) {
+    const bool two = i + kFB < nblk;
+    const double a = pq[i], b = two ? pq[i + kFB] : 0.0;
+    s += a;
+    if (two) s += b;
+  }
   return block_sum1(s);
 }
 
@@ -104,10 +112,22 @@ __device__ inline void sum_parts_chunk(const double *part, uint32_t nblk, int q0
   double v[kDotChunk];
 #pragma unroll
   for (int u = 0; u < kDotChunk; ++u) v[u] = 0.0;
-  for (uint32_t i = threadIdx.x; i < nblk; i += kFB)
+  for (uint32_t i = threadIdx.x; i < nblk; i += 2 * kFB) {
+    const bool two = i + kFB < nblk;
+    double a[2][kDotChunk];
+#pragma unroll
+    for (int u = 0; u < kDotChunk; ++u) {
+      const double *pu = part + (size_t)(q0 + u) * nblk;
+      a[0][u] = q0 + u < nv ? pu[i] : 0.0;
+      a[1][u] = q0 + u < nv && two ? pu[i + kFB] : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < kDotChunk; ++u)
-      if (q0 + u < nv) v[u] += part[(size_t)(q0 + u) * nblk + i];
+      if (q0 + u < nv) {
+        v[u] += a[0][u];
+        if (two) v[u] += a[1][u];
+      }
+  }
   block_sum_n<kDotChunk>(v);
   if (threadIdx.x == 0)
 #pragma unroll
@@ -266,6 +286,20 @@ __global__ __launch_bounds__(kFB) void k_maxpy_n(const T *__restrict__ V, int64_
                                                   int accumulate, double *__restrict__ norm_part) {
   constexpr int kRows = rows_of<T>();
   __shared__ double h[kDotChunk];
+  const uint32_t lo = rows_lo(n), hi = rows_hi(n), first = lo + threadIdx.x;
+  T sv[kRows], vv[kRows][NC];
+  auto load = [&](uint32_t r0) {  // r0 < hi
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      const uint32_t r = min(r0 + e * kFB, hi - 1);
+      sv[e] = w[r];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) vv[e][q] = V[(int64_t)q * ld + r];
+    }
+  };
+  // the first batch is requested before the dot products' partials are
+  // summed, so the two memory round trips overlap
+  if (first < hi) load(first);
   sum_parts_chunk(part, gridDim.x, 0, NC, h);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -277,22 +311,13 @@ __global__ __launch_bounds__(kFB) void k_maxpy_n(const T *__restrict__ V, int64_
   double hq[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) hq[q] = h[q];
-  const uint32_t lo = rows_lo(n), hi = rows_hi(n);
   double nrm = 0.0;
-  for (uint32_t r0 = lo + threadIdx.x; r0 < hi; r0 += kRows * kFB) {
-    double sv[kRows];
-    T vv[kRows][NC];
-#pragma unroll
-    for (int e = 0; e < kRows; ++e) {
-      const uint32_t r = min(r0 + e * kFB, hi - 1);
-      sv[e] = (double)w[r];
-#pragma unroll
-      for (int q = 0; q < NC; ++q) vv[e][q] = V[(int64_t)q * ld + r];
-    }
+  for (uint32_t r0 = first; r0 < hi; r0 += kRows * kFB) {
+    if (r0 != first) load(r0);
 #pragma unroll
     for (int e = 0; e < kRows; ++e) {
       if (r0 + e * kFB >= hi) continue;
-      double t = sv[e];
+      double t = (double)sv[e];
 #pragma unroll
       for (int q = 0; q < NC; ++q) t -= hq[q] * (double)vv[e][q];
       const T tt = (T)t;
@@ -320,15 +345,21 @@ __global__ __launch_bounds__(kFB) void k_scale_rotate(const T *src, T *dst, int6
                                                        uint32_t nblk, Hess hs, int j_fixed,
                                                        Poll *poll) {
   constexpr int kRows = rows_of<T>();
+  const uint32_t S = gridDim.x * kFB, first = blockIdx.x * kFB + threadIdx.x;
+  T v[kRows];  // all loads of a batch first (src and d may be the same vector)
+  auto load = [&](uint32_t r0) {
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) v[e] = r0 + e * S < n ? src[r0 + e * S] : T(0);
+  };
+  // the first batch is requested before the norm's partials are summed, so
+  // the two memory round trips overlap
+  if (first < n) load(first);
   const double h = sqrt(sum_parts(norm_part, nblk, 0));
   const int j = jdev ? (j_fixed < 0 ? -1 : *jdev) : j_fixed;
   T *d = jdev && j >= 0 ? dst + (int64_t)(j + 1) * dst_ld : dst;
   const double inv = h > 0.0 ? 1.0 / h : 0.0;
-  const uint32_t S = gridDim.x * kFB;
-  for (uint32_t r0 = blockIdx.x * kFB + threadIdx.x; r0 < n; r0 += kRows * S) {
-    T v[kRows];  // all loads first (src and d may be the same vector)
-#pragma unroll
-    for (int e = 0; e < kRows; ++e) v[e] = r0 + e * S < n ? src[r0 + e * S] : T(0);
+  for (uint32_t r0 = first; r0 < n; r0 += kRows * S) {
+    if (r0 != first) load(r0);
 #pragma unroll
     for (int e = 0; e < kRows; ++e)
       if (r0 + e * S < n) d[r0 + e * S] = (T)((double)v[e] * inv);
