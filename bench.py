@@ -129,7 +129,17 @@ def parse():
 class Timed:
     """Windows of exactly K launches of ``launch(i)`` replayed from HIP graphs
     on one stream; ``run`` returns the median window's ms per launch and
-    keeps every window's figure in ``windows_ms``."""
+    keeps every window's figure in ``windows_ms``.  A graph holds as many
+    whole rotations of the replicas as fit in one window (at most
+    ``max_nodes`` launches): each replay leaves a gap of a few microseconds
+    before its first kernel, which one rotation per graph (16 launches of
+    the 128^3 product) spread as 0.37 us over every launch.  Each window is
+    preceded by one untimed replay, so that its first launch is already
+    queued when its start event is recorded.  Warm-up is at least
+    ``warmup`` launches and at least ``min_warm_s`` of GPU work."""
+
+    max_nodes = 1024
+    min_warm_s = 0.025
 
     def __init__(self, torch, launch, n_rep: int, steps: int, warmup: int, windows: int = 5):
         self.torch = torch
@@ -153,19 +163,34 @@ class Timed:
         for i in range(min(self.warmup, 3)):  # eager warm-up, before capture
             self.launch(i % self.n_rep)
         torch.cuda.synchronize()
-        full = self.n_rep
+        # a window of K <= max_nodes launches is one graph of exactly K
+        # launches (cycling through the replicas), else whole rotations
+        if self.steps <= self.max_nodes:
+            full = self.steps
+        else:
+            full = self.n_rep * max(1, self.max_nodes // self.n_rep)
         g_full = self._graph(full, 0)
         rem = self.steps % full
         g_rem = self._graph(rem, 0) if rem else None
+        # warm-up: at least ``warmup`` launches and at least min_warm_s of
+        # GPU work (an idle GPU runs its first launches slower)
         for _ in range(max(1, math.ceil(self.warmup / full))):
             g_full.replay()
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < self.min_warm_s:
+            g_full.replay()
+            torch.cuda.synchronize()
         st = torch.cuda.current_stream()
         self.windows_ms = []
         for _ in range(self.windows):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
+            # one untimed replay ahead of the window keeps the GPU busy while
+            # the host submits the timed replays, so the window does not
+            # start with the host's submission latency
+            g_full.replay()
             e0.record(st)
             for _ in range(self.steps // full):
                 g_full.replay()
@@ -293,8 +318,8 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": H["ms"],
         "timing": f"median of 5 windows of exactly {args.steps} launches each (graph replays "
-                  f"bracketed by HIP events on the launch stream); per-window figures in "
-                  f"variants.*.windows_us",
+                  f"bracketed by HIP events on the launch stream, each window preceded by "
+                  f"one untimed replay); per-window figures in variants.*.windows_us",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
