@@ -427,6 +427,81 @@ __global__ __launch_bounds__(kFB) void k_combine(const TZ *__restrict__ Z, int64
   }
 }
 
+// k_combine for a cycle length K known when the step is recorded (the inner
+// layers): the first rows of every Z_q are requested before the triangle is
+// solved, the triangle and g are read into LDS by all threads at once, and
+// each thread keeps kRows rows of every Z_q in flight.  Same operations in
+// the same order as k_combine.
+template <typename TZ, typename TX, int K>
+__global__ __launch_bounds__(kFB) void k_combine_n(const TZ *__restrict__ Z, int64_t ld, Hess hs,
+                                                    TX *x, int64_t x_ld, const int32_t *xjdev,
+                                                    TX *x2, uint32_t n, int add) {
+  constexpr int kRows = rows_of<TZ>();
+  __shared__ double rs[K][K], gs[K], y[K];
+  const uint32_t S = gridDim.x * kFB, first = blockIdx.x * kFB + threadIdx.x;
+  TZ zv[kRows][K];
+  auto load = [&](uint32_t r0) {
+#pragma unroll
+    for (int e = 0; e < kRows; ++e)
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const uint32_t r = r0 + e * S;
+        zv[e][q] = r < n ? Z[(int64_t)q * ld + r] : TZ(0);
+      }
+  };
+  if (first < n) load(first);
+  for (int t = threadIdx.x; t < K * K; t += kFB) {  // column q, rows i <= q
+    const int q = t / K, i = t % K;
+    if (i <= q) rs[q][i] = hs.H[(int64_t)q * hs.ld + i];
+  }
+  if (threadIdx.x < K) gs[threadIdx.x] = hs.g[threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = K - 1; i >= 0; --i) {
+      double sum = gs[i];
+      for (int q = i + 1; q < K; ++q) sum -= rs[q][i] * y[q];
+      const double d = rs[i][i];
+      y[i] = d != 0.0 ? sum / d : 0.0;
+    }
+  }
+  __syncthreads();
+  double yq[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) yq[q] = y[q];
+  TX *xo = xjdev ? x + (int64_t)(*xjdev) * x_ld : x;
+  for (uint32_t r0 = first; r0 < n; r0 += kRows * S) {
+    if (r0 != first) load(r0);
+#pragma unroll
+    for (int e = 0; e < kRows; ++e) {
+      const uint32_t r = r0 + e * S;
+      if (r >= n) continue;
+      double sum = add ? (double)xo[r] : 0.0;
+#pragma unroll
+      for (int q = 0; q < K; ++q) sum += yq[q] * (double)zv[e][q];
+      const TX t = (TX)sum;
+      xo[r] = t;
+      if (x2) x2[r] = t;
+    }
+  }
+}
+
+// k_combine over k_fixed steps, through k_combine_n when k_fixed <= 8.
+template <typename TZ, typename TX>
+void launch_combine(uint32_t nb, hipStream_t s, const TZ *Z, int64_t ld, int k_fixed, Hess hs,
+                    TX *x, int64_t x_ld, const int32_t *xjdev, TX *x2, uint32_t n, int add) {
+  switch (k_fixed) {
+#define PKS_CB(K)                                                                          \
+  case K:                                                                                  \
+    k_combine_n<TZ, TX, K><<<nb, kFB, 0, s>>>(Z, ld, hs, x, x_ld, xjdev, x2, n, add);      \
+    return;
+    PKS_CB(1) PKS_CB(2) PKS_CB(3) PKS_CB(4) PKS_CB(5) PKS_CB(6) PKS_CB(7) PKS_CB(8)
+#undef PKS_CB
+    default:
+      k_combine<TZ, TX><<<nb, kFB, 0, s>>>(Z, ld, k_fixed, nullptr, hs, x, x_ld, xjdev, x2, n,
+                                           add);
+  }
+}
+
 // dst = (TD) src, with src = base + (*jdev) * ld when jdev is set; leaves
 // the partials of ||dst||^2 (the start of an inner cycle).
 template <typename TS, typename TD>
@@ -651,7 +726,7 @@ struct F3RSolve {
                                            nullptr);
       PKS_LAUNCHED();
     }
-    k_combine<T, T><<<nb, kFB, 0, s>>>(z3(0), n, p.m3, nullptr, h3(), z, 0, nullptr, nullptr, n, 0);
+    launch_combine<T, T>(nb, s, z3(0), n, p.m3, h3(), z, 0, nullptr, nullptr, n, 0);
     PKS_LAUNCHED();
     return PKSELL_OK;
   }
@@ -672,8 +747,7 @@ struct F3RSolve {
                                            nullptr);
       PKS_LAUNCHED();
     }
-    k_combine<T, double><<<nb, kFB, 0, s>>>(z2(0), n, p.m2, nullptr, h2(), w.Z1, n, w.j1, w.zbuf,
-                                            n, 0);
+    launch_combine<T, double>(nb, s, z2(0), n, p.m2, h2(), w.Z1, n, w.j1, w.zbuf, n, 0);
     PKS_LAUNCHED();
     if ((rc = a1.run(w.zbuf, w.wbuf, s))) return rc;
     if ((rc = orthogonalise<double>(w.V1, 0, w.j1, w.wbuf, h1()))) return rc;
